@@ -1,0 +1,167 @@
+/*
+ * gigaqbx.h -- C ABI of the MI355X (gfx950) GIGAQBX library: FMM-accelerated
+ * quadrature by expansion (QBX) for the 3D Laplace single- and double-layer potentials.
+ *
+ * Method: Wala & Kloeckner, "A fast algorithm for quadrature by expansion in three
+ * dimensions" (arXiv:1805.06106).  The library evaluates Algorithm 5 (Stages 1-9) for
+ * targets that are all associated with QBX centers:
+ *
+ *   potential(t) = sum_{n <= p_qbx} sum_{|m| <= n} L_n^m(c) |t - c|^n Y_n^m(t - c)
+ *
+ * where c is the center associated with target t and L(c) approximates the QBX local
+ * coefficients of the layer potential (Section 2.1, QBX coefficient integral, discretized
+ * by the quadrature sum over source nodes with weights w_j):
+ *
+ *   single layer S:  L_n^m(c) = sum_j w_j mu_j  1/(2n+1) |s_j - c|^-(n+1) Y_n^-m(s_j - c)
+ *   double layer D:  same with the factor n_j . grad_{s_j} applied (kernel dG/dn_y,
+ *                    G(x, y) = 1 / (4 pi |x - y|), n_j the source normal)
+ *
+ * accelerated by the GIGAQBX FMM of order p_fmm with target confinement factor t_f.
+ *
+ * Conventions for every entry point:
+ *  - Host arrays are read during the call and copied; the caller keeps ownership.
+ *  - Device arrays (density, potential) are caller-owned HIP device allocations; work is
+ *    enqueued on `hip_stream` (NULL = default stream) in stream order.
+ *  - Points are AoS, xyz interleaved: p[3*i + k].
+ *  - Functions return a gq_status; on error nothing is written to caller outputs and
+ *    gq_last_error() (thread-local) describes the failure.  No exceptions cross the ABI.
+ */
+#ifndef GIGAQBX_H
+#define GIGAQBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GQ_OK = 0,
+  GQ_EINVAL = 1,       /* invalid argument */
+  GQ_ENOMEM = 2,       /* device or host allocation failed */
+  GQ_EDEVICE = 3,      /* HIP runtime error */
+  GQ_EUNSUPPORTED = 4  /* valid but outside what this build supports (e.g. p_fmm > 20) */
+} gq_status;
+
+typedef enum { GQ_KERNEL_S = 0, GQ_KERNEL_D = 1 } gq_kernel;
+typedef enum { GQ_FP64 = 0 } gq_precision;
+
+/* gq_params.flags */
+#define GQ_FLAG_HOST_ONLY (1u << 0) /* plan on the host only: no device memory, no apply */
+#define GQ_FLAG_TIMING (1u << 1)    /* record per-stage HIP events in gq_apply (gq_stats) */
+/* Which interaction lists contribute (testing aid).  0 in bits 8..13 means all. */
+#define GQ_LIST_U (1u << 8)       /* List 1 (direct)            Stage 3 */
+#define GQ_LIST_V (1u << 9)       /* List 2 (M2L, then L2L)     Stages 4, 7, 8 */
+#define GQ_LIST_WCLOSE (1u << 10) /* List 3 close (direct)      Stage 5a */
+#define GQ_LIST_WFAR (1u << 11)   /* List 3 far (M2QBXL)        Stage 5b */
+#define GQ_LIST_XCLOSE (1u << 12) /* List 4 close (direct)      Stage 6a */
+#define GQ_LIST_XFAR (1u << 13)   /* List 4 far (P2L, then L2L) Stages 6b, 7, 8 */
+
+typedef struct {
+  int p_qbx;         /* QBX order, 0 <= p_qbx <= p_fmm, p_qbx <= 10 */
+  int p_fmm;         /* FMM order, p_fmm <= 20 */
+  int nmax;          /* max particles (sources+centers+targets) per box before a split, >= 1 */
+  double tcf;        /* target confinement factor t_f, 0 <= t_f < 2 sqrt(3) - 2 (Theorem 1) */
+  int kernel;        /* gq_kernel */
+  int precision;     /* gq_precision */
+  int n_densities;   /* densities evaluated per gq_apply, >= 1 */
+  unsigned flags;    /* GQ_FLAG_* | GQ_LIST_* */
+} gq_params;
+
+typedef struct gq_plan gq_plan; /* opaque */
+
+/* Statistics of a plan (and of the last timed apply). */
+typedef struct {
+  int64_t n_sources, n_centers, n_targets;
+  int64_t n_boxes, n_levels, n_target_boxes, n_suspended_centers;
+  int64_t list_entries[6];  /* box entries of U, V, Wclose, Wfar, Xclose, Xfar */
+  /* interaction counts: U, Wclose, Xclose: (source, center) pairs; V: (box, box) pairs;
+     Wfar: (box, center) pairs; Xfar: (source, box) pairs */
+  int64_t pairs[6];
+  int64_t m2l_classes;      /* distinct M2L offsets in use (at most 1206) */
+  double plan_seconds;      /* host tree + lists + matrices + upload */
+  /* stage times of the last gq_apply with GQ_FLAG_TIMING (ms, summed over densities):
+     0 strength, 1 P2M, 2 M2M, 3 M2L, 4 P2L, 5 L2L, 6 P2QBXL, 7 M2QBXL, 8 L2QBXL,
+     9 QBXL2P, 10 fill, 11 total */
+  double stage_ms[12];
+} gq_stats_t;
+
+/*
+ * Build a plan (Algorithm 5 Stage 1 plus interaction lists, translation operators and
+ * device-resident geometry).
+ *   n_src, src_xyz[3*n_src], src_w[n_src]   source quadrature nodes and final weights
+ *                                           (area element included)
+ *   src_normal[3*n_src]                     unit normals; required for GQ_KERNEL_D, may be
+ *                                           NULL for GQ_KERNEL_S
+ *   n_ctr, ctr_xyz[3*n_ctr], ctr_radius[n_ctr]  QBX centers c = x +- r n (Section 2.2)
+ *   n_tgt, tgt_xyz[3*n_tgt], tgt_center[n_tgt]  targets and their associated center index
+ * Errors: GQ_EINVAL for negative counts, non-finite input, p_qbx > p_fmm, radius <= 0,
+ * center index out of range, missing or non-unit normals (|1-|n|| > 1e-6) for D, t_f out
+ * of range; GQ_EUNSUPPORTED for orders beyond the compiled limits.  *out is set only on
+ * success; release with gq_plan_destroy.
+ */
+gq_status gq_plan_create(const gq_params* params, int64_t n_src, const double* src_xyz,
+                         const double* src_w, const double* src_normal, int64_t n_ctr,
+                         const double* ctr_xyz, const double* ctr_radius, int64_t n_tgt,
+                         const double* tgt_xyz, const int64_t* tgt_center, void* hip_stream,
+                         gq_plan** out);
+
+/*
+ * Evaluate the layer potential (Algorithm 5 Stages 2-9) for params.n_densities densities.
+ *   density   device, [n_densities][n_src] (row d is density d at the input source order)
+ *   potential device, [n_densities][n_tgt], OVERWRITTEN (input target order)
+ * The plan owns its workspace; concurrent applies of one plan must be serialized by the
+ * caller (they share it).  Non-finite densities propagate to the output.
+ */
+gq_status gq_apply(gq_plan* plan, const double* density, double* potential, void* hip_stream);
+
+/* Copy plan statistics. */
+gq_status gq_stats(const gq_plan* plan, gq_stats_t* out);
+
+/* Release a plan (NULL is ignored).  Synchronizes with outstanding device work. */
+void gq_plan_destroy(gq_plan* plan);
+
+/* Thread-local description of the last error ("" if none). */
+const char* gq_last_error(void);
+
+/*
+ * Host-side export of the tree (for inspection and testing; works with
+ * GQ_FLAG_HOST_ONLY).  Boxes are numbered breadth-first with children in octant order
+ * (bit 0: x upper half, bit 1: y, bit 2: z).  Any pointer may be NULL.
+ *   box_center[3*n_boxes], box_h[n_boxes] (half-width), level[n_boxes], parent[n_boxes]
+ *   (-1 for the root), ctr_owner[n_ctr] owning box of each input center.
+ */
+gq_status gq_tree_export(const gq_plan* plan, double* box_center, double* box_h,
+                         int32_t* level, int32_t* parent, int64_t* ctr_owner);
+
+/*
+ * Host-side export of one interaction list as CSR over boxes.
+ *   list: 0 U (List 1), 1 V (List 2), 2 W-close, 3 W-far, 4 X-close, 5 X-far
+ *   ptr[n_boxes+1] (may be NULL), items[*n_items] (may be NULL); *n_items receives the
+ *   entry count.  Lists exist for target boxes (U, W-close, W-far, X-close) and for target
+ *   and target-ancestor boxes (V, X-far; X-close also for ancestors).
+ */
+gq_status gq_list_export(const gq_plan* plan, int list, int64_t* ptr, int32_t* items,
+                         int64_t* n_items);
+
+/*
+ * Download the QBX local coefficients of the last gq_apply for density 0, after Stage 8:
+ * host_out[n_ctr * (p_qbx+1)^2], input center order, in the library's internal real-packed
+ * solid-harmonic form l_n^m = sum_j q_j conj(I_n^m)(s_j - c) (see the DESIGN notes for the
+ * map to the paper's L_n^m).  Synchronizes the plan's last stream.
+ */
+gq_status gq_qbx_locals(gq_plan* plan, double* host_out);
+
+/*
+ * Host computation of one dense translation matrix (column-major, (p+1)^2 square):
+ *   kind 0: M2M child octant a -> parent;  kind 1: L2L parent -> child octant a;
+ *   kind 2: M2L for integer offset (a, b, c) = (x_target - x_source) / (box width).
+ * Scaled real-packed form; for testing.
+ */
+gq_status gq_translation_matrix(int kind, int p, int a, int b, int c, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GIGAQBX_H */

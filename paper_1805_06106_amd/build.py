@@ -1,0 +1,52 @@
+"""Build libgigaqbx.so for gfx950 in-tree (host planner with g++, kernels with hipcc)."""
+
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libgigaqbx.so")
+ARCH = os.environ.get("GQ_OFFLOAD_ARCH", "gfx950")
+
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall"]
+HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout)
+        raise RuntimeError("compile failed: " + " ".join(cmd[:3]))
+    return r.stdout
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = []
+    for f in ("planner.cpp", "translations.cpp"):
+        jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, f),
+                     "-o", os.path.join(BUILD, f + ".o")])
+    for f in ("kernels.hip", "executor.hip"):
+        jobs.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, f),
+                     "-o", os.path.join(BUILD, f + ".o")])
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        for out in ex.map(_run, jobs):
+            if verbose and out:
+                print(out)
+    objs = [os.path.join(BUILD, f + ".o") for f in
+            ("planner.cpp", "translations.cpp", "kernels.hip", "executor.hip")]
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,688 @@
+// Plan construction and the Algorithm 5 evaluation pipeline behind the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gigaqbx.h"
+#include "kernels.hpp"
+#include "planner.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+gq_status fail(gq_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define GQ_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? GQ_ENOMEM : GQ_EDEVICE,                      \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+// A batch of dense translations: tiles of up to kTileCols pairs of one matrix class.
+struct TileSet {
+  std::vector<int> cls, beg, cnt, src, dst;
+  int ntile() const { return (int)cls.size(); }
+};
+
+// pairs (cls, src, dst) -> tiles grouped by class
+void make_tiles(std::vector<std::array<int, 3>> pairs, TileSet& ts) {
+  std::stable_sort(pairs.begin(), pairs.end(),
+                   [](const std::array<int, 3>& a, const std::array<int, 3>& b) { return a[0] < b[0]; });
+  size_t i = 0;
+  while (i < pairs.size()) {
+    size_t j = i;
+    while (j < pairs.size() && pairs[j][0] == pairs[i][0] && j - i < (size_t)gq::kTileCols) ++j;
+    ts.cls.push_back(pairs[i][0]);
+    ts.beg.push_back((int)ts.src.size());
+    ts.cnt.push_back((int)(j - i));
+    for (size_t k = i; k < j; ++k) {
+      ts.src.push_back(pairs[k][1]);
+      ts.dst.push_back(pairs[k][2]);
+    }
+    i = j;
+  }
+}
+
+template <class T>
+struct DevArr {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct gq_plan {
+  gq_params prm{};
+  int np = 0, nq = 0;
+  int64_t n_src = 0, n_ctr = 0, n_tgt = 0;
+  gq::Tree tree;
+  gq::Lists lists;
+  gq_stats_t stats{};
+  hipStream_t last_stream = nullptr;
+
+  // host work description
+  std::vector<int> p2m_boxes;
+  std::vector<TileSet> m2m_levels;  // index: child level
+  TileSet m2l;
+  std::vector<TileSet> l2l_levels;  // index: child level
+  std::vector<int> p2l_box;
+  std::vector<int64_t> p2l_rptr, p2l_rbeg, p2l_rcnt;
+  std::vector<int64_t> near_ptr, near_beg, near_cnt;  // box-indexed CSR of source ranges
+  std::vector<int> k3_box, k3_c0, k3_nc;
+  std::vector<int64_t> wf_ptr;
+  std::vector<int> wf_box;
+  std::vector<int> k5_box, k5_c0, k5_nc;
+  std::vector<int> k8_box, k8_c0, k8_nc;
+
+  // device memory
+  std::vector<void*> allocs;
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *snx = nullptr, *sny = nullptr,
+         *snz = nullptr, *sw = nullptr;
+  int64_t* src_order = nullptr;
+  double *cx = nullptr, *cy = nullptr, *cz = nullptr;
+  double *tx = nullptr, *ty = nullptr, *tz = nullptr;
+  int64_t *tgt_ctr = nullptr, *tgt_out = nullptr;
+  double *bctr = nullptr, *bh = nullptr;
+  int64_t *src_start = nullptr, *src_count = nullptr;
+  int* d_p2m_boxes = nullptr;
+  std::vector<std::array<int*, 5>> d_m2m, d_l2l;
+  std::array<int*, 5> d_m2l{};
+  int *d_p2l_box = nullptr;
+  int64_t *d_p2l_rptr = nullptr, *d_p2l_rbeg = nullptr, *d_p2l_rcnt = nullptr;
+  int64_t *d_near_ptr = nullptr, *d_near_beg = nullptr, *d_near_cnt = nullptr;
+  int *d_k3_box = nullptr, *d_k3_c0 = nullptr, *d_k3_nc = nullptr;
+  int64_t* d_wf_ptr = nullptr;
+  int* d_wf_box = nullptr;
+  int *d_k5_box = nullptr, *d_k5_c0 = nullptr, *d_k5_nc = nullptr;
+  int *d_k8_box = nullptr, *d_k8_c0 = nullptr, *d_k8_nc = nullptr;
+  double *T_m2m = nullptr, *T_l2l = nullptr, *T_m2l = nullptr;
+  double *q = nullptr, *M = nullptr, *L = nullptr, *Lq = nullptr;
+  hipEvent_t ev[13] = {};
+  bool have_events = false;
+
+  ~gq_plan() {
+    if (have_events)
+      for (auto& e : ev) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+template <class T>
+gq_status upload(gq_plan* P, const std::vector<T>& h, T** d, hipStream_t s) {
+  *d = nullptr;
+  if (h.empty()) return GQ_OK;
+  GQ_HIP(hipMalloc((void**)d, h.size() * sizeof(T)));
+  P->allocs.push_back(*d);
+  GQ_HIP(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return GQ_OK;
+}
+
+template <class T>
+gq_status alloc(gq_plan* P, size_t n, T** d) {
+  *d = nullptr;
+  if (n == 0) return GQ_OK;
+  GQ_HIP(hipMalloc((void**)d, n * sizeof(T)));
+  P->allocs.push_back(*d);
+  return GQ_OK;
+}
+
+#define GQ_TRY(x)                  \
+  do {                             \
+    gq_status st_ = (x);           \
+    if (st_ != GQ_OK) return st_;  \
+  } while (0)
+
+bool finite3(const double* p, int64_t n) {
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+void merge_ranges(std::vector<std::pair<int64_t, int64_t>>& r) {
+  std::sort(r.begin(), r.end());
+  std::vector<std::pair<int64_t, int64_t>> out;
+  for (auto& x : r) {
+    if (x.second == 0) continue;
+    if (!out.empty() && out.back().first + out.back().second == x.first)
+      out.back().second += x.second;
+    else
+      out.push_back(x);
+  }
+  r.swap(out);
+}
+
+void center_items(const gq::Tree& T, int b, int chunk, std::vector<int>& box,
+                  std::vector<int>& c0, std::vector<int>& nc) {
+  int64_t s = T.ctr_start[b], n = T.ctr_count[b];
+  for (int64_t o = 0; o < n; o += chunk) {
+    box.push_back(b);
+    c0.push_back((int)(s + o));
+    nc.push_back((int)std::min<int64_t>(chunk, n - o));
+  }
+}
+
+gq_status build_work(gq_plan* P) {
+  const gq::Tree& T = P->tree;
+  const gq::Lists& Ls = P->lists;
+  const int nb = T.nboxes;
+  unsigned mask = (P->prm.flags >> 8) & 63u;
+  if (mask == 0) mask = 63u;
+  auto on = [&](unsigned bit) { return (mask & (bit >> 8)) != 0; };
+
+  // Stage 2a
+  for (int b = 0; b < nb; ++b)
+    if (T.is_leaf(b) && T.src_count[b] > 0) P->p2m_boxes.push_back(b);
+  // Stage 2b, per child level (deepest first when launched)
+  P->m2m_levels.assign(T.nlevels, TileSet());
+  {
+    std::vector<std::vector<std::array<int, 3>>> per(T.nlevels);
+    for (int b = 0; b < nb; ++b) {
+      int pb = T.parent[b];
+      if (pb < 0 || T.sub_src[b] == 0) continue;
+      int oct = -1;
+      for (int o = 0; o < 8; ++o)
+        if (T.child[pb][o] == b) oct = o;
+      per[T.level[b]].push_back({oct, b, pb});
+    }
+    for (int l = 0; l < T.nlevels; ++l) make_tiles(per[l], P->m2m_levels[l]);
+  }
+  // Stage 4
+  std::map<int, int> cls_index;
+  std::vector<int> cls_keys;
+  if (on(GQ_LIST_V)) {
+    std::vector<std::array<int, 3>> pairs;
+    for (int b = 0; b < nb; ++b) {
+      const auto& V = Ls.lst[gq::L_V];
+      for (int64_t k = V.ptr[b]; k < V.ptr[b + 1]; ++k) {
+        int d = V.items[k];
+        int o[3];
+        for (int a = 0; a < 3; ++a) {
+          double off = (T.center[3 * b + a] - T.center[3 * d + a]) / (2.0 * T.h[b]);
+          o[a] = (int)std::lround(off);
+        }
+        int key = (o[0] + 5) * 121 + (o[1] + 5) * 11 + (o[2] + 5);
+        auto it = cls_index.find(key);
+        int ci;
+        if (it == cls_index.end()) {
+          ci = (int)cls_keys.size();
+          cls_index[key] = ci;
+          cls_keys.push_back(key);
+        } else {
+          ci = it->second;
+        }
+        pairs.push_back({ci, d, b});
+      }
+    }
+    make_tiles(pairs, P->m2l);
+  }
+  // Stage 6b
+  if (on(GQ_LIST_XFAR)) {
+    const auto& X = Ls.lst[gq::L_XFAR];
+    P->p2l_rptr.push_back(0);
+    for (int b = 0; b < nb; ++b) {
+      if (X.size(b) == 0) continue;
+      std::vector<std::pair<int64_t, int64_t>> r;
+      for (int64_t k = X.ptr[b]; k < X.ptr[b + 1]; ++k) {
+        int d = X.items[k];
+        r.push_back({T.src_start[d], T.src_count[d]});
+      }
+      merge_ranges(r);
+      P->p2l_box.push_back(b);
+      for (auto& x : r) {
+        P->p2l_rbeg.push_back(x.first);
+        P->p2l_rcnt.push_back(x.second);
+      }
+      P->p2l_rptr.push_back((int64_t)P->p2l_rbeg.size());
+    }
+  }
+  // Stage 7, per child level
+  P->l2l_levels.assign(T.nlevels, TileSet());
+  {
+    std::vector<std::vector<std::array<int, 3>>> per(T.nlevels);
+    for (int b = 0; b < nb; ++b) {
+      int pb = T.parent[b];
+      if (pb < 0 || !Ls.is_owner[b]) continue;
+      int oct = -1;
+      for (int o = 0; o < 8; ++o)
+        if (T.child[pb][o] == b) oct = o;
+      per[T.level[b]].push_back({oct, pb, b});
+    }
+    for (int l = 0; l < T.nlevels; ++l) make_tiles(per[l], P->l2l_levels[l]);
+  }
+  // Stages 3, 5a, 6a (near sources), 5b (W-far), 8
+  P->near_ptr.assign(nb + 1, 0);
+  P->wf_ptr.assign(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) {
+    if (Ls.is_target[b]) {
+      std::vector<std::pair<int64_t, int64_t>> r;
+      const int ids[3] = {gq::L_U, gq::L_WCLOSE, gq::L_XCLOSE};
+      const unsigned bits[3] = {GQ_LIST_U, GQ_LIST_WCLOSE, GQ_LIST_XCLOSE};
+      for (int l = 0; l < 3; ++l) {
+        if (!on(bits[l])) continue;
+        const auto& Lst = Ls.lst[ids[l]];
+        for (int64_t k = Lst.ptr[b]; k < Lst.ptr[b + 1]; ++k) {
+          int d = Lst.items[k];
+          r.push_back({T.src_start[d], T.src_count[d]});
+        }
+      }
+      merge_ranges(r);
+      for (auto& x : r) {
+        P->near_beg.push_back(x.first);
+        P->near_cnt.push_back(x.second);
+      }
+      if (!r.empty()) center_items(T, b, 256, P->k3_box, P->k3_c0, P->k3_nc);
+      if (on(GQ_LIST_WFAR)) {
+        const auto& W = Ls.lst[gq::L_WFAR];
+        for (int64_t k = W.ptr[b]; k < W.ptr[b + 1]; ++k) P->wf_box.push_back(W.items[k]);
+        if (W.size(b) > 0) center_items(T, b, 64, P->k5_box, P->k5_c0, P->k5_nc);
+      }
+      center_items(T, b, 64, P->k8_box, P->k8_c0, P->k8_nc);
+    }
+    P->near_ptr[b + 1] = (int64_t)P->near_beg.size();
+    P->wf_ptr[b + 1] = (int64_t)P->wf_box.size();
+  }
+  P->stats.m2l_classes = (int64_t)cls_keys.size();
+  // statistics
+  gq_stats_t& S = P->stats;
+  S.n_boxes = nb;
+  S.n_levels = T.nlevels;
+  for (int b = 0; b < nb; ++b) {
+    if (Ls.is_target[b]) {
+      S.n_target_boxes++;
+      if (!T.is_leaf(b)) S.n_suspended_centers += T.ctr_count[b];
+    }
+    for (int l = 0; l < gq::L_NLISTS; ++l) {
+      const auto& Lst = Ls.lst[l];
+      int64_t ne = Lst.size(b);
+      bool used = (l == gq::L_V || l == gq::L_XFAR) ? Ls.is_owner[b] : Ls.is_target[b];
+      if (!used) continue;
+      S.list_entries[l] += ne;
+      int64_t nsrc = 0;
+      for (int64_t k = Lst.ptr[b]; k < Lst.ptr[b + 1]; ++k) nsrc += T.src_count[Lst.items[k]];
+      if (l == gq::L_U || l == gq::L_WCLOSE || l == gq::L_XCLOSE) S.pairs[l] += nsrc * T.ctr_count[b];
+      if (l == gq::L_V) S.pairs[l] += ne;
+      if (l == gq::L_WFAR) S.pairs[l] += ne * T.ctr_count[b];
+      if (l == gq::L_XFAR) S.pairs[l] += nsrc;
+    }
+  }
+  // translation matrices
+  const int p = P->prm.p_fmm, np = P->np;
+  std::vector<double> Tm((size_t)8 * np * np), Tl((size_t)8 * np * np);
+  for (int o = 0; o < 8; ++o) {
+    gq::m2m_matrix(p, o, Tm.data() + (size_t)o * np * np);
+    gq::l2l_matrix(p, o, Tl.data() + (size_t)o * np * np);
+  }
+  std::vector<double> Tv((size_t)cls_keys.size() * np * np);
+  for (size_t c = 0; c < cls_keys.size(); ++c) {
+    int key = cls_keys[c];
+    gq::m2l_matrix(p, key / 121 - 5, (key / 11) % 11 - 5, key % 11 - 5, Tv.data() + c * np * np);
+  }
+  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return GQ_OK;
+
+  hipStream_t s = P->last_stream;
+  GQ_TRY(upload(P, Tm, &P->T_m2m, s));
+  GQ_TRY(upload(P, Tl, &P->T_l2l, s));
+  GQ_TRY(upload(P, Tv, &P->T_m2l, s));
+  GQ_TRY(upload(P, P->p2m_boxes, &P->d_p2m_boxes, s));
+  auto up_tiles = [&](const TileSet& t, std::array<int*, 5>& d) -> gq_status {
+    GQ_TRY(upload(P, t.cls, &d[0], s));
+    GQ_TRY(upload(P, t.beg, &d[1], s));
+    GQ_TRY(upload(P, t.cnt, &d[2], s));
+    GQ_TRY(upload(P, t.src, &d[3], s));
+    GQ_TRY(upload(P, t.dst, &d[4], s));
+    return GQ_OK;
+  };
+  P->d_m2m.assign(T.nlevels, {});
+  P->d_l2l.assign(T.nlevels, {});
+  for (int l = 0; l < T.nlevels; ++l) {
+    GQ_TRY(up_tiles(P->m2m_levels[l], P->d_m2m[l]));
+    GQ_TRY(up_tiles(P->l2l_levels[l], P->d_l2l[l]));
+  }
+  GQ_TRY(up_tiles(P->m2l, P->d_m2l));
+  GQ_TRY(upload(P, P->p2l_box, &P->d_p2l_box, s));
+  GQ_TRY(upload(P, P->p2l_rptr, &P->d_p2l_rptr, s));
+  GQ_TRY(upload(P, P->p2l_rbeg, &P->d_p2l_rbeg, s));
+  GQ_TRY(upload(P, P->p2l_rcnt, &P->d_p2l_rcnt, s));
+  GQ_TRY(upload(P, P->near_ptr, &P->d_near_ptr, s));
+  GQ_TRY(upload(P, P->near_beg, &P->d_near_beg, s));
+  GQ_TRY(upload(P, P->near_cnt, &P->d_near_cnt, s));
+  GQ_TRY(upload(P, P->k3_box, &P->d_k3_box, s));
+  GQ_TRY(upload(P, P->k3_c0, &P->d_k3_c0, s));
+  GQ_TRY(upload(P, P->k3_nc, &P->d_k3_nc, s));
+  GQ_TRY(upload(P, P->wf_ptr, &P->d_wf_ptr, s));
+  GQ_TRY(upload(P, P->wf_box, &P->d_wf_box, s));
+  GQ_TRY(upload(P, P->k5_box, &P->d_k5_box, s));
+  GQ_TRY(upload(P, P->k5_c0, &P->d_k5_c0, s));
+  GQ_TRY(upload(P, P->k5_nc, &P->d_k5_nc, s));
+  GQ_TRY(upload(P, P->k8_box, &P->d_k8_box, s));
+  GQ_TRY(upload(P, P->k8_c0, &P->d_k8_c0, s));
+  GQ_TRY(upload(P, P->k8_nc, &P->d_k8_nc, s));
+  return GQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gq_last_error(void) { return g_err.c_str(); }
+
+gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_xyz,
+                         const double* src_w, const double* src_normal, int64_t n_ctr,
+                         const double* ctr_xyz, const double* ctr_radius, int64_t n_tgt,
+                         const double* tgt_xyz, const int64_t* tgt_center, void* hip_stream,
+                         gq_plan** out) {
+  g_err.clear();
+  auto t0 = std::chrono::steady_clock::now();
+  if (!prm || !out) return fail(GQ_EINVAL, "params and out must not be NULL");
+  if (n_src < 0 || n_ctr < 0 || n_tgt < 0) return fail(GQ_EINVAL, "negative count");
+  if (n_src == 0 || n_ctr == 0) return fail(GQ_EINVAL, "need at least one source and one center");
+  if ((n_src && (!src_xyz || !src_w)) || (n_ctr && (!ctr_xyz || !ctr_radius)) ||
+      (n_tgt && (!tgt_xyz || !tgt_center)))
+    return fail(GQ_EINVAL, "NULL input array");
+  if (prm->p_qbx < 0 || prm->p_fmm < 0) return fail(GQ_EINVAL, "negative order");
+  if (prm->p_qbx > prm->p_fmm) return fail(GQ_EINVAL, "p_qbx must not exceed p_fmm");
+  if (prm->p_fmm > gq::kPmax || prm->p_qbx > gq::kQmax)
+    return fail(GQ_EUNSUPPORTED, "order beyond this build's limits (p_fmm <= 20, p_qbx <= 10)");
+  if (prm->nmax < 1) return fail(GQ_EINVAL, "nmax must be >= 1");
+  if (!(prm->tcf >= 0.0 && prm->tcf < 2.0 * std::sqrt(3.0) - 2.0))
+    return fail(GQ_EINVAL, "target confinement factor outside [0, 2 sqrt(3) - 2)");
+  if (prm->kernel != GQ_KERNEL_S && prm->kernel != GQ_KERNEL_D)
+    return fail(GQ_EINVAL, "unknown kernel");
+  if (prm->precision != GQ_FP64) return fail(GQ_EUNSUPPORTED, "only GQ_FP64 is available");
+  if (prm->n_densities < 1) return fail(GQ_EINVAL, "n_densities must be >= 1");
+  if (prm->kernel == GQ_KERNEL_D && !src_normal) return fail(GQ_EINVAL, "double layer needs normals");
+  if (!finite3(src_xyz, n_src) || !finite3(ctr_xyz, n_ctr) || !finite3(tgt_xyz, n_tgt))
+    return fail(GQ_EINVAL, "non-finite coordinates");
+  for (int64_t i = 0; i < n_src; ++i)
+    if (!std::isfinite(src_w[i])) return fail(GQ_EINVAL, "non-finite weight");
+  for (int64_t i = 0; i < n_ctr; ++i)
+    if (!(ctr_radius[i] > 0.0) || !std::isfinite(ctr_radius[i]))
+      return fail(GQ_EINVAL, "center radius must be positive and finite");
+  for (int64_t i = 0; i < n_tgt; ++i)
+    if (tgt_center[i] < 0 || tgt_center[i] >= n_ctr) return fail(GQ_EINVAL, "tgt_center out of range");
+  if (src_normal) {
+    if (!finite3(src_normal, n_src)) return fail(GQ_EINVAL, "non-finite normal");
+    for (int64_t i = 0; i < n_src; ++i) {
+      const double* nn = src_normal + 3 * i;
+      double l = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+      if (std::fabs(l - 1.0) > 1e-6) return fail(GQ_EINVAL, "normals must have unit length");
+    }
+  }
+  gq_plan* P = new (std::nothrow) gq_plan();
+  if (!P) return fail(GQ_ENOMEM, "host allocation failed");
+  P->prm = *prm;
+  P->np = gq::ncoef(prm->p_fmm);
+  P->nq = gq::ncoef(prm->p_qbx);
+  P->n_src = n_src;
+  P->n_ctr = n_ctr;
+  P->n_tgt = n_tgt;
+  P->last_stream = (hipStream_t)hip_stream;
+  gq::TreeParams tp;
+  tp.nmax = prm->nmax;
+  tp.tcf = prm->tcf;
+  std::string msg = gq::build_tree(tp, n_src, src_xyz, n_ctr, ctr_xyz, ctr_radius, n_tgt,
+                                   tgt_xyz, P->tree);
+  if (!msg.empty()) {
+    delete P;
+    return fail(GQ_EINVAL, msg);
+  }
+  gq::build_lists(P->tree, prm->tcf, P->lists);
+  P->stats.n_sources = n_src;
+  P->stats.n_centers = n_ctr;
+  P->stats.n_targets = n_tgt;
+  gq_status st = build_work(P);
+  if (st != GQ_OK) {
+    delete P;
+    return st;
+  }
+  if (!(prm->flags & GQ_FLAG_HOST_ONLY)) {
+    const gq::Tree& T = P->tree;
+    hipStream_t s = P->last_stream;
+    // particles in tree order
+    std::vector<double> a(n_src), b(n_src), c(n_src), na(n_src, 0.0), nb(n_src, 0.0),
+        nc(n_src, 0.0), w(n_src);
+    for (int64_t i = 0; i < n_src; ++i) {
+      int64_t j = T.src_order[i];
+      a[i] = src_xyz[3 * j];
+      b[i] = src_xyz[3 * j + 1];
+      c[i] = src_xyz[3 * j + 2];
+      w[i] = src_w[j];
+      if (src_normal) {
+        na[i] = src_normal[3 * j];
+        nb[i] = src_normal[3 * j + 1];
+        nc[i] = src_normal[3 * j + 2];
+      }
+    }
+    auto go = [&]() -> gq_status {
+      GQ_TRY(upload(P, a, &P->sx, s));
+      GQ_TRY(upload(P, b, &P->sy, s));
+      GQ_TRY(upload(P, c, &P->sz, s));
+      GQ_TRY(upload(P, na, &P->snx, s));
+      GQ_TRY(upload(P, nb, &P->sny, s));
+      GQ_TRY(upload(P, nc, &P->snz, s));
+      GQ_TRY(upload(P, w, &P->sw, s));
+      GQ_TRY(upload(P, T.src_order, &P->src_order, s));
+      std::vector<double> x(n_ctr), y(n_ctr), z(n_ctr);
+      std::vector<int64_t> pos(n_ctr);
+      for (int64_t i = 0; i < n_ctr; ++i) {
+        int64_t j = T.ctr_order[i];
+        pos[j] = i;
+        x[i] = ctr_xyz[3 * j];
+        y[i] = ctr_xyz[3 * j + 1];
+        z[i] = ctr_xyz[3 * j + 2];
+      }
+      GQ_TRY(upload(P, x, &P->cx, s));
+      GQ_TRY(upload(P, y, &P->cy, s));
+      GQ_TRY(upload(P, z, &P->cz, s));
+      // targets sorted by the tree position of their center
+      std::vector<int64_t> tord(n_tgt);
+      for (int64_t i = 0; i < n_tgt; ++i) tord[i] = i;
+      std::stable_sort(tord.begin(), tord.end(), [&](int64_t u, int64_t v) {
+        return pos[tgt_center[u]] < pos[tgt_center[v]];
+      });
+      std::vector<double> tx(n_tgt), ty(n_tgt), tz(n_tgt);
+      std::vector<int64_t> tc(n_tgt);
+      for (int64_t i = 0; i < n_tgt; ++i) {
+        int64_t j = tord[i];
+        tx[i] = tgt_xyz[3 * j];
+        ty[i] = tgt_xyz[3 * j + 1];
+        tz[i] = tgt_xyz[3 * j + 2];
+        tc[i] = pos[tgt_center[j]];
+      }
+      GQ_TRY(upload(P, tx, &P->tx, s));
+      GQ_TRY(upload(P, ty, &P->ty, s));
+      GQ_TRY(upload(P, tz, &P->tz, s));
+      GQ_TRY(upload(P, tc, &P->tgt_ctr, s));
+      GQ_TRY(upload(P, tord, &P->tgt_out, s));
+      GQ_TRY(upload(P, T.center, &P->bctr, s));
+      GQ_TRY(upload(P, T.h, &P->bh, s));
+      GQ_TRY(upload(P, T.src_start, &P->src_start, s));
+      GQ_TRY(upload(P, T.src_count, &P->src_count, s));
+      GQ_TRY(alloc(P, (size_t)n_src, &P->q));
+      GQ_TRY(alloc(P, (size_t)T.nboxes * P->np, &P->M));
+      GQ_TRY(alloc(P, (size_t)T.nboxes * P->np, &P->L));
+      GQ_TRY(alloc(P, (size_t)n_ctr * P->nq, &P->Lq));
+      GQ_HIP(hipStreamSynchronize(s));
+      return GQ_OK;
+    };
+    st = go();
+    if (st != GQ_OK) {
+      delete P;
+      return st;
+    }
+  }
+  P->stats.plan_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = P;
+  return GQ_OK;
+}
+
+gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* hip_stream) {
+  g_err.clear();
+  if (!P) return fail(GQ_EINVAL, "NULL plan");
+  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
+  if (!density || !potential) return fail(GQ_EINVAL, "NULL device buffer");
+  hipStream_t s = (hipStream_t)hip_stream;
+  P->last_stream = s;
+  const gq::Tree& T = P->tree;
+  const int p = P->prm.p_fmm, qo = P->prm.p_qbx, np = P->np;
+  const int kern = P->prm.kernel;
+  const bool timing = (P->prm.flags & GQ_FLAG_TIMING) != 0;
+  if (timing && !P->have_events) {
+    for (auto& e : P->ev) GQ_HIP(hipEventCreate(&e));
+    P->have_events = true;
+  }
+  double stage_ms[12] = {0};
+  gq::SrcSoA src{P->sx, P->sy, P->sz, P->snx, P->sny, P->snz};
+  auto mark = [&](int i) -> gq_status {
+    if (timing) GQ_HIP(hipEventRecord(P->ev[i], s));
+    return GQ_OK;
+  };
+  for (int d = 0; d < P->prm.n_densities; ++d) {
+    GQ_TRY(mark(0));
+    gq::launch_strength(s, P->n_src, P->src_order, P->sw, density + (int64_t)d * P->n_src, P->q);
+    GQ_TRY(mark(1));
+    gq::launch_fill(s, P->M, (int64_t)T.nboxes * np, 0.0);
+    gq::launch_fill(s, P->L, (int64_t)T.nboxes * np, 0.0);
+    gq::launch_fill(s, P->Lq, (int64_t)P->n_ctr * P->nq, 0.0);
+    GQ_TRY(mark(2));
+    gq::launch_p2m(s, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->src_start,
+                   P->src_count, P->bctr, P->bh, src, P->q, P->M);
+    GQ_TRY(mark(3));
+    for (int l = T.nlevels - 1; l >= 1; --l) {
+      const auto& t = P->m2m_levels[l];
+      const auto& dd = P->d_m2m[l];
+      gq::launch_translate(s, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->T_m2m, P->M, P->M);
+    }
+    GQ_TRY(mark(4));
+    gq::launch_translate(s, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
+                         P->d_m2l[3], P->d_m2l[4], P->T_m2l, P->M, P->L);
+    GQ_TRY(mark(5));
+    gq::launch_p2l(s, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_rptr,
+                   P->d_p2l_rbeg, P->d_p2l_rcnt, P->bctr, P->bh, src, P->q, P->L);
+    GQ_TRY(mark(6));
+    for (int l = 1; l < T.nlevels; ++l) {
+      const auto& t = P->l2l_levels[l];
+      const auto& dd = P->d_l2l[l];
+      gq::launch_translate(s, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->T_l2l, P->L, P->L);
+    }
+    GQ_TRY(mark(7));
+    gq::launch_p2qbxl(s, kern, qo, (int)P->k3_box.size(), P->d_k3_box, P->d_k3_c0, P->d_k3_nc,
+                      P->d_near_ptr, P->d_near_beg, P->d_near_cnt, src, P->q, P->cx, P->cy,
+                      P->cz, P->Lq, P->n_ctr);
+    GQ_TRY(mark(8));
+    gq::launch_m2qbxl(s, p, qo, (int)P->k5_box.size(), P->d_k5_box, P->d_k5_c0, P->d_k5_nc,
+                      P->d_wf_ptr, P->d_wf_box, P->bctr, P->bh, P->M, P->cx, P->cy, P->cz,
+                      P->Lq, P->n_ctr);
+    GQ_TRY(mark(9));
+    gq::launch_l2qbxl(s, p, qo, (int)P->k8_box.size(), P->d_k8_box, P->d_k8_c0, P->d_k8_nc,
+                      P->bctr, P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
+    GQ_TRY(mark(10));
+    gq::launch_qbxl2p(s, qo, P->n_tgt, P->tgt_ctr, P->tx, P->ty, P->tz, P->cx, P->cy, P->cz,
+                      P->Lq, P->n_ctr, P->tgt_out, potential + (int64_t)d * P->n_tgt);
+    GQ_TRY(mark(11));
+    GQ_HIP(hipGetLastError());
+    if (timing) {
+      GQ_HIP(hipEventSynchronize(P->ev[11]));
+      // map event intervals to the stage slots of gq_stats_t
+      const int slot[11] = {0, 10, 1, 2, 3, 4, 5, 6, 7, 8, 9};
+      for (int i = 0; i < 11; ++i) {
+        float ms = 0.f;
+        GQ_HIP(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
+        stage_ms[slot[i]] += ms;
+      }
+      float tot = 0.f;
+      GQ_HIP(hipEventElapsedTime(&tot, P->ev[0], P->ev[11]));
+      stage_ms[11] += tot;
+    }
+  }
+  if (timing)
+    for (int i = 0; i < 12; ++i) P->stats.stage_ms[i] = stage_ms[i];
+  return GQ_OK;
+}
+
+gq_status gq_stats(const gq_plan* P, gq_stats_t* out) {
+  if (!P || !out) return fail(GQ_EINVAL, "NULL argument");
+  *out = P->stats;
+  return GQ_OK;
+}
+
+void gq_plan_destroy(gq_plan* P) {
+  if (!P) return;
+  if (!(P->prm.flags & GQ_FLAG_HOST_ONLY)) (void)hipDeviceSynchronize();
+  delete P;
+}
+
+gq_status gq_tree_export(const gq_plan* P, double* box_center, double* box_h, int32_t* level,
+                         int32_t* parent, int64_t* ctr_owner) {
+  if (!P) return fail(GQ_EINVAL, "NULL plan");
+  const gq::Tree& T = P->tree;
+  for (int b = 0; b < T.nboxes; ++b) {
+    if (box_center)
+      for (int a = 0; a < 3; ++a) box_center[3 * b + a] = T.center[3 * b + a];
+    if (box_h) box_h[b] = T.h[b];
+    if (level) level[b] = T.level[b];
+    if (parent) parent[b] = T.parent[b];
+  }
+  if (ctr_owner)
+    for (int64_t i = 0; i < P->n_ctr; ++i) ctr_owner[T.ctr_order[i]] = T.ctr_box[i];
+  return GQ_OK;
+}
+
+gq_status gq_list_export(const gq_plan* P, int list, int64_t* ptr, int32_t* items,
+                         int64_t* n_items) {
+  if (!P) return fail(GQ_EINVAL, "NULL plan");
+  if (list < 0 || list >= gq::L_NLISTS) return fail(GQ_EINVAL, "list index out of range");
+  const gq::BoxList& L = P->lists.lst[list];
+  if (n_items) *n_items = L.total();
+  if (ptr)
+    for (size_t i = 0; i < L.ptr.size(); ++i) ptr[i] = L.ptr[i];
+  if (items)
+    for (size_t i = 0; i < L.items.size(); ++i) items[i] = L.items[i];
+  return GQ_OK;
+}
+
+gq_status gq_qbx_locals(gq_plan* P, double* host_out) {
+  if (!P || !host_out) return fail(GQ_EINVAL, "NULL argument");
+  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
+  std::vector<double> buf((size_t)P->n_ctr * P->nq);
+  GQ_HIP(hipStreamSynchronize(P->last_stream));
+  GQ_HIP(hipMemcpy(buf.data(), P->Lq, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < P->n_ctr; ++i) {
+    int64_t j = P->tree.ctr_order[i];
+    for (int k = 0; k < P->nq; ++k) host_out[j * P->nq + k] = buf[(size_t)k * P->n_ctr + i];
+  }
+  return GQ_OK;
+}
+
+gq_status gq_translation_matrix(int kind, int p, int a, int b, int c, double* out) {
+  if (!out || p < 0 || p > gq::kPmax) return fail(GQ_EINVAL, "bad argument");
+  if (kind == 0 || kind == 1) {
+    if (a < 0 || a > 7) return fail(GQ_EINVAL, "octant out of range");
+    (kind == 0 ? gq::m2m_matrix : gq::l2l_matrix)(p, a, out);
+    return GQ_OK;
+  }
+  if (kind == 2) {
+    if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 1)
+      return fail(GQ_EINVAL, "offset must be nonzero");
+    gq::m2l_matrix(p, a, b, c, out);
+    return GQ_OK;
+  }
+  return fail(GQ_EINVAL, "unknown kind");
+}
+
+}  // extern "C"

@@ -1,0 +1,953 @@
+// GIGAQBX FMM device kernels for gfx950 (CDNA4, 64-wide wavefronts), FP64 throughout.
+//
+// Expansion conventions (see translations.cpp for the derivations):
+//   * solid harmonics with the Condon-Shortley phase; J_n^m := conj(I_n^m)
+//   * multipoles and box locals are scaled by the box half-width a:
+//       mu~_n^m = a^-n sum q R_n^m(s - x_b),   l~_n^m = a^(n+1) sum q J_n^m(s - x_b)
+//   * QBX locals are unscaled: l_n^m(c) = sum q J_n^m(s - c), potential
+//       phi(t) = (1/4pi) sum_n [l_n^0 R_n^0 + 2 sum_{m>0} Re(l_n^m R_n^m)](t - c)
+//   * coefficient vectors are real-packed per degree n: offset n^2,
+//       [Re c_n^0, Re c_n^1, Im c_n^1, ..., Re c_n^n, Im c_n^n]
+//   * QBX locals are stored coefficient-major, Lq[k * nctr + c], so consecutive centers
+//     (consecutive lanes) touch consecutive addresses.
+//   * double layer: the source factor is n_s . grad_s, applied with the ladders
+//       d_z R_n^m = R_{n-1}^m, (d_x + i d_y) R_n^m = R_{n-1}^{m+1}, (d_x - i d_y) R_n^m = -R_{n-1}^{m-1}
+//       d_z I_n^m = -I_{n+1}^m, (d_x + i d_y) I_n^m = I_{n+1}^{m+1}, (d_x - i d_y) I_n^m = -I_{n+1}^{m-1}
+//     and n.grad = n_z d_z + (n_x - i n_y)/2 (d_x + i d_y) + (n_x + i n_y)/2 (d_x - i d_y).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace gq {
+
+namespace {
+
+__device__ __forceinline__ int pkre(int n, int m) { return n * n + (m ? 2 * m - 1 : 0); }
+__device__ __forceinline__ int pkim(int n, int m) { return n * n + 2 * m; }
+__host__ __device__ constexpr int cpk_re(int n, int m) { return n * n + (m ? 2 * m - 1 : 0); }
+__host__ __device__ constexpr int cpk_im(int n, int m) { return n * n + 2 * m; }
+__device__ __forceinline__ int cidx(int n, int m) { return n * n + n + m; }
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
+
+// ------------------------------------------------------------------------------------
+// simple elementwise kernels
+// ------------------------------------------------------------------------------------
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_strength(int64_t n, const int64_t* __restrict__ order,
+                           const double* __restrict__ w, const double* __restrict__ dens,
+                           double* __restrict__ q) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) q[i] = w[i] * dens[order[i]];
+}
+
+// ------------------------------------------------------------------------------------
+// P2M and P2L: one 32-lane group per source, lane m owns the order-m column of the
+// expansion (all degrees n >= m), 8 sources in flight per 256-thread block.
+// ------------------------------------------------------------------------------------
+
+constexpr int kGroup = 32;
+constexpr int kInvTab = kPmax + 3;
+
+__device__ __forceinline__ void fill_invtab(double* tab) {
+  // tab[n * kInvTab + m] = 1/(n^2 - m^2) for n > m
+  for (int i = threadIdx.x; i < kInvTab * kInvTab; i += blockDim.x) {
+    int n = i / kInvTab, m = i % kInvTab;
+    tab[i] = n > m ? 1.0 / (double)(n * n - m * m) : 0.0;
+  }
+}
+
+// Reduce the per-lane column accumulators of all 8 groups and store/accumulate them.
+template <bool kAccumulate>
+__device__ __forceinline__ void reduce_store_columns(double (&ar)[kPmax + 2],
+                                                     double (&ai)[kPmax + 2], int P,
+                                                     double* red, double* out) {
+  const int lane = threadIdx.x & 31, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int n = 0; n <= kPmax + 1; ++n) {
+    ar[n] += __shfl_down(ar[n], 32, 64);
+    ai[n] += __shfl_down(ai[n], 32, 64);
+  }
+  // red layout: [wave][n][lane] re, then im
+  if ((threadIdx.x & 63) < 32) {
+#pragma unroll
+    for (int n = 0; n <= kPmax + 1; ++n) {
+      red[(wave * 2 * (kPmax + 2) + n) * 32 + lane] = ar[n];
+      red[(wave * 2 * (kPmax + 2) + kPmax + 2 + n) * 32 + lane] = ai[n];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const int m = lane;
+    for (int n = m; n <= P; ++n) {
+      double sr = 0.0, si = 0.0;
+      for (int w = 0; w < 4; ++w) {
+        sr += red[(w * 2 * (kPmax + 2) + n) * 32 + lane];
+        si += red[(w * 2 * (kPmax + 2) + kPmax + 2 + n) * 32 + lane];
+      }
+      if (kAccumulate) {
+        out[pkre(n, m)] += sr;
+        if (m) out[pkim(n, m)] += si;
+      } else {
+        out[pkre(n, m)] = sr;
+        if (m) out[pkim(n, m)] = si;
+      }
+    }
+  }
+}
+
+template <int KERN>
+__global__ __launch_bounds__(256) void k_p2m(int P, const int* __restrict__ boxes,
+                                             const int64_t* __restrict__ src_start,
+                                             const int64_t* __restrict__ src_count,
+                                             const double* __restrict__ bctr,
+                                             const double* __restrict__ bh, SrcSoA src,
+                                             const double* __restrict__ q,
+                                             double* __restrict__ M) {
+  __shared__ double invtab[kInvTab * kInvTab];
+  __shared__ double red[4 * 2 * (kPmax + 2) * 32];
+  fill_invtab(invtab);
+  __syncthreads();
+  const int b = boxes[blockIdx.x];
+  const int np = (P + 1) * (P + 1);
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int m = lane;
+  const double a = bh[b], inv_a = 1.0 / a;
+  const double xb = bctr[3 * b], yb = bctr[3 * b + 1], zb = bctr[3 * b + 2];
+  double ar[kPmax + 2], ai[kPmax + 2];
+#pragma unroll
+  for (int n = 0; n <= kPmax + 1; ++n) ar[n] = ai[n] = 0.0;
+  const int64_t s0 = src_start[b], ns = src_count[b];
+  for (int64_t j = grp; j < ns; j += 8) {
+    const int64_t s = s0 + j;
+    const double ux = (src.x[s] - xb) * inv_a, uy = (src.y[s] - yb) * inv_a,
+                 uz = (src.z[s] - zb) * inv_a;
+    const double qq = q[s];
+    const double r2 = ux * ux + uy * uy + uz * uz;
+    // diagonal R_m^m = prod_{k<=m} -(ux + i uy)/(2k)
+    double dr = 1.0, di = 0.0;
+#pragma unroll
+    for (int k = 1; k <= kPmax; ++k) {
+      if (k <= m) {
+        const double f = -0.5 / k;
+        const double nr = f * (dr * ux - di * uy), ni = f * (dr * uy + di * ux);
+        dr = nr;
+        di = ni;
+      }
+    }
+    double qz = 0, qxh = 0, qyh = 0;
+    if (KERN) {
+      qz = qq * src.nz[s] * inv_a;
+      qxh = 0.5 * qq * src.nx[s] * inv_a;
+      qyh = 0.5 * qq * src.ny[s] * inv_a;
+    }
+    double p1r = 0, p1i = 0, p2r = 0, p2i = 0;  // R_{n-1}^m, R_{n-2}^m
+#pragma unroll
+    for (int n = 0; n <= kPmax; ++n) {
+      if (n > P) continue;  // uniform
+      double cr, ci;
+      if (n < m) {
+        cr = 0.0;
+        ci = 0.0;
+      } else if (n == m) {
+        cr = dr;
+        ci = di;
+      } else if (n == m + 1) {
+        cr = uz * p1r;
+        ci = uz * p1i;
+      } else {
+        const double t = invtab[n * kInvTab + m];
+        const double c1 = (2.0 * n - 1.0) * uz;
+        cr = (c1 * p1r - r2 * p2r) * t;
+        ci = (c1 * p1i - r2 * p2i) * t;
+      }
+      if (KERN == 0) {
+        ar[n] += qq * cr;
+        ai[n] += qq * ci;
+      } else if (n >= 1) {
+        // R_{n-1}^{m+1}, R_{n-1}^{m-1} from the neighbouring lanes
+        double upr = __shfl_down(p1r, 1, 32), upi = __shfl_down(p1i, 1, 32);
+        double dnr = __shfl_up(p1r, 1, 32), dni = __shfl_up(p1i, 1, 32);
+        if (m + 1 > P) {
+          upr = 0.0;
+          upi = 0.0;
+        }
+        if (m == 0) {  // R^-1 = -conj(R^1)
+          dnr = -upr;
+          dni = upi;
+        }
+        ar[n] += qz * p1r + (qxh * upr + qyh * upi) - (qxh * dnr - qyh * dni);
+        ai[n] += qz * p1i + (qxh * upi - qyh * upr) - (qxh * dni + qyh * dnr);
+      }
+      p2r = p1r;
+      p2i = p1i;
+      p1r = cr;
+      p1i = ci;
+    }
+  }
+  reduce_store_columns<false>(ar, ai, P, red, M + (int64_t)b * np);
+}
+
+template <int KERN>
+__global__ __launch_bounds__(256) void k_p2l(int P, const int* __restrict__ boxes,
+                                             const int64_t* __restrict__ rng_ptr,
+                                             const int64_t* __restrict__ rng_beg,
+                                             const int64_t* __restrict__ rng_cnt,
+                                             const double* __restrict__ bctr,
+                                             const double* __restrict__ bh, SrcSoA src,
+                                             const double* __restrict__ q,
+                                             double* __restrict__ L) {
+  __shared__ double red[4 * 2 * (kPmax + 2) * 32];
+  const int item = blockIdx.x;
+  const int b = boxes[item];
+  const int np = (P + 1) * (P + 1);
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int m = lane;
+  const double a = bh[b], inv_a = 1.0 / a;
+  const double xb = bctr[3 * b], yb = bctr[3 * b + 1], zb = bctr[3 * b + 2];
+  const int NT = P + KERN;  // highest degree of J needed
+  double ar[kPmax + 2], ai[kPmax + 2];
+#pragma unroll
+  for (int n = 0; n <= kPmax + 1; ++n) ar[n] = ai[n] = 0.0;
+  for (int64_t r = rng_ptr[item]; r < rng_ptr[item + 1]; ++r) {
+    const int64_t s0 = rng_beg[r], ns = rng_cnt[r];
+    for (int64_t j = grp; j < ns; j += 8) {
+      const int64_t s = s0 + j;
+      const double ux = (src.x[s] - xb) * inv_a, uy = (src.y[s] - yb) * inv_a,
+                   uz = (src.z[s] - zb) * inv_a;
+      const double qq = q[s];
+      const double r2 = ux * ux + uy * uy + uz * uz;
+      const double ir2 = 1.0 / r2;
+      // diagonal J_m^m = J_0^0 prod_{k<=m} -(2k-1)(ux - i uy)/r^2
+      double dr = sqrt(ir2), di = 0.0;
+#pragma unroll
+      for (int k = 1; k <= kPmax + 1; ++k) {
+        if (k <= m) {
+          const double f = -(2.0 * k - 1.0) * ir2;
+          const double nr = f * (dr * ux + di * uy), ni = f * (di * ux - dr * uy);
+          dr = nr;
+          di = ni;
+        }
+      }
+      double qz = 0, qxh = 0, qyh = 0;
+      if (KERN) {
+        qz = qq * src.nz[s] * inv_a;
+        qxh = 0.5 * qq * src.nx[s] * inv_a;
+        qyh = 0.5 * qq * src.ny[s] * inv_a;
+      }
+      double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
+#pragma unroll
+      for (int n = 0; n <= kPmax + 1; ++n) {
+        if (n > NT) continue;  // uniform
+        double cr, ci;
+        if (n < m) {
+          cr = 0.0;
+          ci = 0.0;
+        } else if (n == m) {
+          cr = dr;
+          ci = di;
+        } else {
+          const double c1 = (2.0 * n - 1.0) * uz * ir2;
+          const double c2 = (double)((n - 1) * (n - 1) - m * m) * ir2;
+          cr = c1 * p1r - c2 * p2r;
+          ci = c1 * p1i - c2 * p2i;
+        }
+        if (KERN == 0) {
+          ar[n] += qq * cr;
+          ai[n] += qq * ci;
+        } else {
+          // l_{n-1}^m += -qz J_n^m + (qx + i qy)/2 J_n^{m+1} - (qx - i qy)/2 J_n^{m-1}
+          double upr = __shfl_down(cr, 1, 32), upi = __shfl_down(ci, 1, 32);
+          double dnr = __shfl_up(cr, 1, 32), dni = __shfl_up(ci, 1, 32);
+          if (m + 1 > NT) {
+            upr = 0.0;
+            upi = 0.0;
+          }
+          if (m == 0) {  // J^-1 = -conj(J^1)
+            dnr = -upr;
+            dni = upi;
+          }
+          if (n >= 1) {
+            ar[n - 1] += -qz * cr + (qxh * upr - qyh * upi) - (qxh * dnr + qyh * dni);
+            ai[n - 1] += -qz * ci + (qxh * upi + qyh * upr) - (qxh * dni - qyh * dnr);
+          }
+        }
+        p2r = p1r;
+        p2i = p1i;
+        p1r = cr;
+        p1i = ci;
+      }
+    }
+  }
+  reduce_store_columns<true>(ar, ai, P, red, L + (int64_t)b * np);
+}
+
+// ------------------------------------------------------------------------------------
+// Batched dense translation Y[dst] += T[cls] X[src]; one tile = up to kTileCols pairs of
+// one class.  T column-major (np x np).  VALU FP64; each thread owns output rows.
+// ------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict__ tile_cls,
+                                                   const int* __restrict__ tile_beg,
+                                                   const int* __restrict__ tile_cnt,
+                                                   const int* __restrict__ pair_src,
+                                                   const int* __restrict__ pair_dst,
+                                                   const double* __restrict__ T,
+                                                   const double* __restrict__ X,
+                                                   double* __restrict__ Y) {
+  extern __shared__ double xs[];  // [np][kTileCols]
+  const int t = blockIdx.x;
+  const int cls = tile_cls[t], beg = tile_beg[t], cnt = tile_cnt[t];
+  for (int i = threadIdx.x; i < np * kTileCols; i += blockDim.x) {
+    const int c = i / np, k = i - c * np;
+    xs[k * kTileCols + c] = c < cnt ? X[(int64_t)pair_src[beg + c] * np + k] : 0.0;
+  }
+  __syncthreads();
+  const double* Tc = T + (int64_t)cls * np * np;
+  for (int row = threadIdx.x; row < np; row += blockDim.x) {
+    double acc[kTileCols];
+#pragma unroll
+    for (int c = 0; c < kTileCols; ++c) acc[c] = 0.0;
+    for (int k = 0; k < np; ++k) {
+      const double a = Tc[(int64_t)k * np + row];
+#pragma unroll
+      for (int c = 0; c < kTileCols; ++c) acc[c] = fma(a, xs[k * kTileCols + c], acc[c]);
+    }
+    for (int c = 0; c < cnt; ++c) atomicAdd(&Y[(int64_t)pair_dst[beg + c] * np + row], acc[c]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// P2QBXL: one thread per (center, source slice); sources staged through LDS.
+// ------------------------------------------------------------------------------------
+
+template <int Q>
+__device__ __forceinline__ void p2qbxl_single(double dx, double dy, double dz, double qq,
+                                              double (&acc)[(Q + 1) * (Q + 1)]) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ir2 = 1.0 / r2;
+  const double zr = dz * ir2;
+  // running diagonal q J_m^m, J = conj(I)
+  double dr = qq * sqrt(ir2), di = 0.0;
+#pragma unroll
+  for (int m = 0; m <= Q; ++m) {
+    if (m > 0) {
+      const double fr = -(2.0 * m - 1.0) * dx * ir2, fi = (2.0 * m - 1.0) * dy * ir2;
+      const double nr = dr * fr - di * fi, ni = dr * fi + di * fr;
+      dr = nr;
+      di = ni;
+    }
+    acc[cpk_re(m, m)] += dr;
+    if (m) acc[cpk_im(m, m)] += di;
+    double p1r = dr, p1i = di, p2r = 0.0, p2i = 0.0;
+#pragma unroll
+    for (int n = m + 1; n <= Q; ++n) {
+      const double c1 = (2.0 * n - 1.0) * zr;
+      const double c2 = (double)((n - 1) * (n - 1) - m * m) * ir2;
+      const double cr = c1 * p1r - c2 * p2r;
+      const double ci = c1 * p1i - c2 * p2i;
+      acc[cpk_re(n, m)] += cr;
+      if (m) acc[cpk_im(n, m)] += ci;
+      p2r = p1r;
+      p2i = p1i;
+      p1r = cr;
+      p1i = ci;
+    }
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz, double qz,
+                                              double qxh, double qyh,
+                                              double (&acc)[(Q + 1) * (Q + 1)]) {
+  // l_n^m += -qz J_{n+1}^m + (qx+i qy)/2 J_{n+1}^{m+1} - (qx-i qy)/2 J_{n+1}^{m-1},
+  // scattered from each J_N^M (N = n+1 <= Q+1) to the outputs it feeds.
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ir2 = 1.0 / r2;
+  const double zr = dz * ir2;
+  double dr = sqrt(ir2), di = 0.0;
+#pragma unroll
+  for (int M = 0; M <= Q + 1; ++M) {
+    if (M > 0) {
+      const double fr = -(2.0 * M - 1.0) * dx * ir2, fi = (2.0 * M - 1.0) * dy * ir2;
+      const double nr = dr * fr - di * fi, ni = dr * fi + di * fr;
+      dr = nr;
+      di = ni;
+    }
+    double p1r = 0.0, p1i = 0.0, p2r = 0.0, p2i = 0.0;
+#pragma unroll
+    for (int N = M; N <= Q + 1; ++N) {
+      double jr, ji;
+      if (N == M) {
+        jr = dr;
+        ji = di;
+      } else {
+        const double c1 = (2.0 * N - 1.0) * zr;
+        const double c2 = (double)((N - 1) * (N - 1) - M * M) * ir2;
+        jr = c1 * p1r - c2 * p2r;
+        ji = c1 * p1i - c2 * p2i;
+      }
+      if (N >= 1) {
+        const int n = N - 1;
+        if (M <= n) {  // -qz J_N^M -> l_n^M
+          acc[cpk_re(n, M)] -= qz * jr;
+          if (M) acc[cpk_im(n, M)] -= qz * ji;
+        }
+        if (M == 1) {  // (qa J^1 + conj(qa J^1)) -> l_n^0
+          acc[cpk_re(n, 0)] += 2.0 * (qxh * jr - qyh * ji);
+        } else if (M >= 2 && M - 1 <= n) {  // qa J_N^M -> l_n^{M-1}
+          acc[cpk_re(n, M - 1)] += qxh * jr - qyh * ji;
+          acc[cpk_im(n, M - 1)] += qxh * ji + qyh * jr;
+        }
+        if (M + 1 <= n) {  // -conj(qa) J_N^M -> l_n^{M+1}
+          acc[cpk_re(n, M + 1)] -= qxh * jr + qyh * ji;
+          acc[cpk_im(n, M + 1)] -= qxh * ji - qyh * jr;
+        }
+      }
+      if (N == M) {
+        p1r = jr;
+        p1i = ji;
+      } else {
+        p2r = p1r;
+        p2i = p1i;
+        p1r = jr;
+        p1i = ji;
+      }
+    }
+  }
+}
+
+template <int Q, int KERN>
+__global__ __launch_bounds__(256) void k_p2qbxl(const int* __restrict__ it_box,
+                                                const int* __restrict__ it_c0,
+                                                const int* __restrict__ it_nc,
+                                                const int64_t* __restrict__ rng_ptr,
+                                                const int64_t* __restrict__ rng_beg,
+                                                const int64_t* __restrict__ rng_cnt,
+                                                SrcSoA src, const double* __restrict__ qs,
+                                                const double* __restrict__ cx,
+                                                const double* __restrict__ cy,
+                                                const double* __restrict__ cz,
+                                                double* __restrict__ Lq, int64_t nctr) {
+  constexpr int NQ = (Q + 1) * (Q + 1);
+  constexpr int NF = KERN ? 7 : 4;
+  constexpr int kRed = 8;
+  __shared__ double ss[NF * 256];
+  __shared__ double red[kRed * 256];
+  const int item = blockIdx.x;
+  const int b = it_box[item];
+  const int c0 = it_c0[item], nc = it_nc[item];
+  const int S = 256 / nc;
+  const int tid = threadIdx.x;
+  const int ci = tid % nc, sl = tid / nc;
+  const bool active = sl < S;
+  const int64_t c = (int64_t)c0 + ci;
+  const double xc = cx[c], yc = cy[c], zc = cz[c];
+  double acc[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
+  for (int64_t r = rng_ptr[b]; r < rng_ptr[b + 1]; ++r) {
+    const int64_t beg = rng_beg[r], cnt = rng_cnt[r];
+    for (int64_t off = 0; off < cnt; off += 256) {
+      const int n = (int)min((int64_t)256, cnt - off);
+      __syncthreads();
+      if (tid < n) {
+        const int64_t s = beg + off + tid;
+        ss[0 * 256 + tid] = src.x[s];
+        ss[1 * 256 + tid] = src.y[s];
+        ss[2 * 256 + tid] = src.z[s];
+        const double qq = qs[s];
+        if (KERN) {
+          ss[3 * 256 + tid] = qq * src.nz[s];
+          ss[4 * 256 + tid] = 0.5 * qq * src.nx[s];
+          ss[5 * 256 + tid] = 0.5 * qq * src.ny[s];
+        } else {
+          ss[3 * 256 + tid] = qq;
+        }
+      }
+      __syncthreads();
+      if (active) {
+        for (int j = sl; j < n; j += S) {
+          const double dx = ss[j] - xc, dy = ss[256 + j] - yc, dz = ss[512 + j] - zc;
+          if (KERN)
+            p2qbxl_double<Q>(dx, dy, dz, ss[768 + j], ss[1024 + j], ss[1280 + j], acc);
+          else
+            p2qbxl_single<Q>(dx, dy, dz, ss[768 + j], acc);
+        }
+      }
+    }
+  }
+  // reduce over source slices and add into Lq
+  if (S == 1) {
+    if (active)
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
+    return;
+  }
+#pragma unroll
+  for (int base = 0; base < NQ; base += kRed) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRed; ++k)
+      if (base + k < NQ) red[k * 256 + tid] = active ? acc[base + k] : 0.0;
+    __syncthreads();
+    if (sl == 0) {
+      for (int k = 0; k < kRed && base + k < NQ; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < S; ++j) s += red[k * 256 + j * nc + ci];
+        Lq[(int64_t)(base + k) * nctr + c] += s;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// M2QBXL and L2QBXL: one thread per center; the (box) expansion is expanded to all
+// signed orders in LDS; J (resp. R) is generated column by column (fixed order M,
+// increasing degree N) and scattered into the order-Q outputs it feeds.
+// ------------------------------------------------------------------------------------
+
+constexpr int kFull = (kPmax + 1) * (kPmax + 1);
+
+__device__ __forceinline__ void stage_full(const double* __restrict__ e, int P, double* fr,
+                                           double* fi) {
+  // e: real-packed; fr/fi[cidx(n, m)] for |m| <= n, using c^-m = (-1)^m conj(c^m)
+  const int np = (P + 1) * (P + 1);
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    int n = (int)sqrt((double)i);
+    while (n * n > i) --n;
+    while ((n + 1) * (n + 1) <= i) ++n;
+    const int off = i - n * n;
+    if (off == 0) {
+      fr[cidx(n, 0)] = e[i];
+      fi[cidx(n, 0)] = 0.0;
+    } else {
+      const int m = (off + 1) >> 1;
+      if (off & 1) {  // real part
+        const double v = e[i];
+        fr[cidx(n, m)] = v;
+        fr[cidx(n, -m)] = (m & 1) ? -v : v;
+      } else {
+        const double v = e[i];
+        fi[cidx(n, m)] = v;
+        fi[cidx(n, -m)] = (m & 1) ? v : -v;
+      }
+    }
+  }
+}
+
+template <int Q>
+__global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it_box,
+                                               const int* __restrict__ it_c0,
+                                               const int* __restrict__ it_nc,
+                                               const int64_t* __restrict__ wf_ptr,
+                                               const int* __restrict__ wf_box,
+                                               const double* __restrict__ bctr,
+                                               const double* __restrict__ bh,
+                                               const double* __restrict__ M,
+                                               const double* __restrict__ cx,
+                                               const double* __restrict__ cy,
+                                               const double* __restrict__ cz,
+                                               double* __restrict__ Lq, int64_t nctr) {
+  constexpr int NQ = (Q + 1) * (Q + 1);
+  __shared__ double mr[kFull], mi[kFull];
+  const int item = blockIdx.x;
+  const int b = it_box[item];
+  const int c0 = it_c0[item], nc = it_nc[item];
+  const bool active = (int)threadIdx.x < nc;
+  const int64_t c = (int64_t)c0 + (active ? threadIdx.x : 0);
+  const double xc = cx[c], yc = cy[c], zc = cz[c];
+  const int np = (P + 1) * (P + 1);
+  const int NT = P + Q;
+  double acc[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
+  for (int64_t w = wf_ptr[b]; w < wf_ptr[b + 1]; ++w) {
+    const int d = wf_box[w];
+    __syncthreads();
+    stage_full(M + (int64_t)d * np, P, mr, mi);
+    __syncthreads();
+    const double a = bh[d], inv_a = 1.0 / a;
+    const double ux = (xc - bctr[3 * d]) * inv_a, uy = (yc - bctr[3 * d + 1]) * inv_a,
+                 uz = (zc - bctr[3 * d + 2]) * inv_a;
+    const double r2 = ux * ux + uy * uy + uz * uz, ir2 = 1.0 / r2, zr = uz * ir2;
+    double t[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) t[i] = 0.0;
+    double dr = sqrt(ir2), di = 0.0;
+    for (int Mo = 0; Mo <= NT; ++Mo) {
+      if (Mo > 0) {
+        const double fr = -(2.0 * Mo - 1.0) * ux * ir2, fi = (2.0 * Mo - 1.0) * uy * ir2;
+        const double nr = dr * fr - di * fi, ni = dr * fi + di * fr;
+        dr = nr;
+        di = ni;
+      }
+      const double sgn = (Mo & 1) ? -1.0 : 1.0;
+      double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
+      for (int N = Mo; N <= NT; ++N) {
+        double jr, ji;
+        if (N == Mo) {
+          jr = dr;
+          ji = di;
+        } else {
+          const double c1 = (2.0 * N - 1.0) * zr;
+          const double c2 = (double)((N - 1) * (N - 1) - Mo * Mo) * ir2;
+          jr = c1 * p1r - c2 * p2r;
+          ji = c1 * p1i - c2 * p2i;
+          p2r = p1r;
+          p2i = p1i;
+        }
+        p1r = jr;
+        p1i = ji;
+        // l_j^k += mu~_n^m J_N^{m+k}, n = N - j: m = Mo - k and m = -Mo - k (J^-Mo)
+#pragma unroll
+        for (int j = 0; j <= Q; ++j) {
+          const int n = N - j;
+          if (n < 0 || n > P) continue;
+#pragma unroll
+          for (int k = 0; k <= j; ++k) {
+            const int m1 = Mo - k;
+            if (m1 >= -n && m1 <= n) {
+              const double ar = mr[cidx(n, m1)], ai = mi[cidx(n, m1)];
+              t[cpk_re(j, k)] += ar * jr - ai * ji;
+              if (k) t[cpk_im(j, k)] += ar * ji + ai * jr;
+            }
+            if (Mo > 0) {
+              const int m2 = -Mo - k;
+              if (m2 >= -n) {
+                const double ar = mr[cidx(n, m2)], ai = mi[cidx(n, m2)];
+                // (-1)^Mo conj(J)
+                t[cpk_re(j, k)] += sgn * (ar * jr + ai * ji);
+                if (k) t[cpk_im(j, k)] += sgn * (ai * jr - ar * ji);
+              }
+            }
+          }
+        }
+      }
+    }
+    // scale (-1)^j a^-(j+1)
+    double s = inv_a;
+#pragma unroll
+    for (int j = 0; j <= Q; ++j) {
+      const double f = (j & 1) ? -s : s;
+#pragma unroll
+      for (int k = 0; k <= j; ++k) {
+        acc[cpk_re(j, k)] += f * t[cpk_re(j, k)];
+        if (k) acc[cpk_im(j, k)] += f * t[cpk_im(j, k)];
+      }
+      s *= inv_a;
+    }
+  }
+  if (active)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
+}
+
+template <int Q>
+__global__ __launch_bounds__(64) void k_l2qbxl(int P, const int* __restrict__ it_box,
+                                               const int* __restrict__ it_c0,
+                                               const int* __restrict__ it_nc,
+                                               const double* __restrict__ bctr,
+                                               const double* __restrict__ bh,
+                                               const double* __restrict__ L,
+                                               const double* __restrict__ cx,
+                                               const double* __restrict__ cy,
+                                               const double* __restrict__ cz,
+                                               double* __restrict__ Lq, int64_t nctr) {
+  constexpr int NQ = (Q + 1) * (Q + 1);
+  __shared__ double lr[kFull], li[kFull];
+  __shared__ double invtab[kInvTab * kInvTab];
+  const int item = blockIdx.x;
+  const int b = it_box[item];
+  const int c0 = it_c0[item], nc = it_nc[item];
+  const bool active = (int)threadIdx.x < nc;
+  const int64_t c = (int64_t)c0 + (active ? threadIdx.x : 0);
+  const int np = (P + 1) * (P + 1);
+  fill_invtab(invtab);
+  stage_full(L + (int64_t)b * np, P, lr, li);
+  __syncthreads();
+  const double a = bh[b], inv_a = 1.0 / a;
+  const double ux = (cx[c] - bctr[3 * b]) * inv_a, uy = (cy[c] - bctr[3 * b + 1]) * inv_a,
+               uz = (cz[c] - bctr[3 * b + 2]) * inv_a;
+  const double r2 = ux * ux + uy * uy + uz * uz;
+  double t[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) t[i] = 0.0;
+  double dr = 1.0, di = 0.0;
+  for (int mu = 0; mu <= P; ++mu) {
+    if (mu > 0) {
+      const double f = -0.5 / mu;
+      const double nr = f * (dr * ux - di * uy), ni = f * (dr * uy + di * ux);
+      dr = nr;
+      di = ni;
+    }
+    const double sgn = (mu & 1) ? -1.0 : 1.0;
+    double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
+    for (int N = mu; N <= P; ++N) {
+      double rr, ri;
+      if (N == mu) {
+        rr = dr;
+        ri = di;
+      } else if (N == mu + 1) {
+        rr = uz * p1r;
+        ri = uz * p1i;
+        p2r = p1r;
+        p2i = p1i;
+      } else {
+        const double tt = invtab[N * kInvTab + mu];
+        const double c1 = (2.0 * N - 1.0) * uz;
+        rr = (c1 * p1r - r2 * p2r) * tt;
+        ri = (c1 * p1i - r2 * p2i) * tt;
+        p2r = p1r;
+        p2i = p1i;
+      }
+      p1r = rr;
+      p1i = ri;
+      // l_j^k += l~_n^m R_N^{m-k}, n = N + j: m = mu + k and m = -mu + k (R^-mu)
+#pragma unroll
+      for (int j = 0; j <= Q; ++j) {
+        const int n = N + j;
+        if (n > P) continue;
+#pragma unroll
+        for (int k = 0; k <= j; ++k) {
+          const int m1 = mu + k;
+          if (m1 <= n) {
+            const double ar = lr[cidx(n, m1)], ai = li[cidx(n, m1)];
+            t[cpk_re(j, k)] += ar * rr - ai * ri;
+            if (k) t[cpk_im(j, k)] += ar * ri + ai * rr;
+          }
+          if (mu > 0) {
+            const int m2 = k - mu;
+            if (m2 >= -n) {
+              const double ar = lr[cidx(n, m2)], ai = li[cidx(n, m2)];
+              t[cpk_re(j, k)] += sgn * (ar * rr + ai * ri);
+              if (k) t[cpk_im(j, k)] += sgn * (ai * rr - ar * ri);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!active) return;
+  double s = inv_a;
+#pragma unroll
+  for (int j = 0; j <= Q; ++j) {
+#pragma unroll
+    for (int k = 0; k <= j; ++k) {
+      Lq[(int64_t)cpk_re(j, k) * nctr + c] += s * t[cpk_re(j, k)];
+      if (k) Lq[(int64_t)cpk_im(j, k) * nctr + c] += s * t[cpk_im(j, k)];
+    }
+    s *= inv_a;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// QBXL2P: one thread per target.
+// ------------------------------------------------------------------------------------
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_qbxl2p(int64_t ntgt, const int64_t* __restrict__ tgt_ctr,
+                                                const double* __restrict__ tx,
+                                                const double* __restrict__ ty,
+                                                const double* __restrict__ tz,
+                                                const double* __restrict__ cx,
+                                                const double* __restrict__ cy,
+                                                const double* __restrict__ cz,
+                                                const double* __restrict__ Lq, int64_t nctr,
+                                                const int64_t* __restrict__ out_idx,
+                                                double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntgt) return;
+  const int64_t c = tgt_ctr[t];
+  const double ux = tx[t] - cx[c], uy = ty[t] - cy[c], uz = tz[t] - cz[c];
+  const double r2 = ux * ux + uy * uy + uz * uz;
+  double phi = 0.0;
+  double dr = 1.0, di = 0.0;
+#pragma unroll
+  for (int m = 0; m <= Q; ++m) {
+    if (m > 0) {
+      const double f = -0.5 / m;
+      const double nr = f * (dr * ux - di * uy), ni = f * (dr * uy + di * ux);
+      dr = nr;
+      di = ni;
+    }
+    const double wgt = m ? 2.0 : 1.0;
+    double p1r = dr, p1i = di, p2r = 0.0, p2i = 0.0;
+    phi += wgt * (Lq[(int64_t)cpk_re(m, m) * nctr + c] * dr -
+                  (m ? Lq[(int64_t)cpk_im(m, m) * nctr + c] * di : 0.0));
+#pragma unroll
+    for (int n = m + 1; n <= Q; ++n) {
+      double rr, ri;
+      if (n == m + 1) {
+        rr = uz * p1r;
+        ri = uz * p1i;
+      } else {
+        const double inv = 1.0 / (double)(n * n - m * m);
+        const double c1 = (2.0 * n - 1.0) * uz;
+        rr = (c1 * p1r - r2 * p2r) * inv;
+        ri = (c1 * p1i - r2 * p2i) * inv;
+      }
+      phi += wgt * (Lq[(int64_t)cpk_re(n, m) * nctr + c] * rr -
+                    (m ? Lq[(int64_t)cpk_im(n, m) * nctr + c] * ri : 0.0));
+      p2r = p1r;
+      p2i = p1i;
+      p1r = rr;
+      p1i = ri;
+    }
+  }
+  out[out_idx[t]] = phi * kInv4Pi;
+}
+
+// ------------------------------------------------------------------------------------
+// dispatch helpers over the compile-time QBX order
+// ------------------------------------------------------------------------------------
+
+template <template <int> class F, int Qv = 0>
+struct QDispatch {
+  template <class... A>
+  static void run(int q, A&&... a) {
+    if (q == Qv)
+      F<Qv>::go(a...);
+    else if constexpr (Qv < kQmax)
+      QDispatch<F, Qv + 1>::run(q, a...);
+  }
+};
+
+inline dim3 grid1d(int64_t n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+template <int Q>
+struct P2qbxlGo {
+  static void go(hipStream_t s, int kernel, int nitem, const int* it_box, const int* it_c0,
+                 const int* it_nc, const int64_t* rp, const int64_t* rb, const int64_t* rc,
+                 SrcSoA src, const double* qs, const double* cx, const double* cy,
+                 const double* cz, double* Lq, int64_t nctr) {
+    if (kernel)
+      k_p2qbxl<Q, 1><<<nitem, 256, 0, s>>>(it_box, it_c0, it_nc, rp, rb, rc, src, qs, cx, cy,
+                                           cz, Lq, nctr);
+    else
+      k_p2qbxl<Q, 0><<<nitem, 256, 0, s>>>(it_box, it_c0, it_nc, rp, rb, rc, src, qs, cx, cy,
+                                           cz, Lq, nctr);
+  }
+};
+
+template <int Q>
+struct M2qbxlGo {
+  static void go(hipStream_t s, int p, int nitem, const int* it_box, const int* it_c0,
+                 const int* it_nc, const int64_t* wf_ptr, const int* wf_box,
+                 const double* bctr, const double* bh, const double* M, const double* cx,
+                 const double* cy, const double* cz, double* Lq, int64_t nctr) {
+    k_m2qbxl<Q><<<nitem, 64, 0, s>>>(p, it_box, it_c0, it_nc, wf_ptr, wf_box, bctr, bh, M, cx,
+                                     cy, cz, Lq, nctr);
+  }
+};
+
+template <int Q>
+struct L2qbxlGo {
+  static void go(hipStream_t s, int p, int nitem, const int* it_box, const int* it_c0,
+                 const int* it_nc, const double* bctr, const double* bh, const double* L,
+                 const double* cx, const double* cy, const double* cz, double* Lq,
+                 int64_t nctr) {
+    k_l2qbxl<Q><<<nitem, 64, 0, s>>>(p, it_box, it_c0, it_nc, bctr, bh, L, cx, cy, cz, Lq,
+                                     nctr);
+  }
+};
+
+template <int Q>
+struct Qbxl2pGo {
+  static void go(hipStream_t s, int64_t ntgt, const int64_t* tgt_ctr, const double* tx,
+                 const double* ty, const double* tz, const double* cx, const double* cy,
+                 const double* cz, const double* Lq, int64_t nctr, const int64_t* out_idx,
+                 double* out) {
+    k_qbxl2p<Q><<<grid1d(ntgt, 256), 256, 0, s>>>(ntgt, tgt_ctr, tx, ty, tz, cx, cy, cz, Lq,
+                                                  nctr, out_idx, out);
+  }
+};
+
+}  // namespace
+
+void launch_fill(hipStream_t s, double* p, int64_t n, double v) {
+  if (n <= 0) return;
+  int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  k_fill<<<(unsigned)blocks, 256, 0, s>>>(p, n, v);
+}
+
+void launch_strength(hipStream_t s, int64_t n, const int64_t* order, const double* w,
+                     const double* density, double* q) {
+  if (n <= 0) return;
+  k_strength<<<grid1d(n, 256), 256, 0, s>>>(n, order, w, density, q);
+}
+
+void launch_p2m(hipStream_t s, int kernel, int p, int nbox, const int* boxes,
+                const int64_t* src_start, const int64_t* src_count, const double* bctr,
+                const double* bh, SrcSoA src, const double* q, double* M) {
+  if (nbox <= 0) return;
+  if (kernel)
+    k_p2m<1><<<nbox, 256, 0, s>>>(p, boxes, src_start, src_count, bctr, bh, src, q, M);
+  else
+    k_p2m<0><<<nbox, 256, 0, s>>>(p, boxes, src_start, src_count, bctr, bh, src, q, M);
+}
+
+void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
+                const int64_t* rng_ptr, const int64_t* rng_beg, const int64_t* rng_cnt,
+                const double* bctr, const double* bh, SrcSoA src, const double* q, double* L) {
+  if (nitem <= 0) return;
+  if (kernel)
+    k_p2l<1><<<nitem, 256, 0, s>>>(p, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
+  else
+    k_p2l<0><<<nitem, 256, 0, s>>>(p, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
+}
+
+void launch_translate(hipStream_t s, int np, int ntile, const int* tile_cls,
+                      const int* tile_beg, const int* tile_cnt, const int* pair_src,
+                      const int* pair_dst, const double* T, const double* X, double* Y) {
+  if (ntile <= 0) return;
+  size_t lds = (size_t)np * kTileCols * sizeof(double);
+  k_translate<<<ntile, 256, lds, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T,
+                                      X, Y);
+}
+
+void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
+                   const int* it_c0, const int* it_nc, const int64_t* rng_ptr,
+                   const int64_t* rng_beg, const int64_t* rng_cnt, SrcSoA src,
+                   const double* qs, const double* cx, const double* cy, const double* cz,
+                   double* Lq, int64_t nctr) {
+  if (nitem <= 0) return;
+  QDispatch<P2qbxlGo>::run(q, s, kernel, nitem, it_box, it_c0, it_nc, rng_ptr, rng_beg,
+                           rng_cnt, src, qs, cx, cy, cz, Lq, nctr);
+}
+
+void launch_m2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
+                   const int* it_c0, const int* it_nc, const int64_t* wf_ptr,
+                   const int* wf_box, const double* bctr, const double* bh, const double* M,
+                   const double* cx, const double* cy, const double* cz, double* Lq,
+                   int64_t nctr) {
+  if (nitem <= 0) return;
+  QDispatch<M2qbxlGo>::run(q, s, p, nitem, it_box, it_c0, it_nc, wf_ptr, wf_box, bctr, bh, M,
+                           cx, cy, cz, Lq, nctr);
+}
+
+void launch_l2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
+                   const int* it_c0, const int* it_nc, const double* bctr, const double* bh,
+                   const double* L, const double* cx, const double* cy, const double* cz,
+                   double* Lq, int64_t nctr) {
+  if (nitem <= 0) return;
+  QDispatch<L2qbxlGo>::run(q, s, p, nitem, it_box, it_c0, it_nc, bctr, bh, L, cx, cy, cz, Lq,
+                           nctr);
+}
+
+void launch_qbxl2p(hipStream_t s, int q, int64_t ntgt, const int64_t* tgt_ctr,
+                   const double* tx, const double* ty, const double* tz, const double* cx,
+                   const double* cy, const double* cz, const double* Lq, int64_t nctr,
+                   const int64_t* out_idx, double* out) {
+  if (ntgt <= 0) return;
+  QDispatch<Qbxl2pGo>::run(q, s, ntgt, tgt_ctr, tx, ty, tz, cx, cy, cz, Lq, nctr, out_idx,
+                           out);
+}
+
+}  // namespace gq

@@ -1,0 +1,67 @@
+// Launchers for the GIGAQBX device kernels (gfx950).  All arrays are device pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gq {
+
+constexpr int kPmax = 20;  // highest FMM order supported by the device kernels
+constexpr int kQmax = 10;  // highest QBX order supported by the device kernels
+constexpr int kTileCols = 16;  // expansions per translation tile
+
+struct SrcSoA {
+  const double *x, *y, *z, *nx, *ny, *nz;
+};
+
+// q[i] = w[i] * density[order[i]]
+void launch_strength(hipStream_t s, int64_t n, const int64_t* order, const double* w,
+                     const double* density, double* q);
+void launch_fill(hipStream_t s, double* p, int64_t n, double v);
+
+// Stage 2a: multipoles (scaled) of leaf boxes from their own sources.
+void launch_p2m(hipStream_t s, int kernel, int p, int nbox, const int* boxes,
+                const int64_t* src_start, const int64_t* src_count, const double* bctr,
+                const double* bh, SrcSoA src, const double* q, double* M);
+
+// Stage 6b: box locals (scaled) of target boxes from the sources of their X-far boxes.
+// Item i: box boxes[i], source ranges [rng_ptr[i], rng_ptr[i+1]) of (rng_beg, rng_cnt).
+// Accumulates into L.
+void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
+                const int64_t* rng_ptr, const int64_t* rng_beg, const int64_t* rng_cnt,
+                const double* bctr, const double* bh, SrcSoA src, const double* q, double* L);
+
+// Batched dense translations: for each tile t, Y[dst] += T[cls] X[src] for its pairs.
+void launch_translate(hipStream_t s, int np, int ntile, const int* tile_cls,
+                      const int* tile_beg, const int* tile_cnt, const int* pair_src,
+                      const int* pair_dst, const double* T, const double* X, double* Y);
+
+// Stages 3, 5a, 6a: QBX locals from the near sources (U, W-close, X-close).
+// Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]).
+void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
+                   const int* it_c0, const int* it_nc, const int64_t* rng_ptr,
+                   const int64_t* rng_beg, const int64_t* rng_cnt, SrcSoA src,
+                   const double* qs, const double* cx, const double* cy, const double* cz,
+                   double* Lq, int64_t nctr);
+
+// Stage 5b: QBX locals from W-far multipoles (list per target box in CSR wf_ptr/wf_box).
+void launch_m2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
+                   const int* it_c0, const int* it_nc, const int64_t* wf_ptr,
+                   const int* wf_box, const double* bctr, const double* bh, const double* M,
+                   const double* cx, const double* cy, const double* cz, double* Lq,
+                   int64_t nctr);
+
+// Stage 8: QBX locals from the owning box's local.
+void launch_l2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
+                   const int* it_c0, const int* it_nc, const double* bctr, const double* bh,
+                   const double* L, const double* cx, const double* cy, const double* cz,
+                   double* Lq, int64_t nctr);
+
+// Stage 9: potential at targets (tree order t -> output index out_idx[t]).
+void launch_qbxl2p(hipStream_t s, int q, int64_t ntgt, const int64_t* tgt_ctr,
+                   const double* tx, const double* ty, const double* tz, const double* cx,
+                   const double* cy, const double* cz, const double* Lq, int64_t nctr,
+                   const int64_t* out_idx, double* out);
+
+}  // namespace gq

@@ -1,0 +1,75 @@
+// Host-side planner for the GIGAQBX FMM: octree with target-confinement-restricted QBX
+// centers (Algorithm 5, Stage 1) and the interaction lists of Section 5.2 (Lists 1-4 and
+// the close/far split of Lists 3 and 4).  Plain C++17; no device code.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gq {
+
+struct TreeParams {
+  int nmax = 512;
+  double tcf = 0.9;
+  int max_level = 30;
+};
+
+// Octree.  Boxes are numbered breadth-first, children in octant order (bit 0: x upper,
+// bit 1: y upper, bit 2: z upper).  Particles are renumbered in depth-first (preorder)
+// order of their owning box, so every box owns a contiguous range.
+struct Tree {
+  int nboxes = 0;
+  int nlevels = 0;
+  double root_center[3] = {0, 0, 0};
+  double root_h = 0;
+  std::vector<double> center;  // 3 * nboxes
+  std::vector<double> h;       // half-width |b|
+  std::vector<int> level, parent;
+  std::vector<std::array<int, 8>> child;  // -1 where pruned
+  std::vector<int> nchild;
+  std::vector<int64_t> ix, iy, iz;        // integer cell coordinates at the box's level
+  std::vector<int> preorder;              // boxes in depth-first order
+  std::vector<int> pre_index;             // box -> position in preorder
+  // ownership after renumbering
+  std::vector<int64_t> src_start, src_count;  // owned sources (leaves only)
+  std::vector<int64_t> ctr_start, ctr_count;  // owned centers
+  std::vector<int64_t> sub_src;               // sources in subtree
+  std::vector<int64_t> src_order;  // tree position -> input source index
+  std::vector<int64_t> ctr_order;  // tree position -> input center index
+  std::vector<int64_t> ctr_box;    // tree position -> owning box
+  bool is_leaf(int b) const { return nchild[b] == 0; }
+};
+
+// CSR list over boxes: entries of box b are items[ptr[b] .. ptr[b+1]).
+struct BoxList {
+  std::vector<int64_t> ptr;
+  std::vector<int> items;
+  int64_t size(int b) const { return ptr[b + 1] - ptr[b]; }
+  int64_t total() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+enum ListId { L_U = 0, L_V = 1, L_WCLOSE = 2, L_WFAR = 3, L_XCLOSE = 4, L_XFAR = 5, L_NLISTS = 6 };
+
+struct Lists {
+  std::vector<uint8_t> is_target;    // box owns >= 1 center
+  std::vector<uint8_t> is_owner;     // target or target-ancestor box
+  BoxList lst[L_NLISTS];
+};
+
+// Builds the tree.  Returns an empty string on success, else a message.
+std::string build_tree(const TreeParams& prm, int64_t n_src, const double* src_xyz,
+                       int64_t n_ctr, const double* ctr_xyz, const double* ctr_radius,
+                       int64_t n_tgt, const double* tgt_xyz, Tree& tree);
+
+// Builds all interaction lists for target and target-ancestor boxes.
+void build_lists(const Tree& tree, double tcf, Lists& lists);
+
+// Dense real-packed translation matrices in scaled form (see translations.cpp).
+int ncoef(int p);
+void m2m_matrix(int p, int octant, double* T);                  // child multipole -> parent
+void l2l_matrix(int p, int octant, double* T);                  // parent local -> child
+void m2l_matrix(int p, int ox, int oy, int oz, double* T);      // same-level, offset 2*o
+
+}  // namespace gq

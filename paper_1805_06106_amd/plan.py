@@ -1,0 +1,71 @@
+"""Convenience wrapper owning a plan handle (argument marshalling only)."""
+
+from __future__ import annotations
+
+from . import _capi as C
+
+
+class Plan:
+    """A GIGAQBX plan for fixed geometry; apply() evaluates densities on the GPU.
+
+    Geometry arrays are numpy (N,3)/(N,) float64; densities/potentials are torch tensors on
+    the GPU, shaped (n_densities, n_src) / (n_densities, n_tgt), float64.
+    """
+
+    def __init__(self, *, src_xyz, src_w, src_normal, ctr_xyz, ctr_radius, tgt_xyz, tgt_center,
+                 p_qbx, p_fmm, kernel="S", nmax=512, tcf=0.9, n_densities=1, timing=False,
+                 host_only=False, lists=None, stream=None):
+        flags = (C.GQ_FLAG_TIMING if timing else 0) | (C.GQ_FLAG_HOST_ONLY if host_only else 0)
+        self.params = C.make_params(p_qbx, p_fmm, nmax=nmax, tcf=tcf, kernel=kernel,
+                                    n_densities=n_densities, flags=flags, lists=lists)
+        self.n_src = int(src_xyz.shape[0])
+        self.n_ctr = int(ctr_xyz.shape[0])
+        self.n_tgt = int(tgt_xyz.shape[0])
+        self.p_qbx = int(p_qbx)
+        self.n_densities = int(n_densities)
+        self.handle = None
+        self.handle = C.gq_plan_create(self.params, src_xyz, src_w, src_normal, ctr_xyz,
+                                       ctr_radius, tgt_xyz, tgt_center, stream=stream)
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        args = dict(p_qbx=w.p_qbx, p_fmm=w.p_fmm, kernel=w.kernel, nmax=w.nmax, tcf=w.tcf)
+        args.update(kw)
+        return cls(src_xyz=w.src_xyz, src_w=w.src_w, src_normal=w.src_normal, ctr_xyz=w.ctr_xyz,
+                   ctr_radius=w.ctr_radius, tgt_xyz=w.tgt_xyz, tgt_center=w.tgt_center, **args)
+
+    def apply(self, density, potential=None, stream=None):
+        import torch
+
+        if potential is None:
+            potential = torch.empty((self.n_densities, self.n_tgt), dtype=torch.float64,
+                                    device=density.device)
+        if density.dtype != torch.float64 or not density.is_contiguous():
+            raise ValueError("density must be a contiguous float64 device tensor")
+        if tuple(density.shape) != (self.n_densities, self.n_src):
+            raise ValueError(f"density shape {tuple(density.shape)} != {(self.n_densities, self.n_src)}")
+        C.gq_apply(self.handle, density, potential, stream=stream)
+        return potential
+
+    def stats(self):
+        return C.gq_stats(self.handle)
+
+    def qbx_locals(self):
+        return C.gq_qbx_locals(self.handle, self.n_ctr, self.p_qbx)
+
+    def tree(self):
+        return C.gq_tree_export(self.handle, self.n_ctr)
+
+    def list(self, name):
+        return C.gq_list_export(self.handle, name)
+
+    def close(self):
+        if self.handle:
+            C.gq_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,154 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance: the stated bar for the FP64 path is 1e-8 relative (l-inf error over l-inf norm of
+the oracle's result, per density); the tests assert 1e-10, which the two FP64
+implementations (different formula routes, same arithmetic precision) meet with margin.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.gigaqbx import OracleFMM
+from workloads import workload_c1, workload_tiny
+
+import gq_convert as CV
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+TOL = 1e-10
+
+CASES = {
+    "S-l1-n32": dict(level=1, order=2, kernel="S", p_qbx=3, p_fmm=6, nmax=32),
+    "D-l1-n32": dict(level=1, order=2, kernel="D", p_qbx=3, p_fmm=6, nmax=32),
+    "S-l2-tf05": dict(level=2, order=1, kernel="S", p_qbx=2, p_fmm=5, nmax=24, tcf=0.5),
+    "D-l2-flat": dict(level=2, order=1, kernel="D", p_qbx=2, p_fmm=5, nmax=40, curved=False),
+    "D-l2-q5p15": dict(level=2, order=2, kernel="D", p_qbx=5, p_fmm=15, nmax=48),
+    "S-l2-q8p20": dict(level=2, order=2, kernel="S", p_qbx=8, p_fmm=20, nmax=48),
+}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    import paper_1805_06106_amd  # noqa: F401  (fails loudly if the library is missing)
+
+    return torch.device("cuda:0")
+
+
+def run_gpu(w, dev, **kw):
+    import torch
+
+    from paper_1805_06106_amd import Plan
+
+    P = Plan.from_workload(w, n_densities=w.density.shape[0], **kw)
+    dens = torch.tensor(w.density, dtype=torch.float64, device=dev)
+    pot = P.apply(dens)
+    torch.cuda.synchronize()
+    return P, pot.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_gpu_vs_tier_b(dev, case):
+    w = workload_tiny(**CASES[case])
+    print(f"[gpu] case={case} n_src={w.n_src} n_ctr={w.n_ctr}", flush=True)
+    P, pot = run_gpu(w, dev)
+    F = OracleFMM(w)
+    tids, ref, qloc = F.evaluate()
+    assert rel(pot[0][tids], ref) < TOL
+    # QBX locals (after Stage 8) against the oracle's, mapped to the internal form
+    Lq = P.qbx_locals()
+    for c in range(0, w.n_ctr, max(1, w.n_ctr // 97)):
+        want = CV.paper_local_to_packed(qloc[c], w.p_qbx)
+        assert np.max(np.abs(Lq[c] - want)) <= TOL * np.max(np.abs(want)) * 10
+
+
+@pytest.mark.parametrize("case", ["S-l1-n32", "D-l1-n32", "D-l2-q5p15"])
+@pytest.mark.parametrize("lst", ["U", "V", "Wclose", "Wfar", "Xclose", "Xfar"])
+def test_gpu_per_list_vs_tier_b(dev, case, lst):
+    w = workload_tiny(**CASES[case])
+    print(f"[gpu] case={case} list={lst}", flush=True)
+    _, pot = run_gpu(w, dev, lists=(lst,))
+    F = OracleFMM(w)
+    tids, ref, _ = F.evaluate(lists=(lst,))
+    _, full, _ = F.evaluate()
+    err = np.max(np.abs(pot[0][tids] - ref)) / np.max(np.abs(full))
+    assert err < TOL
+
+
+@pytest.mark.parametrize("kernel", ["S", "D"])
+def test_single_box_equals_direct(dev, kernel):
+    w = workload_tiny(level=1, order=2, kernel=kernel, p_qbx=4, p_fmm=4, nmax=10 ** 7)
+    print(f"[gpu] single box {kernel}", flush=True)
+    _, pot = run_gpu(w, dev)
+    ref, _ = O.direct_qbx(kernel, w.p_qbx, w.src_xyz, w.strengths()[0], w.ctr_xyz, w.tgt_xyz,
+                          w.tgt_center, nrm=w.src_normal)
+    assert rel(pot[0], ref) < 1e-12
+
+
+def test_c1_vs_tier_b_and_tier_a(dev):
+    w = workload_c1()
+    print("[gpu] C1 sphere320 S 3/10", flush=True)
+    _, pot = run_gpu(w, dev)
+    F = OracleFMM(w)
+    tids, ref, _ = F.evaluate()
+    assert rel(pot[0][tids], ref) < TOL
+    refA, _ = O.direct_qbx("S", w.p_qbx, w.src_xyz, w.strengths()[0], w.ctr_xyz, w.tgt_xyz,
+                           w.tgt_center)
+    assert rel(pot[0], refA) <= 0.75 ** (w.p_fmm + 1)
+
+
+def test_c1_small_boxes_vs_tier_b(dev):
+    w = workload_c1(nmax=32)
+    print("[gpu] C1 nmax=32", flush=True)
+    _, pot = run_gpu(w, dev)
+    F = OracleFMM(w)
+    rng = np.random.default_rng(0)
+    cs = np.sort(rng.choice(w.n_ctr, 300, replace=False))
+    tids, ref, _ = F.evaluate(centers=cs)
+    assert rel(pot[0][tids], ref) < TOL
+
+
+def test_multiple_densities(dev):
+    w = workload_tiny(level=1, order=2, kernel="D", p_qbx=3, p_fmm=6, nmax=32, n_densities=3)
+    print("[gpu] 3 densities", flush=True)
+    _, pot = run_gpu(w, dev)
+    F = OracleFMM(w)
+    for d in range(3):
+        tids, ref, _ = F.evaluate(density_index=d)
+        assert rel(pot[d][tids], ref) < TOL
+
+
+def test_repeat_apply_stable(dev):
+    import torch
+
+    from paper_1805_06106_amd import Plan
+
+    w = workload_tiny(**CASES["D-l1-n32"])
+    P = Plan.from_workload(w)
+    dens = torch.tensor(w.density, device=dev)
+    a = P.apply(dens).cpu().numpy()
+    b = P.apply(dens).cpu().numpy()
+    assert rel(a, b) < 1e-14
+
+
+def test_zero_density_and_linearity(dev):
+    import torch
+
+    from paper_1805_06106_amd import Plan
+
+    w = workload_tiny(**CASES["S-l1-n32"])
+    P = Plan.from_workload(w)
+    z = torch.zeros((1, w.n_src), dtype=torch.float64, device=dev)
+    assert float(P.apply(z).abs().max()) == 0.0
+    d1 = torch.tensor(w.density, device=dev)
+    d2 = torch.tensor(np.random.default_rng(5).standard_normal((1, w.n_src)), device=dev)
+    p1, p2, p12 = P.apply(d1).cpu().numpy(), P.apply(d2).cpu().numpy(), P.apply(2 * d1 - d2).cpu().numpy()
+    assert rel(p12, 2 * p1 - p2) < 1e-12
