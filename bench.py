@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Benchmark: QBX-FMM target evaluations per second on one MI355X.
+
+Workload (default): the 'urchin' surface rho = 1 + 0.2 Re Y_8^4 on 20,480 curved triangles,
+28 nodes per triangle (573,440 sources), two QBX centers per node (1,146,880 centers, one
+target each), double-layer potential, p_qbx = 5, p_fmm = 15, nmax = 512, t_f = 0.9, FP64.
+One step = one full evaluation (Algorithm 5 Stages 2-9) of one density with the plan cached
+and all inputs resident in HBM.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from workloads import workload_c1, workload_c2, workload_c4
+
+    return {"c1": workload_c1, "c2": workload_c2, "c4": workload_c4}[name]()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--cpu-sample", type=int, default=128,
+                    help="centers evaluated by the CPU oracle (direct QBX) for the baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures a single GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from paper_1805_06106_amd import costmodel as CM
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = make_workload(args.workload)
+    log(f"workload {w.name}: {w.n_src} sources, {w.n_ctr} centers, {w.n_tgt} targets, "
+        f"kernel {w.kernel}, p_qbx={w.p_qbx}, p_fmm={w.p_fmm} ({time.time() - t0:.1f}s)")
+    t0 = time.time()
+    plan = Plan.from_workload(w, timing=True)
+    plan_wall = time.time() - t0
+    st = plan.stats()
+    log(f"plan: {st['n_boxes']} boxes, {st['n_levels']} levels, pairs {st['pairs']} "
+        f"({plan_wall:.2f}s)")
+    dens = torch.tensor(w.density[:1], dtype=torch.float64, device=dev)
+    pot = torch.empty((1, w.n_tgt), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        plan.apply(dens, pot, stream=stream)
+    torch.cuda.synchronize()
+    plan.stats()  # closes the warmup timing window
+    log(f"warmup {args.warmup} done; timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply(dens, pot, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    st = plan.stats()
+    k = max(st["timed_applies"], 1)
+    stage_ms = {s: v / k for s, v in st["stage_ms"].items()}
+    value = w.n_tgt / (ms_per_step * 1e-3)
+    log(f"{ms_per_step:.2f} ms/step, {value:.4g} target evals/s; stage ms {stage_ms}")
+
+    flops = CM.apply_flops(st, w.p_fmm, w.p_qbx, w.kernel)
+    kern_stage = {"p2qbxl": "p2qbxl", "m2qbxl": "m2qbxl", "m2l": "m2l", "l2qbxl": "l2qbxl"}
+    dominant = max(kern_stage, key=lambda s: stage_ms[kern_stage[s]])
+    dom_ms = stage_ms[kern_stage[dominant]]
+    achieved = flops[dominant] / (dom_ms * 1e-3) / 1e12
+    roofline = {"kernel": dominant, "bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": flops[dominant], "ms_per_launch": round(dom_ms, 4)}
+    per_stage = {}
+    for s, f in flops.items():
+        ms = stage_ms[kern_stage.get(s, s)]
+        per_stage[s] = {"ms": round(ms, 4), "tflops": round(f / (ms * 1e-3) / 1e12, 3) if ms > 0 else None}
+    m2l = {"engine": "fp64 valu", "ms": round(stage_ms["m2l"], 4),
+           "tflops": per_stage["m2l"]["tflops"],
+           "frac_of_fp64_peak": round(per_stage["m2l"]["tflops"] / PEAK_FP64_VALU_TFLOPS, 4)
+           if per_stage["m2l"]["tflops"] else None}
+
+    cpu = None
+    err_direct = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        rng = np.random.default_rng(12345)
+        cids = np.sort(rng.choice(w.n_ctr, args.cpu_sample, replace=False))
+        log(f"cpu baseline: direct QBX oracle on {len(cids)} centers")
+        t0 = time.perf_counter()
+        tids, ref, used = O.direct_qbx_sampled(w, cids, density_index=0,
+                                               nthreads=int(os.environ.get("OMP_NUM_THREADS", "0")))
+        dt = time.perf_counter() - t0
+        got = pot[0].cpu().numpy()[tids]
+        err_direct = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        cpu = {"value": round(len(tids) / dt, 3), "unit": "target evals/s", "cores": int(used),
+               "kind": "oracle",
+               "sample": f"direct (unaccelerated) FP64 QBX on {len(cids)} random centers of "
+                         f"{w.n_ctr}, each from all {w.n_src} sources; {dt:.1f}s"}
+        log(f"cpu baseline {cpu['value']} evals/s on {used} threads; rel err vs direct {err_direct:.3e}")
+
+    out = {
+        "metric": "QBX-FMM target evals/sec at stated rel. error; M2L MFMA util (FP32 vs FP64)",
+        "value": round(value, 1),
+        "unit": "target evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "kernel": w.kernel, "p_qbx": w.p_qbx, "p_fmm": w.p_fmm,
+                   "n_sources": w.n_src, "n_centers": w.n_ctr, "n_targets": w.n_tgt,
+                   "nmax": w.nmax, "tcf": w.tcf, "n_densities": 1, "precision": "fp64"},
+        "rel_err_vs_direct_qbx": err_direct,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "m2l": m2l,
+        "stages": per_stage,
+        "stage_ms": {s: round(v, 4) for s, v in stage_ms.items()},
+        "plan_seconds": round(plan_wall, 3),
+        "tree": {"boxes": st["n_boxes"], "levels": st["n_levels"], "pairs": st["pairs"]},
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -80,10 +80,12 @@ typedef struct {
   int64_t pairs[6];
   int64_t m2l_classes;      /* distinct M2L offsets in use (at most 1206) */
   double plan_seconds;      /* host tree + lists + matrices + upload */
-  /* stage times of the last gq_apply with GQ_FLAG_TIMING (ms, summed over densities):
+  /* With GQ_FLAG_TIMING: stage times (ms, HIP events on the apply stream) summed over all
+     gq_apply calls (and densities) since the previous gq_stats call, and their count:
      0 strength, 1 P2M, 2 M2M, 3 M2L, 4 P2L, 5 L2L, 6 P2QBXL, 7 M2QBXL, 8 L2QBXL,
      9 QBXL2P, 10 fill, 11 total */
   double stage_ms[12];
+  int64_t timed_applies;
 } gq_stats_t;
 
 /*
@@ -115,8 +117,9 @@ gq_status gq_plan_create(const gq_params* params, int64_t n_src, const double* s
  */
 gq_status gq_apply(gq_plan* plan, const double* density, double* potential, void* hip_stream);
 
-/* Copy plan statistics. */
-gq_status gq_stats(const gq_plan* plan, gq_stats_t* out);
+/* Copy plan statistics.  With GQ_FLAG_TIMING this waits for the timed applies, sums
+   their stage times into out->stage_ms and starts a new timing window. */
+gq_status gq_stats(gq_plan* plan, gq_stats_t* out);
 
 /* Release a plan (NULL is ignored).  Synchronizes with outstanding device work. */
 void gq_plan_destroy(gq_plan* plan);

@@ -50,7 +50,7 @@ class gq_stats_t(ctypes.Structure):
                 ("n_suspended_centers", ctypes.c_int64),
                 ("list_entries", ctypes.c_int64 * 6), ("pairs", ctypes.c_int64 * 6),
                 ("m2l_classes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
-                ("stage_ms", ctypes.c_double * 12)]
+                ("stage_ms", ctypes.c_double * 12), ("timed_applies", ctypes.c_int64)]
 
 
 class GQError(RuntimeError):
@@ -170,6 +170,7 @@ def gq_stats(plan):
         "pairs": dict(zip(LIST_INDEX, list(s.pairs))),
         "m2l_classes": s.m2l_classes, "plan_seconds": s.plan_seconds,
         "stage_ms": dict(zip(STAGES, list(s.stage_ms))),
+        "timed_applies": s.timed_applies,
     }
 
 

@@ -1,0 +1,96 @@
+"""Floating-point operation counts per interaction for each stage of the evaluation.
+
+Counts follow the arithmetic each kernel performs for one unit of work (a fused
+multiply-add counts 2, a division or square root counts 1).  They are used to turn
+measured kernel times into achieved FLOP/s; they are not used by the compute path.
+
+Units:
+  p2qbxl  one (source, center) pair of Lists 1, 3-close, 4-close (Stages 3, 5a, 6a)
+  m2qbxl  one (List 3-far box, center) pair (Stage 5b)
+  l2qbxl  one center (Stage 8)
+  translate  one dense (p+1)^2 x (p+1)^2 matrix-vector product (M2M, M2L, L2L)
+  qbxl2p  one target (Stage 9)
+"""
+
+from __future__ import annotations
+
+
+def p2qbxl_pair(q: int, kernel: str) -> int:
+    f = 3 + 5 + 1 + 1 + 1 + (1 if kernel == "S" else 0)  # d, |d|^2, 1/|d|^2, z/|d|^2, sqrt(, *q)
+    top = q if kernel == "S" else q + 1
+    for m in range(0, top + 1):
+        if m > 0:
+            f += 10  # diagonal: factor (4) and complex product (6)
+        for n in range(m, top + 1):
+            if n > m:
+                f += 5 if m == 0 else 8  # recurrence: c1, c2 and the 2-term update
+            if kernel == "S":
+                f += 1 if m == 0 else 2  # accumulate
+            else:
+                if n == 0:
+                    continue
+                nn = n - 1
+                if m <= nn:
+                    f += 2 if m == 0 else 4  # -n_z J -> l^m
+                if m == 1:
+                    f += 5  # 2 Re(qa J^1) -> l^0
+                elif m >= 2 and m - 1 <= nn:
+                    f += 8  # qa J -> l^(m-1)
+                if m + 1 <= nn:
+                    f += 4 if m == 0 else 8  # -conj(qa) J -> l^(m+1)
+    return f
+
+
+def _stream_macs(p: int, q: int, irregular: bool) -> int:
+    """Complex MAC flops of the order-q outputs fed by a streamed order-(p+q) (M2QBXL) or
+    order-p (L2QBXL) solid-harmonic table."""
+    f = 0
+    nt = p + q if irregular else p
+    for mo in range(0, nt + 1):
+        for N in range(mo, nt + 1):
+            for j in range(q + 1):
+                n = N - j if irregular else N + j
+                if n < 0 or n > p:
+                    continue
+                for k in range(j + 1):
+                    m1 = mo - k if irregular else mo + k
+                    if -n <= m1 <= n:
+                        f += 8 if k else 4
+                    if mo > 0:
+                        m2 = -mo - k if irregular else k - mo
+                        if -n <= m2 <= n:
+                            f += 8 if k else 4
+    return f
+
+
+def m2qbxl_pair(p: int, q: int) -> int:
+    nt = p + q
+    gen = 14 + 10 * nt + 8 * (nt * (nt + 1) // 2)
+    return gen + _stream_macs(p, q, True) + 2 * (q + 1) ** 2
+
+
+def l2qbxl_center(p: int, q: int) -> int:
+    gen = 14 + 10 * p + 9 * (p * (p + 1) // 2)
+    return gen + _stream_macs(p, q, False) + 2 * (q + 1) ** 2
+
+
+def translate(p: int) -> int:
+    n = (p + 1) ** 2
+    return 2 * n * n
+
+
+def qbxl2p_target(q: int) -> int:
+    return 8 + 10 * q + 9 * (q * (q + 1) // 2) + 4 * (q + 1) ** 2 + 1
+
+
+def apply_flops(stats: dict, p: int, q: int, kernel: str) -> dict:
+    """Executed-work model of one apply, per stage, from the plan's interaction counts."""
+    pr = stats["pairs"]
+    near = pr["U"] + pr["Wclose"] + pr["Xclose"]
+    return {
+        "p2qbxl": near * p2qbxl_pair(q, kernel),
+        "m2qbxl": pr["Wfar"] * m2qbxl_pair(p, q),
+        "m2l": pr["V"] * translate(p),
+        "l2qbxl": stats["n_centers"] * l2qbxl_center(p, q),
+        "qbxl2p": stats["n_targets"] * qbxl2p_target(q),
+    }

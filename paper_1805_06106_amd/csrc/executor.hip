@@ -55,12 +55,6 @@ void make_tiles(std::vector<std::array<int, 3>> pairs, TileSet& ts) {
   }
 }
 
-template <class T>
-struct DevArr {
-  T* p = nullptr;
-  size_t n = 0;
-};
-
 }  // namespace
 
 struct gq_plan {
@@ -109,12 +103,14 @@ struct gq_plan {
   int *d_k8_box = nullptr, *d_k8_c0 = nullptr, *d_k8_nc = nullptr;
   double *T_m2m = nullptr, *T_l2l = nullptr, *T_m2l = nullptr;
   double *q = nullptr, *M = nullptr, *L = nullptr, *Lq = nullptr;
-  hipEvent_t ev[13] = {};
-  bool have_events = false;
+  // per-stage timing: one event set per density pass, summed by gq_stats()
+  std::vector<std::array<hipEvent_t, 12>> ev_sets;
+  size_t ev_used = 0;
+  int64_t timed_applies = 0;
 
   ~gq_plan() {
-    if (have_events)
-      for (auto& e : ev) (void)hipEventDestroy(e);
+    for (auto& set : ev_sets)
+      for (auto& e : set) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -542,17 +538,21 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
   const int p = P->prm.p_fmm, qo = P->prm.p_qbx, np = P->np;
   const int kern = P->prm.kernel;
   const bool timing = (P->prm.flags & GQ_FLAG_TIMING) != 0;
-  if (timing && !P->have_events) {
-    for (auto& e : P->ev) GQ_HIP(hipEventCreate(&e));
-    P->have_events = true;
-  }
-  double stage_ms[12] = {0};
   gq::SrcSoA src{P->sx, P->sy, P->sz, P->snx, P->sny, P->snz};
+  hipEvent_t* ev = nullptr;
   auto mark = [&](int i) -> gq_status {
-    if (timing) GQ_HIP(hipEventRecord(P->ev[i], s));
+    if (timing) GQ_HIP(hipEventRecord(ev[i], s));
     return GQ_OK;
   };
   for (int d = 0; d < P->prm.n_densities; ++d) {
+    if (timing) {
+      if (P->ev_used == P->ev_sets.size()) {
+        std::array<hipEvent_t, 12> set{};
+        for (auto& e : set) GQ_HIP(hipEventCreate(&e));
+        P->ev_sets.push_back(set);
+      }
+      ev = P->ev_sets[P->ev_used++].data();
+    }
     GQ_TRY(mark(0));
     gq::launch_strength(s, P->n_src, P->src_order, P->sw, density + (int64_t)d * P->n_src, P->q);
     GQ_TRY(mark(1));
@@ -596,27 +596,34 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
                       P->Lq, P->n_ctr, P->tgt_out, potential + (int64_t)d * P->n_tgt);
     GQ_TRY(mark(11));
     GQ_HIP(hipGetLastError());
-    if (timing) {
-      GQ_HIP(hipEventSynchronize(P->ev[11]));
-      // map event intervals to the stage slots of gq_stats_t
-      const int slot[11] = {0, 10, 1, 2, 3, 4, 5, 6, 7, 8, 9};
-      for (int i = 0; i < 11; ++i) {
-        float ms = 0.f;
-        GQ_HIP(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
-        stage_ms[slot[i]] += ms;
-      }
-      float tot = 0.f;
-      GQ_HIP(hipEventElapsedTime(&tot, P->ev[0], P->ev[11]));
-      stage_ms[11] += tot;
-    }
   }
-  if (timing)
-    for (int i = 0; i < 12; ++i) P->stats.stage_ms[i] = stage_ms[i];
+  if (timing) P->timed_applies += 1;
   return GQ_OK;
 }
 
-gq_status gq_stats(const gq_plan* P, gq_stats_t* out) {
+gq_status gq_stats(gq_plan* P, gq_stats_t* out) {
   if (!P || !out) return fail(GQ_EINVAL, "NULL argument");
+  if (P->ev_used > 0) {
+    // sum the stage intervals of every density pass recorded since the last call
+    const int slot[11] = {0, 10, 1, 2, 3, 4, 5, 6, 7, 8, 9};
+    double ms[12] = {0};
+    GQ_HIP(hipEventSynchronize(P->ev_sets[P->ev_used - 1][11]));
+    for (size_t k = 0; k < P->ev_used; ++k) {
+      auto& e = P->ev_sets[k];
+      for (int i = 0; i < 11; ++i) {
+        float t = 0.f;
+        GQ_HIP(hipEventElapsedTime(&t, e[i], e[i + 1]));
+        ms[slot[i]] += t;
+      }
+      float tot = 0.f;
+      GQ_HIP(hipEventElapsedTime(&tot, e[0], e[11]));
+      ms[11] += tot;
+    }
+    for (int i = 0; i < 12; ++i) P->stats.stage_ms[i] = ms[i];
+    P->stats.timed_applies = P->timed_applies;
+    P->ev_used = 0;
+    P->timed_applies = 0;
+  }
   *out = P->stats;
   return GQ_OK;
 }
