@@ -66,6 +66,10 @@ typedef struct {
   int precision;     /* gq_precision */
   int n_densities;   /* densities evaluated per gq_apply, >= 1 */
   unsigned flags;    /* GQ_FLAG_* | GQ_LIST_* */
+  /* Remark 4 of Section 5.2.4: a List 3 far box whose subtree holds at most this many
+     sources is evaluated directly instead (its source leaves join List 3 close).  Exact
+     replacement of an approximated interaction by a direct one; 0 disables it. */
+  int wfar_direct_max;
 } gq_params;
 
 typedef struct gq_plan gq_plan; /* opaque */

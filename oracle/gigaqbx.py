@@ -22,6 +22,9 @@ library.  Readings taken where the paper is silent (each is listed in the design
     contribute nothing); leaf entries (Lists 1, 3close, 4) must own sources.
   * Targets associated with centers are evaluated only through their centers (Stage 9's
     second loop); a box is a target box when it owns at least one center.
+  * Remark 4 (optional, parameter wfar_direct_max, 0 = off): a List 3 far box whose
+    subtree holds at most that many sources is removed from List 3 far and its source
+    leaves are added to List 3 close.
 
 Numerical steps in the order of Algorithm 5 (all coefficients complex, paper form):
   Stage 2: multipole of every needed box.  M2M of an order-p multipole is exact for the
@@ -240,8 +243,9 @@ class OracleTree:
 class OracleLists:
     """Interaction lists of Section 5.2.3-5.2.4, evaluated lazily per box."""
 
-    def __init__(self, tree: OracleTree):
+    def __init__(self, tree: OracleTree, wfar_direct_max: int = 0):
         self.t = tree
+        self.wfar_direct_max = int(wfar_direct_max)
         self._cache = {}
 
     def _get(self, name, b, fn):
@@ -335,14 +339,26 @@ class OracleLists:
         return s
 
     def Wclose(self, b):
-        """List 3 close: source leaves in W_b or below that are not d < TCR(b)."""
+        """List 3 close: source leaves in W_b or below that are not d < TCR(b); with
+        Remark 4, also the source leaves of the small List 3 far boxes."""
         def f(b):
             t = self.t
-            return {d for d in self._w_closure(b)
-                    if t.is_leaf[d] and t.n_own_src[d] > 0 and not t.prec_tcr(d, b)}
+            out = {d for d in self._w_closure(b)
+                   if t.is_leaf[d] and t.n_own_src[d] > 0 and not t.prec_tcr(d, b)}
+            for d in self._wfar_def(b):
+                if self._moved(d):
+                    out |= {int(x) for x in t.subtree(d) if t.is_leaf[x] and t.n_own_src[x] > 0}
+            return out
         return self._get("Wclose", b, f)
 
+    def _moved(self, d):
+        return self.wfar_direct_max > 0 and self.t.sub_src[d] <= self.wfar_direct_max
+
     def Wfar(self, b):
+        """List 3 far (after Remark 4, if enabled)."""
+        return self._get("Wfar", b, lambda b: {d for d in self._wfar_def(b) if not self._moved(d)})
+
+    def _wfar_def(self, b):
         """List 3 far: d in W_b or below with d < TCR(b) and no such ancestor in that set."""
         def f(b):
             t = self.t
@@ -361,7 +377,7 @@ class OracleLists:
                 if ok:
                     out.add(d)
             return out
-        return self._get("Wfar", b, f)
+        return self._get("Wfar_def", b, f)
 
     def Xclose(self, b):
         """List 4 close: d in X_w for some w in anc(b) or b, with not TCR(b) < d."""
@@ -391,7 +407,8 @@ class OracleLists:
 class OracleFMM:
     """Tier B: GIGAQBX evaluation of the S or D layer potential."""
 
-    def __init__(self, w, nmax=None, tcf=None, p_fmm=None, p_qbx=None, nthreads=0):
+    def __init__(self, w, nmax=None, tcf=None, p_fmm=None, p_qbx=None, nthreads=0,
+                 wfar_direct_max=0):
         self.w = w
         self.kernel = w.kernel
         self.p = int(w.p_fmm if p_fmm is None else p_fmm)
@@ -400,7 +417,7 @@ class OracleFMM:
         self.tree = OracleTree(w.src_xyz, w.ctr_xyz, w.ctr_radius, w.tgt_xyz,
                                w.nmax if nmax is None else nmax,
                                w.tcf if tcf is None else tcf)
-        self.lists = OracleLists(self.tree)
+        self.lists = OracleLists(self.tree, wfar_direct_max)
         self._mpole = {}
 
     # --- expansions --------------------------------------------------------------------

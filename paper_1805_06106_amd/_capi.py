@@ -40,7 +40,8 @@ EXPORTED = ("gq_plan_create", "gq_apply", "gq_stats", "gq_plan_destroy", "gq_las
 class gq_params(ctypes.Structure):
     _fields_ = [("p_qbx", ctypes.c_int), ("p_fmm", ctypes.c_int), ("nmax", ctypes.c_int),
                 ("tcf", ctypes.c_double), ("kernel", ctypes.c_int), ("precision", ctypes.c_int),
-                ("n_densities", ctypes.c_int), ("flags", ctypes.c_uint)]
+                ("n_densities", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("wfar_direct_max", ctypes.c_int)]
 
 
 class gq_stats_t(ctypes.Structure):
@@ -128,13 +129,13 @@ def gq_last_error():
 
 
 def make_params(p_qbx, p_fmm, nmax=512, tcf=0.9, kernel="S", n_densities=1, flags=0,
-                lists=None):
+                lists=None, wfar_direct_max=0):
     k = {"S": GQ_KERNEL_S, "D": GQ_KERNEL_D}.get(kernel, kernel)
     if lists is not None:
         for nm in lists:
             flags |= LIST_BITS[nm]
     return gq_params(int(p_qbx), int(p_fmm), int(nmax), float(tcf), int(k), GQ_FP64,
-                     int(n_densities), int(flags))
+                     int(n_densities), int(flags), int(wfar_direct_max))
 
 
 def gq_plan_create(params, src_xyz, src_w, src_normal, ctr_xyz, ctr_radius, tgt_xyz,

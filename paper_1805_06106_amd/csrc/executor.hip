@@ -75,9 +75,8 @@ struct gq_plan {
   std::vector<int64_t> p2l_rptr, p2l_rbeg, p2l_rcnt;
   std::vector<int64_t> near_ptr, near_beg, near_cnt;  // box-indexed CSR of source ranges
   std::vector<int> k3_box, k3_c0, k3_nc;
-  std::vector<int64_t> wf_ptr;
   std::vector<int> wf_box;
-  std::vector<int> k5_box, k5_c0, k5_nc;
+  std::vector<int> k5_c0, k5_nc, k5_w0, k5_w1;
   std::vector<int> k8_box, k8_c0, k8_nc;
 
   // device memory
@@ -97,9 +96,8 @@ struct gq_plan {
   int64_t *d_p2l_rptr = nullptr, *d_p2l_rbeg = nullptr, *d_p2l_rcnt = nullptr;
   int64_t *d_near_ptr = nullptr, *d_near_beg = nullptr, *d_near_cnt = nullptr;
   int *d_k3_box = nullptr, *d_k3_c0 = nullptr, *d_k3_nc = nullptr;
-  int64_t* d_wf_ptr = nullptr;
   int* d_wf_box = nullptr;
-  int *d_k5_box = nullptr, *d_k5_c0 = nullptr, *d_k5_nc = nullptr;
+  int *d_k5_c0 = nullptr, *d_k5_nc = nullptr, *d_k5_w0 = nullptr, *d_k5_w1 = nullptr;
   int *d_k8_box = nullptr, *d_k8_c0 = nullptr, *d_k8_nc = nullptr;
   double *T_m2m = nullptr, *T_l2l = nullptr, *T_m2l = nullptr;
   double *q = nullptr, *M = nullptr, *L = nullptr, *Lq = nullptr;
@@ -261,7 +259,6 @@ gq_status build_work(gq_plan* P) {
   }
   // Stages 3, 5a, 6a (near sources), 5b (W-far), 8
   P->near_ptr.assign(nb + 1, 0);
-  P->wf_ptr.assign(nb + 1, 0);
   for (int b = 0; b < nb; ++b) {
     if (Ls.is_target[b]) {
       std::vector<std::pair<int64_t, int64_t>> r;
@@ -283,13 +280,22 @@ gq_status build_work(gq_plan* P) {
       if (!r.empty()) center_items(T, b, 256, P->k3_box, P->k3_c0, P->k3_nc);
       if (on(GQ_LIST_WFAR)) {
         const auto& W = Ls.lst[gq::L_WFAR];
+        const int w0 = (int)P->wf_box.size();
         for (int64_t k = W.ptr[b]; k < W.ptr[b + 1]; ++k) P->wf_box.push_back(W.items[k]);
-        if (W.size(b) > 0) center_items(T, b, 64, P->k5_box, P->k5_c0, P->k5_nc);
+        const int w1 = (int)P->wf_box.size();
+        // (center chunk of <= 64) x (W-far chunk of <= kWfarChunk boxes) items
+        const int kWfarChunk = 4;
+        for (int64_t o = 0; o < T.ctr_count[b]; o += 64)
+          for (int ws = w0; ws < w1; ws += kWfarChunk) {
+            P->k5_c0.push_back((int)(T.ctr_start[b] + o));
+            P->k5_nc.push_back((int)std::min<int64_t>(64, T.ctr_count[b] - o));
+            P->k5_w0.push_back(ws);
+            P->k5_w1.push_back(std::min(w1, ws + kWfarChunk));
+          }
       }
       center_items(T, b, 64, P->k8_box, P->k8_c0, P->k8_nc);
     }
     P->near_ptr[b + 1] = (int64_t)P->near_beg.size();
-    P->wf_ptr[b + 1] = (int64_t)P->wf_box.size();
   }
   P->stats.m2l_classes = (int64_t)cls_keys.size();
   // statistics
@@ -359,11 +365,11 @@ gq_status build_work(gq_plan* P) {
   GQ_TRY(upload(P, P->k3_box, &P->d_k3_box, s));
   GQ_TRY(upload(P, P->k3_c0, &P->d_k3_c0, s));
   GQ_TRY(upload(P, P->k3_nc, &P->d_k3_nc, s));
-  GQ_TRY(upload(P, P->wf_ptr, &P->d_wf_ptr, s));
   GQ_TRY(upload(P, P->wf_box, &P->d_wf_box, s));
-  GQ_TRY(upload(P, P->k5_box, &P->d_k5_box, s));
   GQ_TRY(upload(P, P->k5_c0, &P->d_k5_c0, s));
   GQ_TRY(upload(P, P->k5_nc, &P->d_k5_nc, s));
+  GQ_TRY(upload(P, P->k5_w0, &P->d_k5_w0, s));
+  GQ_TRY(upload(P, P->k5_w1, &P->d_k5_w1, s));
   GQ_TRY(upload(P, P->k8_box, &P->d_k8_box, s));
   GQ_TRY(upload(P, P->k8_c0, &P->d_k8_c0, s));
   GQ_TRY(upload(P, P->k8_nc, &P->d_k8_nc, s));
@@ -400,6 +406,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     return fail(GQ_EINVAL, "unknown kernel");
   if (prm->precision != GQ_FP64) return fail(GQ_EUNSUPPORTED, "only GQ_FP64 is available");
   if (prm->n_densities < 1) return fail(GQ_EINVAL, "n_densities must be >= 1");
+  if (prm->wfar_direct_max < 0) return fail(GQ_EINVAL, "wfar_direct_max must be >= 0");
   if (prm->kernel == GQ_KERNEL_D && !src_normal) return fail(GQ_EINVAL, "double layer needs normals");
   if (!finite3(src_xyz, n_src) || !finite3(ctr_xyz, n_ctr) || !finite3(tgt_xyz, n_tgt))
     return fail(GQ_EINVAL, "non-finite coordinates");
@@ -436,7 +443,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     delete P;
     return fail(GQ_EINVAL, msg);
   }
-  gq::build_lists(P->tree, prm->tcf, P->lists);
+  gq::build_lists(P->tree, prm->tcf, prm->wfar_direct_max, P->lists);
   P->stats.n_sources = n_src;
   P->stats.n_centers = n_ctr;
   P->stats.n_targets = n_tgt;
@@ -585,8 +592,8 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
                       P->d_near_ptr, P->d_near_beg, P->d_near_cnt, src, P->q, P->cx, P->cy,
                       P->cz, P->Lq, P->n_ctr);
     GQ_TRY(mark(8));
-    gq::launch_m2qbxl(s, p, qo, (int)P->k5_box.size(), P->d_k5_box, P->d_k5_c0, P->d_k5_nc,
-                      P->d_wf_ptr, P->d_wf_box, P->bctr, P->bh, P->M, P->cx, P->cy, P->cz,
+    gq::launch_m2qbxl(s, p, qo, (int)P->k5_c0.size(), P->d_k5_c0, P->d_k5_nc, P->d_k5_w0,
+                      P->d_k5_w1, P->d_wf_box, P->bctr, P->bh, P->M, P->cx, P->cy, P->cz,
                       P->Lq, P->n_ctr);
     GQ_TRY(mark(9));
     gq::launch_l2qbxl(s, p, qo, (int)P->k8_box.size(), P->d_k8_box, P->d_k8_c0, P->d_k8_nc,

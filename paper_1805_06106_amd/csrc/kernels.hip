@@ -289,9 +289,19 @@ __global__ __launch_bounds__(256) void k_p2l(int P, const int* __restrict__ boxe
 }
 
 // ------------------------------------------------------------------------------------
-// Batched dense translation Y[dst] += T[cls] X[src]; one tile = up to kTileCols pairs of
-// one class.  T column-major (np x np).  VALU FP64; each thread owns output rows.
+// Batched dense translation on the FP64 matrix cores: for each tile (up to kTileCols = 64
+// pairs of one matrix class) Y[dst_c] += T X[src_c], T column-major np x np.
+// v_mfma_f64_16x16x4f64: D(16x16) += A(16x4) B(4x16); lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and holds D[l/16 + 4r][l%16], r = 0..3 (register r, lane l).
+// M = matrix rows, N = pairs, K = input coefficients.  A block (4 waves) walks the rows in
+// rounds of 16 row-blocks; wave w owns row-blocks w, w+4, w+8, w+12 of the round and all 4
+// column blocks (16 accumulator tiles), so each matrix element is read once per tile.  The
+// input expansions are staged in LDS in chunks of kKc coefficients; outputs are added
+// atomically (several classes can target one box).
 // ------------------------------------------------------------------------------------
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int kKc = 64;
 
 __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict__ tile_cls,
                                                    const int* __restrict__ tile_beg,
@@ -301,25 +311,62 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
                                                    const double* __restrict__ T,
                                                    const double* __restrict__ X,
                                                    double* __restrict__ Y) {
-  extern __shared__ double xs[];  // [np][kTileCols]
+  __shared__ double xs[kKc * kTileCols];  // [k][col]
   const int t = blockIdx.x;
   const int cls = tile_cls[t], beg = tile_beg[t], cnt = tile_cnt[t];
-  for (int i = threadIdx.x; i < np * kTileCols; i += blockDim.x) {
-    const int c = i / np, k = i - c * np;
-    xs[k * kTileCols + c] = c < cnt ? X[(int64_t)pair_src[beg + c] * np + k] : 0.0;
-  }
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const double* Tc = T + (int64_t)cls * np * np;
-  for (int row = threadIdx.x; row < np; row += blockDim.x) {
-    double acc[kTileCols];
+  const int nrb = (np + 15) >> 4;
+  for (int r0 = 0; r0 < nrb; r0 += 16) {
+    d4_t acc[4][4];
 #pragma unroll
-    for (int c = 0; c < kTileCols; ++c) acc[c] = 0.0;
-    for (int k = 0; k < np; ++k) {
-      const double a = Tc[(int64_t)k * np + row];
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int c = 0; c < kTileCols; ++c) acc[c] = fma(a, xs[k * kTileCols + c], acc[c]);
+      for (int cb = 0; cb < 4; ++cb) acc[i][cb] = (d4_t){0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < np; kc += kKc) {
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < kKc * kTileCols; idx += 256) {
+        const int col = idx / kKc, kk = idx - col * kKc;
+        const int k = kc + kk;
+        xs[kk * kTileCols + col] =
+            (col < cnt && k < np) ? X[(int64_t)pair_src[beg + col] * np + k] : 0.0;
+      }
+      __syncthreads();
+      const int kend = min(kKc, np - kc);
+#pragma unroll 2
+      for (int k0 = 0; k0 < kend; k0 += 4) {
+        const int k = kc + k0 + lk;
+        double b[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) b[cb] = xs[(k0 + lk) * kTileCols + cb * 16 + li];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rb = r0 + wave + 4 * i;
+          const int row = rb * 16 + li;
+          const double a = (rb < nrb && row < np && k < np) ? Tc[(int64_t)k * np + row] : 0.0;
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[cb], acc[i][cb], 0, 0, 0);
+        }
+      }
     }
-    for (int c = 0; c < cnt; ++c) atomicAdd(&Y[(int64_t)pair_dst[beg + c] * np + row], acc[c]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rb = r0 + wave + 4 * i;
+      if (rb >= nrb) continue;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int col = cb * 16 + li;
+        if (col >= cnt) continue;
+        double* y = Y + (int64_t)pair_dst[beg + col] * np;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb * 16 + lk + 4 * r;
+          if (row < np) unsafeAtomicAdd(&y[row], acc[i][cb][r]);
+        }
+      }
+    }
   }
 }
 
@@ -330,16 +377,20 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
 template <int Q>
 __device__ __forceinline__ void p2qbxl_single(double dx, double dy, double dz, double qq,
                                               double (&acc)[(Q + 1) * (Q + 1)]) {
-  const double r2 = dx * dx + dy * dy + dz * dz;
+  // l_n^m += q J_n^m(s - c), J = conj(I): columns of fixed order m, increasing degree n
+  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
   const double ir2 = 1.0 / r2;
   const double zr = dz * ir2;
-  // running diagonal q J_m^m, J = conj(I)
+  double zk[Q + 2];  // (2k - 1) z / r^2
+#pragma unroll
+  for (int k = 1; k <= Q + 1; ++k) zk[k] = (2.0 * k - 1.0) * zr;
+  const double xr = dx * ir2, yr = dy * ir2;
   double dr = qq * sqrt(ir2), di = 0.0;
 #pragma unroll
   for (int m = 0; m <= Q; ++m) {
-    if (m > 0) {
-      const double fr = -(2.0 * m - 1.0) * dx * ir2, fi = (2.0 * m - 1.0) * dy * ir2;
-      const double nr = dr * fr - di * fi, ni = dr * fi + di * fr;
+    if (m > 0) {  // J_m^m = -(2m-1)(x - i y)/r^2 J_{m-1}^{m-1}
+      const double fr = -(2.0 * m - 1.0) * xr, fi = (2.0 * m - 1.0) * yr;
+      const double nr = fma(dr, fr, -di * fi), ni = fma(dr, fi, di * fr);
       dr = nr;
       di = ni;
     }
@@ -348,16 +399,17 @@ __device__ __forceinline__ void p2qbxl_single(double dx, double dy, double dz, d
     double p1r = dr, p1i = di, p2r = 0.0, p2i = 0.0;
 #pragma unroll
     for (int n = m + 1; n <= Q; ++n) {
-      const double c1 = (2.0 * n - 1.0) * zr;
       const double c2 = (double)((n - 1) * (n - 1) - m * m) * ir2;
-      const double cr = c1 * p1r - c2 * p2r;
-      const double ci = c1 * p1i - c2 * p2i;
+      const double cr = fma(zk[n], p1r, -c2 * p2r);
       acc[cpk_re(n, m)] += cr;
-      if (m) acc[cpk_im(n, m)] += ci;
       p2r = p1r;
-      p2i = p1i;
       p1r = cr;
-      p1i = ci;
+      if (m) {
+        const double ci = fma(zk[n], p1i, -c2 * p2i);
+        acc[cpk_im(n, m)] += ci;
+        p2i = p1i;
+        p1i = ci;
+      }
     }
   }
 }
@@ -366,17 +418,21 @@ template <int Q>
 __device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz, double qz,
                                               double qxh, double qyh,
                                               double (&acc)[(Q + 1) * (Q + 1)]) {
-  // l_n^m += -qz J_{n+1}^m + (qx+i qy)/2 J_{n+1}^{m+1} - (qx-i qy)/2 J_{n+1}^{m-1},
-  // scattered from each J_N^M (N = n+1 <= Q+1) to the outputs it feeds.
-  const double r2 = dx * dx + dy * dy + dz * dz;
+  // l_n^m += -qz J_{n+1}^m + qa J_{n+1}^{m+1} - conj(qa) J_{n+1}^{m-1}, qa = (qx + i qy)/2,
+  // scattered from each J_N^M (N = n+1 <= Q+1) into the outputs it feeds, as FMA chains.
+  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
   const double ir2 = 1.0 / r2;
   const double zr = dz * ir2;
+  double zk[Q + 3];
+#pragma unroll
+  for (int k = 1; k <= Q + 1; ++k) zk[k] = (2.0 * k - 1.0) * zr;
+  const double xr = dx * ir2, yr = dy * ir2;
   double dr = sqrt(ir2), di = 0.0;
 #pragma unroll
   for (int M = 0; M <= Q + 1; ++M) {
     if (M > 0) {
-      const double fr = -(2.0 * M - 1.0) * dx * ir2, fi = (2.0 * M - 1.0) * dy * ir2;
-      const double nr = dr * fr - di * fi, ni = dr * fi + di * fr;
+      const double fr = -(2.0 * M - 1.0) * xr, fi = (2.0 * M - 1.0) * yr;
+      const double nr = fma(dr, fr, -di * fi), ni = fma(dr, fi, di * fr);
       dr = nr;
       di = ni;
     }
@@ -388,26 +444,25 @@ __device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz, d
         jr = dr;
         ji = di;
       } else {
-        const double c1 = (2.0 * N - 1.0) * zr;
         const double c2 = (double)((N - 1) * (N - 1) - M * M) * ir2;
-        jr = c1 * p1r - c2 * p2r;
-        ji = c1 * p1i - c2 * p2i;
+        jr = fma(zk[N], p1r, -c2 * p2r);
+        ji = M ? fma(zk[N], p1i, -c2 * p2i) : 0.0;
       }
       if (N >= 1) {
         const int n = N - 1;
         if (M <= n) {  // -qz J_N^M -> l_n^M
-          acc[cpk_re(n, M)] -= qz * jr;
-          if (M) acc[cpk_im(n, M)] -= qz * ji;
+          acc[cpk_re(n, M)] = fma(-qz, jr, acc[cpk_re(n, M)]);
+          if (M) acc[cpk_im(n, M)] = fma(-qz, ji, acc[cpk_im(n, M)]);
         }
-        if (M == 1) {  // (qa J^1 + conj(qa J^1)) -> l_n^0
-          acc[cpk_re(n, 0)] += 2.0 * (qxh * jr - qyh * ji);
+        if (M == 1) {  // qa J^1 + conj(qa J^1) -> l_n^0
+          acc[cpk_re(n, 0)] = fma(2.0 * qxh, jr, fma(-2.0 * qyh, ji, acc[cpk_re(n, 0)]));
         } else if (M >= 2 && M - 1 <= n) {  // qa J_N^M -> l_n^{M-1}
-          acc[cpk_re(n, M - 1)] += qxh * jr - qyh * ji;
-          acc[cpk_im(n, M - 1)] += qxh * ji + qyh * jr;
+          acc[cpk_re(n, M - 1)] = fma(qxh, jr, fma(-qyh, ji, acc[cpk_re(n, M - 1)]));
+          acc[cpk_im(n, M - 1)] = fma(qxh, ji, fma(qyh, jr, acc[cpk_im(n, M - 1)]));
         }
         if (M + 1 <= n) {  // -conj(qa) J_N^M -> l_n^{M+1}
-          acc[cpk_re(n, M + 1)] -= qxh * jr + qyh * ji;
-          acc[cpk_im(n, M + 1)] -= qxh * ji - qyh * jr;
+          acc[cpk_re(n, M + 1)] = fma(-qxh, jr, fma(-qyh, ji, acc[cpk_re(n, M + 1)]));
+          acc[cpk_im(n, M + 1)] = fma(-qxh, ji, fma(qyh, jr, acc[cpk_im(n, M + 1)]));
         }
       }
       if (N == M) {
@@ -508,45 +563,79 @@ __global__ __launch_bounds__(256) void k_p2qbxl(const int* __restrict__ it_box,
 }
 
 // ------------------------------------------------------------------------------------
-// M2QBXL and L2QBXL: one thread per center; the (box) expansion is expanded to all
-// signed orders in LDS; J (resp. R) is generated column by column (fixed order M,
-// increasing degree N) and scattered into the order-Q outputs it feeds.
+// M2QBXL and L2QBXL: one thread per center.  The box expansion is rescaled to its
+// physical (unscaled) form and expanded to all signed orders in a zero-padded LDS table of
+// complex pairs; the solid harmonics of the center offset are generated column by column
+// (fixed order M, increasing degree N) and each value is scattered into the order-Q
+// outputs it feeds.  Table addresses are a per-(M, N) base plus a compile-time offset per
+// output (j, k); entries outside |m| <= n <= P read zeros, so the inner body is
+// branch-free apart from one uniform degree check per j.
 // ------------------------------------------------------------------------------------
 
-constexpr int kFull = (kPmax + 1) * (kPmax + 1);
+// M2QBXL: l_j^k(c) = sum_{n,m} [(-1)^n mu_n^m] [(-1)^N J_N^{m+k}(c - x_d)], N = n + j
+// (mu unscaled multipole, J = conj(I)); padded table rows n + Q, columns m + MOFF.
+template <int Q, int PT>
+struct M2qTab {
+  static constexpr int MOFF = PT + 2 * Q;
+  static constexpr int W = 2 * PT + 3 * Q + 1;
+  static constexpr int ROWS = PT + 2 * Q + 1;
+};
 
-__device__ __forceinline__ void stage_full(const double* __restrict__ e, int P, double* fr,
-                                           double* fi) {
-  // e: real-packed; fr/fi[cidx(n, m)] for |m| <= n, using c^-m = (-1)^m conj(c^m)
+// L2QBXL: l_j^k(c) = sum_{n,m} l_n^m R_{n-j}^{m-k}(c - x_b) (l unscaled box local);
+// padded table rows n, columns m + MOFF.
+template <int Q>
+struct L2qTab {
+  static constexpr int MOFF = kPmax;
+  static constexpr int W = 2 * kPmax + Q + 1;
+  static constexpr int ROWS = kPmax + Q + 1;
+};
+
+// Fill the nonzero part (n <= P, |m| <= n) of a padded table from a real-packed scaled
+// expansion e, multiplying degree n by scale(n).  c^-m = (-1)^m conj(c^m).
+template <class F>
+__device__ __forceinline__ void fill_padded(const double* __restrict__ e, int P, double2* tab,
+                                            int row0, int W, int moff, F scale) {
   const int np = (P + 1) * (P + 1);
+  double* t = reinterpret_cast<double*>(tab);
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
     int n = (int)sqrt((double)i);
     while (n * n > i) --n;
     while ((n + 1) * (n + 1) <= i) ++n;
     const int off = i - n * n;
+    const double v = e[i] * scale(n);
+    const int row = (row0 + n) * W + moff;
     if (off == 0) {
-      fr[cidx(n, 0)] = e[i];
-      fi[cidx(n, 0)] = 0.0;
+      t[2 * row] = v;
+      t[2 * row + 1] = 0.0;
     } else {
       const int m = (off + 1) >> 1;
+      const double sg = (m & 1) ? -1.0 : 1.0;
       if (off & 1) {  // real part
-        const double v = e[i];
-        fr[cidx(n, m)] = v;
-        fr[cidx(n, -m)] = (m & 1) ? -v : v;
-      } else {
-        const double v = e[i];
-        fi[cidx(n, m)] = v;
-        fi[cidx(n, -m)] = (m & 1) ? v : -v;
+        t[2 * (row + m)] = v;
+        t[2 * (row - m)] = sg * v;
+      } else {  // imaginary part
+        t[2 * (row + m) + 1] = v;
+        t[2 * (row - m) + 1] = -sg * v;
       }
     }
   }
 }
 
 template <int Q>
-__global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it_box,
-                                               const int* __restrict__ it_c0,
+__device__ __forceinline__ void cmac(double (&acc)[(Q + 1) * (Q + 1)], int j, int k, double2 a,
+                                     double br, double bi) {
+  acc[cpk_re(j, k)] = fma(a.x, br, fma(-a.y, bi, acc[cpk_re(j, k)]));
+  if (k) acc[cpk_im(j, k)] = fma(a.x, bi, fma(a.y, br, acc[cpk_im(j, k)]));
+}
+
+// Item i: centers [it_c0, it_c0 + it_nc) of one target box and the List 3 far boxes
+// wf_box[it_w0 .. it_w1); long lists are split over several items, so the outputs are
+// added atomically.
+template <int Q, int PT>
+__global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it_c0,
                                                const int* __restrict__ it_nc,
-                                               const int64_t* __restrict__ wf_ptr,
+                                               const int* __restrict__ it_w0,
+                                               const int* __restrict__ it_w1,
                                                const int* __restrict__ wf_box,
                                                const double* __restrict__ bctr,
                                                const double* __restrict__ bh,
@@ -555,10 +644,11 @@ __global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it
                                                const double* __restrict__ cy,
                                                const double* __restrict__ cz,
                                                double* __restrict__ Lq, int64_t nctr) {
+  using TB = M2qTab<Q, PT>;
   constexpr int NQ = (Q + 1) * (Q + 1);
-  __shared__ double mr[kFull], mi[kFull];
+  __shared__ double2 tab[TB::ROWS * TB::W];
+  for (int i = threadIdx.x; i < TB::ROWS * TB::W; i += blockDim.x) tab[i] = make_double2(0.0, 0.0);
   const int item = blockIdx.x;
-  const int b = it_box[item];
   const int c0 = it_c0[item], nc = it_nc[item];
   const bool active = (int)threadIdx.x < nc;
   const int64_t c = (int64_t)c0 + (active ? threadIdx.x : 0);
@@ -568,22 +658,21 @@ __global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it
   double acc[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
-  for (int64_t w = wf_ptr[b]; w < wf_ptr[b + 1]; ++w) {
+  for (int w = it_w0[item]; w < it_w1[item]; ++w) {
     const int d = wf_box[w];
+    const double a = bh[d];
     __syncthreads();
-    stage_full(M + (int64_t)d * np, P, mr, mi);
+    fill_padded(M + (int64_t)d * np, P, tab, Q, TB::W, TB::MOFF,
+                [a](int n) { return (n & 1) ? -pow(a, (double)n) : pow(a, (double)n); });
     __syncthreads();
-    const double a = bh[d], inv_a = 1.0 / a;
-    const double ux = (xc - bctr[3 * d]) * inv_a, uy = (yc - bctr[3 * d + 1]) * inv_a,
-                 uz = (zc - bctr[3 * d + 2]) * inv_a;
-    const double r2 = ux * ux + uy * uy + uz * uz, ir2 = 1.0 / r2, zr = uz * ir2;
-    double t[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) t[i] = 0.0;
+    const double vx = xc - bctr[3 * d], vy = yc - bctr[3 * d + 1], vz = zc - bctr[3 * d + 2];
+    const double ir2 = 1.0 / (vx * vx + vy * vy + vz * vz), zr = vz * ir2;
+    // J'_N^M = (-1)^N conj(I_N^M)(v), generated for fixed M with increasing N
     double dr = sqrt(ir2), di = 0.0;
     for (int Mo = 0; Mo <= NT; ++Mo) {
       if (Mo > 0) {
-        const double fr = -(2.0 * Mo - 1.0) * ux * ir2, fi = (2.0 * Mo - 1.0) * uy * ir2;
+        const double f = (2.0 * Mo - 1.0) * ir2;
+        const double fr = f * vx, fi = -f * vy;
         const double nr = dr * fr - di * fi, ni = dr * fi + di * fr;
         dr = nr;
         di = ni;
@@ -598,55 +687,35 @@ __global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it
         } else {
           const double c1 = (2.0 * N - 1.0) * zr;
           const double c2 = (double)((N - 1) * (N - 1) - Mo * Mo) * ir2;
-          jr = c1 * p1r - c2 * p2r;
-          ji = c1 * p1i - c2 * p2i;
+          jr = -c1 * p1r - c2 * p2r;
+          ji = -c1 * p1i - c2 * p2i;
           p2r = p1r;
           p2i = p1i;
         }
         p1r = jr;
         p1i = ji;
-        // l_j^k += mu~_n^m J_N^{m+k}, n = N - j: m = Mo - k and m = -Mo - k (J^-Mo)
+        const double jnr = sgn * jr, jni = -sgn * ji;  // J'^{-M} = (-1)^M conj(J'^M)
+        const double2* t1 = tab + (N * TB::W + Mo + TB::MOFF);
+        const double2* t2 = tab + (N * TB::W - Mo + TB::MOFF);
 #pragma unroll
         for (int j = 0; j <= Q; ++j) {
           const int n = N - j;
-          if (n < 0 || n > P) continue;
+          if (n < 0 || n > P) continue;  // uniform
+          if (Mo - j <= n) {
 #pragma unroll
-          for (int k = 0; k <= j; ++k) {
-            const int m1 = Mo - k;
-            if (m1 >= -n && m1 <= n) {
-              const double ar = mr[cidx(n, m1)], ai = mi[cidx(n, m1)];
-              t[cpk_re(j, k)] += ar * jr - ai * ji;
-              if (k) t[cpk_im(j, k)] += ar * ji + ai * jr;
-            }
-            if (Mo > 0) {
-              const int m2 = -Mo - k;
-              if (m2 >= -n) {
-                const double ar = mr[cidx(n, m2)], ai = mi[cidx(n, m2)];
-                // (-1)^Mo conj(J)
-                t[cpk_re(j, k)] += sgn * (ar * jr + ai * ji);
-                if (k) t[cpk_im(j, k)] += sgn * (ai * jr - ar * ji);
-              }
-            }
+            for (int k = 0; k <= j; ++k) cmac<Q>(acc, j, k, t1[(Q - j) * TB::W - k], jr, ji);
+          }
+          if (Mo > 0 && Mo <= n) {
+#pragma unroll
+            for (int k = 0; k <= j; ++k) cmac<Q>(acc, j, k, t2[(Q - j) * TB::W - k], jnr, jni);
           }
         }
       }
     }
-    // scale (-1)^j a^-(j+1)
-    double s = inv_a;
-#pragma unroll
-    for (int j = 0; j <= Q; ++j) {
-      const double f = (j & 1) ? -s : s;
-#pragma unroll
-      for (int k = 0; k <= j; ++k) {
-        acc[cpk_re(j, k)] += f * t[cpk_re(j, k)];
-        if (k) acc[cpk_im(j, k)] += f * t[cpk_im(j, k)];
-      }
-      s *= inv_a;
-    }
   }
   if (active)
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
+    for (int i = 0; i < NQ; ++i) unsafeAtomicAdd(&Lq[(int64_t)i * nctr + c], acc[i]);
 }
 
 template <int Q>
@@ -660,30 +729,33 @@ __global__ __launch_bounds__(64) void k_l2qbxl(int P, const int* __restrict__ it
                                                const double* __restrict__ cy,
                                                const double* __restrict__ cz,
                                                double* __restrict__ Lq, int64_t nctr) {
+  using TB = L2qTab<Q>;
   constexpr int NQ = (Q + 1) * (Q + 1);
-  __shared__ double lr[kFull], li[kFull];
+  __shared__ double2 tab[TB::ROWS * TB::W];
   __shared__ double invtab[kInvTab * kInvTab];
+  for (int i = threadIdx.x; i < TB::ROWS * TB::W; i += blockDim.x) tab[i] = make_double2(0.0, 0.0);
+  fill_invtab(invtab);
   const int item = blockIdx.x;
   const int b = it_box[item];
   const int c0 = it_c0[item], nc = it_nc[item];
   const bool active = (int)threadIdx.x < nc;
   const int64_t c = (int64_t)c0 + (active ? threadIdx.x : 0);
   const int np = (P + 1) * (P + 1);
-  fill_invtab(invtab);
-  stage_full(L + (int64_t)b * np, P, lr, li);
+  const double a = bh[b];
   __syncthreads();
-  const double a = bh[b], inv_a = 1.0 / a;
-  const double ux = (cx[c] - bctr[3 * b]) * inv_a, uy = (cy[c] - bctr[3 * b + 1]) * inv_a,
-               uz = (cz[c] - bctr[3 * b + 2]) * inv_a;
-  const double r2 = ux * ux + uy * uy + uz * uz;
-  double t[NQ];
+  fill_padded(L + (int64_t)b * np, P, tab, 0, TB::W, TB::MOFF,
+              [a](int n) { return pow(a, -(double)(n + 1)); });
+  __syncthreads();
+  const double vx = cx[c] - bctr[3 * b], vy = cy[c] - bctr[3 * b + 1], vz = cz[c] - bctr[3 * b + 2];
+  const double r2 = vx * vx + vy * vy + vz * vz;
+  double acc[NQ];
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) t[i] = 0.0;
+  for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
   double dr = 1.0, di = 0.0;
   for (int mu = 0; mu <= P; ++mu) {
     if (mu > 0) {
       const double f = -0.5 / mu;
-      const double nr = f * (dr * ux - di * uy), ni = f * (dr * uy + di * ux);
+      const double nr = f * (dr * vx - di * vy), ni = f * (dr * vy + di * vx);
       dr = nr;
       di = ni;
     }
@@ -694,14 +766,9 @@ __global__ __launch_bounds__(64) void k_l2qbxl(int P, const int* __restrict__ it
       if (N == mu) {
         rr = dr;
         ri = di;
-      } else if (N == mu + 1) {
-        rr = uz * p1r;
-        ri = uz * p1i;
-        p2r = p1r;
-        p2i = p1i;
       } else {
         const double tt = invtab[N * kInvTab + mu];
-        const double c1 = (2.0 * N - 1.0) * uz;
+        const double c1 = (2.0 * N - 1.0) * vz;
         rr = (c1 * p1r - r2 * p2r) * tt;
         ri = (c1 * p1i - r2 * p2i) * tt;
         p2r = p1r;
@@ -709,42 +776,27 @@ __global__ __launch_bounds__(64) void k_l2qbxl(int P, const int* __restrict__ it
       }
       p1r = rr;
       p1i = ri;
-      // l_j^k += l~_n^m R_N^{m-k}, n = N + j: m = mu + k and m = -mu + k (R^-mu)
+      const double rnr = sgn * rr, rni = -sgn * ri;  // R^{-mu} = (-1)^mu conj(R^mu)
+      const double2* t1 = tab + (N * TB::W + mu + TB::MOFF);
+      const double2* t2 = tab + (N * TB::W - mu + TB::MOFF);
 #pragma unroll
       for (int j = 0; j <= Q; ++j) {
         const int n = N + j;
-        if (n > P) continue;
+        if (n > P) continue;  // uniform
+        if (mu <= n) {
 #pragma unroll
-        for (int k = 0; k <= j; ++k) {
-          const int m1 = mu + k;
-          if (m1 <= n) {
-            const double ar = lr[cidx(n, m1)], ai = li[cidx(n, m1)];
-            t[cpk_re(j, k)] += ar * rr - ai * ri;
-            if (k) t[cpk_im(j, k)] += ar * ri + ai * rr;
-          }
-          if (mu > 0) {
-            const int m2 = k - mu;
-            if (m2 >= -n) {
-              const double ar = lr[cidx(n, m2)], ai = li[cidx(n, m2)];
-              t[cpk_re(j, k)] += sgn * (ar * rr + ai * ri);
-              if (k) t[cpk_im(j, k)] += sgn * (ai * rr - ar * ri);
-            }
-          }
+          for (int k = 0; k <= j; ++k) cmac<Q>(acc, j, k, t1[j * TB::W + k], rr, ri);
+        }
+        if (mu > 0 && mu - j <= n) {
+#pragma unroll
+          for (int k = 0; k <= j; ++k) cmac<Q>(acc, j, k, t2[j * TB::W + k], rnr, rni);
         }
       }
     }
   }
   if (!active) return;
-  double s = inv_a;
 #pragma unroll
-  for (int j = 0; j <= Q; ++j) {
-#pragma unroll
-    for (int k = 0; k <= j; ++k) {
-      Lq[(int64_t)cpk_re(j, k) * nctr + c] += s * t[cpk_re(j, k)];
-      if (k) Lq[(int64_t)cpk_im(j, k) * nctr + c] += s * t[cpk_im(j, k)];
-    }
-    s *= inv_a;
-  }
+  for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
 }
 
 // ------------------------------------------------------------------------------------
@@ -838,12 +890,23 @@ struct P2qbxlGo {
 
 template <int Q>
 struct M2qbxlGo {
-  static void go(hipStream_t s, int p, int nitem, const int* it_box, const int* it_c0,
-                 const int* it_nc, const int64_t* wf_ptr, const int* wf_box,
-                 const double* bctr, const double* bh, const double* M, const double* cx,
-                 const double* cy, const double* cz, double* Lq, int64_t nctr) {
-    k_m2qbxl<Q><<<nitem, 64, 0, s>>>(p, it_box, it_c0, it_nc, wf_ptr, wf_box, bctr, bh, M, cx,
-                                     cy, cz, Lq, nctr);
+  static void go(hipStream_t s, int p, int nitem, const int* it_c0, const int* it_nc,
+                 const int* it_w0, const int* it_w1, const int* wf_box, const double* bctr,
+                 const double* bh, const double* M, const double* cx, const double* cy,
+                 const double* cz, double* Lq, int64_t nctr) {
+    // smallest compiled table bound covering p
+    if (p <= 8)
+      k_m2qbxl<Q, 8><<<nitem, 64, 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
+                                          cx, cy, cz, Lq, nctr);
+    else if (p <= 12)
+      k_m2qbxl<Q, 12><<<nitem, 64, 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
+                                           cx, cy, cz, Lq, nctr);
+    else if (p <= 16)
+      k_m2qbxl<Q, 16><<<nitem, 64, 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
+                                           cx, cy, cz, Lq, nctr);
+    else
+      k_m2qbxl<Q, kPmax><<<nitem, 64, 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh,
+                                              M, cx, cy, cz, Lq, nctr);
   }
 };
 
@@ -907,9 +970,8 @@ void launch_translate(hipStream_t s, int np, int ntile, const int* tile_cls,
                       const int* tile_beg, const int* tile_cnt, const int* pair_src,
                       const int* pair_dst, const double* T, const double* X, double* Y) {
   if (ntile <= 0) return;
-  size_t lds = (size_t)np * kTileCols * sizeof(double);
-  k_translate<<<ntile, 256, lds, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T,
-                                      X, Y);
+  k_translate<<<ntile, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T, X,
+                                    Y);
 }
 
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
@@ -922,14 +984,13 @@ void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_bo
                            rng_cnt, src, qs, cx, cy, cz, Lq, nctr);
 }
 
-void launch_m2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
-                   const int* it_c0, const int* it_nc, const int64_t* wf_ptr,
-                   const int* wf_box, const double* bctr, const double* bh, const double* M,
-                   const double* cx, const double* cy, const double* cz, double* Lq,
-                   int64_t nctr) {
+void launch_m2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_c0,
+                   const int* it_nc, const int* it_w0, const int* it_w1, const int* wf_box,
+                   const double* bctr, const double* bh, const double* M, const double* cx,
+                   const double* cy, const double* cz, double* Lq, int64_t nctr) {
   if (nitem <= 0) return;
-  QDispatch<M2qbxlGo>::run(q, s, p, nitem, it_box, it_c0, it_nc, wf_ptr, wf_box, bctr, bh, M,
-                           cx, cy, cz, Lq, nctr);
+  QDispatch<M2qbxlGo>::run(q, s, p, nitem, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M, cx,
+                           cy, cz, Lq, nctr);
 }
 
 void launch_l2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,

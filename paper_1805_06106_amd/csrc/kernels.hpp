@@ -9,7 +9,7 @@ namespace gq {
 
 constexpr int kPmax = 20;  // highest FMM order supported by the device kernels
 constexpr int kQmax = 10;  // highest QBX order supported by the device kernels
-constexpr int kTileCols = 16;  // expansions per translation tile
+constexpr int kTileCols = 64;  // expansions per translation tile
 
 struct SrcSoA {
   const double *x, *y, *z, *nx, *ny, *nz;
@@ -45,12 +45,12 @@ void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_bo
                    const double* qs, const double* cx, const double* cy, const double* cz,
                    double* Lq, int64_t nctr);
 
-// Stage 5b: QBX locals from W-far multipoles (list per target box in CSR wf_ptr/wf_box).
-void launch_m2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
-                   const int* it_c0, const int* it_nc, const int64_t* wf_ptr,
-                   const int* wf_box, const double* bctr, const double* bh, const double* M,
-                   const double* cx, const double* cy, const double* cz, double* Lq,
-                   int64_t nctr);
+// Stage 5b: QBX locals from W-far multipoles.  Item i: centers [it_c0, it_c0 + it_nc) and
+// W-far boxes wf_box[it_w0 .. it_w1); accumulated atomically into Lq.
+void launch_m2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_c0,
+                   const int* it_nc, const int* it_w0, const int* it_w1, const int* wf_box,
+                   const double* bctr, const double* bh, const double* M, const double* cx,
+                   const double* cy, const double* cz, double* Lq, int64_t nctr);
 
 // Stage 8: QBX locals from the owning box's local.
 void launch_l2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,

@@ -385,7 +385,7 @@ void sort_unique(std::vector<int>& v) {
 
 }  // namespace
 
-void build_lists(const Tree& T, double tcf, Lists& out) {
+void build_lists(const Tree& T, double tcf, int wfar_direct_max, Lists& out) {
   const int nb = T.nboxes;
   ListBuilder B(T, tcf);
   out.is_target.assign(nb, 0);
@@ -416,8 +416,14 @@ void build_lists(const Tree& T, double tcf, Lists& out) {
       sort_unique(U);
       per[L_U][b] = std::move(U);
       auto W = B.list_W(b);
-      std::vector<int> wc, wf;
-      for (int d : W) B.wsplit(d, b, wc, wf);
+      std::vector<int> wc, wf0, wf;
+      for (int d : W) B.wsplit(d, b, wc, wf0);
+      for (int d : wf0) {
+        if (wfar_direct_max > 0 && T.sub_src[d] <= wfar_direct_max)
+          B.leaves_below(d, wc);  // Remark 4: evaluate this box's sources directly
+        else
+          wf.push_back(d);
+      }
       sort_unique(wc);
       sort_unique(wf);
       per[L_WCLOSE][b] = std::move(wc);

@@ -64,7 +64,9 @@ std::string build_tree(const TreeParams& prm, int64_t n_src, const double* src_x
                        int64_t n_tgt, const double* tgt_xyz, Tree& tree);
 
 // Builds all interaction lists for target and target-ancestor boxes.
-void build_lists(const Tree& tree, double tcf, Lists& lists);
+// wfar_direct_max > 0: List 3 far boxes with at most that many sources are replaced by
+// their source leaves in List 3 close (Remark 4).
+void build_lists(const Tree& tree, double tcf, int wfar_direct_max, Lists& lists);
 
 // Dense real-packed translation matrices in scaled form (see translations.cpp).
 int ncoef(int p);

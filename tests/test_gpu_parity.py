@@ -83,6 +83,15 @@ def test_gpu_per_list_vs_tier_b(dev, case, lst):
     assert err < TOL
 
 
+@pytest.mark.parametrize("case,thr", [("D-l1-n32", 24), ("D-l2-q5p15", 64), ("S-l2-q8p20", 10 ** 6)])
+def test_gpu_remark4_vs_tier_b(dev, case, thr):
+    w = workload_tiny(**CASES[case])
+    print(f"[gpu] case={case} wfar_direct_max={thr}", flush=True)
+    _, pot = run_gpu(w, dev, wfar_direct_max=thr)
+    tids, ref, _ = OracleFMM(w, wfar_direct_max=thr).evaluate()
+    assert rel(pot[0][tids], ref) < TOL
+
+
 @pytest.mark.parametrize("kernel", ["S", "D"])
 def test_single_box_equals_direct(dev, kernel):
     w = workload_tiny(level=1, order=2, kernel=kernel, p_qbx=4, p_fmm=4, nmax=10 ** 7)

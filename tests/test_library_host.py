@@ -47,11 +47,12 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("case", sorted(CASES) + ["D-l1-n32-r4"])
 def test_planner_matches_oracle_lists(gq, case):
-    w = workload_tiny(**CASES[case])
-    P = gq.Plan.from_workload(w, host_only=True)
-    F = OracleFMM(w)
+    thr = 24 if case.endswith("-r4") else 0
+    w = workload_tiny(**CASES[case.replace("-r4", "")])
+    P = gq.Plan.from_workload(w, host_only=True, wfar_direct_max=thr)
+    F = OracleFMM(w, wfar_direct_max=thr)
     c, h, lev, par, own = P.tree()
     t = F.tree
     assert len(h) == t.nboxes

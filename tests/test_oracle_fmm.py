@@ -151,3 +151,22 @@ def test_list_split_sums_to_total(fmm):
         _, p1, _ = fmm.evaluate(lists=(nm,))
         parts = parts + p1
     assert np.max(np.abs(parts - pot)) <= 1e-12 * np.max(np.abs(pot))
+
+
+@pytest.mark.parametrize("thr", [8, 40, 10 ** 6])
+def test_remark4_partition_and_value(thr):
+    """Remark 4 moves small List 3 far boxes to direct evaluation: the partition still holds
+    and the result moves toward direct QBX (never away from it by more than the bound)."""
+    w = workload_tiny(level=1, order=2, kernel="D", p_qbx=3, p_fmm=6, nmax=32)
+    F0 = OracleFMM(w)
+    F = OracleFMM(w, wfar_direct_max=thr)
+    for b in F.list_owner_boxes():
+        missing, multi = F.partition_check(b)
+        assert not missing and not multi
+    moved = sum(len(F0.lists.Wfar(b)) - len(F.lists.Wfar(b)) for b in F.target_boxes())
+    assert moved > 0
+    if thr >= 10 ** 6:
+        assert all(len(F.lists.Wfar(b)) == 0 for b in F.target_boxes())
+    ref = _tier_a(w)
+    tids, pot, _ = F.evaluate()
+    assert np.max(np.abs(pot - ref[tids])) / np.max(np.abs(ref)) <= 0.75 ** (w.p_fmm + 1)
