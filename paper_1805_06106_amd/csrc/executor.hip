@@ -68,6 +68,7 @@ struct gq_plan {
 
   // host work description
   std::vector<int> p2m_boxes;
+  std::vector<int64_t> p2m_rptr, p2m_rbeg, p2m_rcnt;
   std::vector<TileSet> m2m_levels;  // index: child level
   TileSet m2l;
   std::vector<TileSet> l2l_levels;  // index: child level
@@ -90,6 +91,7 @@ struct gq_plan {
   double *bctr = nullptr, *bh = nullptr;
   int64_t *src_start = nullptr, *src_count = nullptr;
   int* d_p2m_boxes = nullptr;
+  int64_t *d_p2m_rptr = nullptr, *d_p2m_rbeg = nullptr, *d_p2m_rcnt = nullptr;
   std::vector<std::array<int*, 5>> d_m2m, d_l2l;
   std::array<int*, 5> d_m2l{};
   int *d_p2l_box = nullptr;
@@ -178,8 +180,14 @@ gq_status build_work(gq_plan* P) {
   auto on = [&](unsigned bit) { return (mask & (bit >> 8)) != 0; };
 
   // Stage 2a
+  P->p2m_rptr.push_back(0);
   for (int b = 0; b < nb; ++b)
-    if (T.is_leaf(b) && T.src_count[b] > 0) P->p2m_boxes.push_back(b);
+    if (T.is_leaf(b) && T.src_count[b] > 0) {
+      P->p2m_boxes.push_back(b);
+      P->p2m_rbeg.push_back(T.src_start[b]);
+      P->p2m_rcnt.push_back(T.src_count[b]);
+      P->p2m_rptr.push_back((int64_t)P->p2m_rbeg.size());
+    }
   // Stage 2b, per child level (deepest first when launched)
   P->m2m_levels.assign(T.nlevels, TileSet());
   {
@@ -340,6 +348,9 @@ gq_status build_work(gq_plan* P) {
   GQ_TRY(upload(P, Tl, &P->T_l2l, s));
   GQ_TRY(upload(P, Tv, &P->T_m2l, s));
   GQ_TRY(upload(P, P->p2m_boxes, &P->d_p2m_boxes, s));
+  GQ_TRY(upload(P, P->p2m_rptr, &P->d_p2m_rptr, s));
+  GQ_TRY(upload(P, P->p2m_rbeg, &P->d_p2m_rbeg, s));
+  GQ_TRY(upload(P, P->p2m_rcnt, &P->d_p2m_rcnt, s));
   auto up_tiles = [&](const TileSet& t, std::array<int*, 5>& d) -> gq_status {
     GQ_TRY(upload(P, t.cls, &d[0], s));
     GQ_TRY(upload(P, t.beg, &d[1], s));
@@ -567,8 +578,8 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
     gq::launch_fill(s, P->L, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->Lq, (int64_t)P->n_ctr * P->nq, 0.0);
     GQ_TRY(mark(2));
-    gq::launch_p2m(s, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->src_start,
-                   P->src_count, P->bctr, P->bh, src, P->q, P->M);
+    gq::launch_p2m(s, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_rptr,
+                   P->d_p2m_rbeg, P->d_p2m_rcnt, P->bctr, P->bh, src, P->q, P->M);
     GQ_TRY(mark(3));
     for (int l = T.nlevels - 1; l >= 1; --l) {
       const auto& t = P->m2m_levels[l];

@@ -48,11 +48,9 @@ __global__ void k_strength(int64_t n, const int64_t* __restrict__ order,
 }
 
 // ------------------------------------------------------------------------------------
-// P2M and P2L: one 32-lane group per source, lane m owns the order-m column of the
-// expansion (all degrees n >= m), 8 sources in flight per 256-thread block.
+// P2M and P2L
 // ------------------------------------------------------------------------------------
 
-constexpr int kGroup = 32;
 constexpr int kInvTab = kPmax + 3;
 
 __device__ __forceinline__ void fill_invtab(double* tab) {
@@ -63,229 +61,192 @@ __device__ __forceinline__ void fill_invtab(double* tab) {
   }
 }
 
-// Reduce the per-lane column accumulators of all 8 groups and store/accumulate them.
-template <bool kAccumulate>
-__device__ __forceinline__ void reduce_store_columns(double (&ar)[kPmax + 2],
-                                                     double (&ai)[kPmax + 2], int P,
-                                                     double* red, double* out) {
-  const int lane = threadIdx.x & 31, wave = threadIdx.x >> 6;
+// Source-to-box expansions (P2M of leaf boxes, P2L of List 4 far boxes).
+//
+// One wavefront per box; each lane owns up to kSrcPerLane sources of the current batch.
+// The loops over order m and degree N of the solid-harmonic table H (H = R for P2M,
+// J = conj(I) for P2L, degrees 0..NT) are uniform across the wave: every lane advances the
+// recurrences of its own sources, the entry H_N^m weighted by each source's moment weights
+// is summed over the lane's sources, reduced across the wave with xor shuffles and added by
+// lane 0 into an LDS table.  Moments:
+//   single layer:  A = sum q H
+//   double layer:  A = sum w_z H, B = sum beta H, C = sum conj(beta) H, combined as
+//     P2M:  mu_n^m = A_{n-1}^m + B_{n-1}^{m+1} - C_{n-1}^{m-1}  (w_z = q n_z / a,
+//           beta = q (n_x - i n_y) / (2a); R ladders)
+//     P2L:  l_n^m  = A_{n+1}^m + B_{n+1}^{m+1} - C_{n+1}^{m-1}  (w_z = -q n_z / a,
+//           beta = q (n_x + i n_y) / (2a); J ladders)
+//   with H^-1 = -conj(H^1), so the order-0 output is A^0 + 2 Re(B^1).
+constexpr int kSrcPerLane = 4;
+constexpr int kTriMax = (kPmax + 2) * (kPmax + 3) / 2;  // entries with 0 <= m <= N <= kPmax+1
+
+__device__ __forceinline__ int tri(int N, int m) { return N * (N + 1) / 2 + m; }
+
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-  for (int n = 0; n <= kPmax + 1; ++n) {
-    ar[n] += __shfl_down(ar[n], 32, 64);
-    ai[n] += __shfl_down(ai[n], 32, 64);
-  }
-  // red layout: [wave][n][lane] re, then im
-  if ((threadIdx.x & 63) < 32) {
-#pragma unroll
-    for (int n = 0; n <= kPmax + 1; ++n) {
-      red[(wave * 2 * (kPmax + 2) + n) * 32 + lane] = ar[n];
-      red[(wave * 2 * (kPmax + 2) + kPmax + 2 + n) * 32 + lane] = ai[n];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < 32) {
-    const int m = lane;
-    for (int n = m; n <= P; ++n) {
-      double sr = 0.0, si = 0.0;
-      for (int w = 0; w < 4; ++w) {
-        sr += red[(w * 2 * (kPmax + 2) + n) * 32 + lane];
-        si += red[(w * 2 * (kPmax + 2) + kPmax + 2 + n) * 32 + lane];
-      }
-      if (kAccumulate) {
-        out[pkre(n, m)] += sr;
-        if (m) out[pkim(n, m)] += si;
-      } else {
-        out[pkre(n, m)] = sr;
-        if (m) out[pkim(n, m)] = si;
-      }
-    }
-  }
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
-template <int KERN>
-__global__ __launch_bounds__(256) void k_p2m(int P, const int* __restrict__ boxes,
-                                             const int64_t* __restrict__ src_start,
-                                             const int64_t* __restrict__ src_count,
-                                             const double* __restrict__ bctr,
-                                             const double* __restrict__ bh, SrcSoA src,
-                                             const double* __restrict__ q,
-                                             double* __restrict__ M) {
+template <int KERN, bool IRR>
+__global__ __launch_bounds__(64) void k_p2x(int P, const int* __restrict__ boxes,
+                                            const int64_t* __restrict__ rng_ptr,
+                                            const int64_t* __restrict__ rng_beg,
+                                            const int64_t* __restrict__ rng_cnt,
+                                            const double* __restrict__ bctr,
+                                            const double* __restrict__ bh, SrcSoA src,
+                                            const double* __restrict__ q,
+                                            double* __restrict__ out) {
+  constexpr int NMOM = KERN ? 3 : 1;
+  constexpr int K = kSrcPerLane;
   __shared__ double invtab[kInvTab * kInvTab];
-  __shared__ double red[4 * 2 * (kPmax + 2) * 32];
-  fill_invtab(invtab);
-  __syncthreads();
-  const int b = boxes[blockIdx.x];
-  const int np = (P + 1) * (P + 1);
-  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
-  const int m = lane;
-  const double a = bh[b], inv_a = 1.0 / a;
-  const double xb = bctr[3 * b], yb = bctr[3 * b + 1], zb = bctr[3 * b + 2];
-  double ar[kPmax + 2], ai[kPmax + 2];
-#pragma unroll
-  for (int n = 0; n <= kPmax + 1; ++n) ar[n] = ai[n] = 0.0;
-  const int64_t s0 = src_start[b], ns = src_count[b];
-  for (int64_t j = grp; j < ns; j += 8) {
-    const int64_t s = s0 + j;
-    const double ux = (src.x[s] - xb) * inv_a, uy = (src.y[s] - yb) * inv_a,
-                 uz = (src.z[s] - zb) * inv_a;
-    const double qq = q[s];
-    const double r2 = ux * ux + uy * uy + uz * uz;
-    // diagonal R_m^m = prod_{k<=m} -(ux + i uy)/(2k)
-    double dr = 1.0, di = 0.0;
-#pragma unroll
-    for (int k = 1; k <= kPmax; ++k) {
-      if (k <= m) {
-        const double f = -0.5 / k;
-        const double nr = f * (dr * ux - di * uy), ni = f * (dr * uy + di * ux);
-        dr = nr;
-        di = ni;
-      }
-    }
-    double qz = 0, qxh = 0, qyh = 0;
-    if (KERN) {
-      qz = qq * src.nz[s] * inv_a;
-      qxh = 0.5 * qq * src.nx[s] * inv_a;
-      qyh = 0.5 * qq * src.ny[s] * inv_a;
-    }
-    double p1r = 0, p1i = 0, p2r = 0, p2i = 0;  // R_{n-1}^m, R_{n-2}^m
-#pragma unroll
-    for (int n = 0; n <= kPmax; ++n) {
-      if (n > P) continue;  // uniform
-      double cr, ci;
-      if (n < m) {
-        cr = 0.0;
-        ci = 0.0;
-      } else if (n == m) {
-        cr = dr;
-        ci = di;
-      } else if (n == m + 1) {
-        cr = uz * p1r;
-        ci = uz * p1i;
-      } else {
-        const double t = invtab[n * kInvTab + m];
-        const double c1 = (2.0 * n - 1.0) * uz;
-        cr = (c1 * p1r - r2 * p2r) * t;
-        ci = (c1 * p1i - r2 * p2i) * t;
-      }
-      if (KERN == 0) {
-        ar[n] += qq * cr;
-        ai[n] += qq * ci;
-      } else if (n >= 1) {
-        // R_{n-1}^{m+1}, R_{n-1}^{m-1} from the neighbouring lanes
-        double upr = __shfl_down(p1r, 1, 32), upi = __shfl_down(p1i, 1, 32);
-        double dnr = __shfl_up(p1r, 1, 32), dni = __shfl_up(p1i, 1, 32);
-        if (m + 1 > P) {
-          upr = 0.0;
-          upi = 0.0;
-        }
-        if (m == 0) {  // R^-1 = -conj(R^1)
-          dnr = -upr;
-          dni = upi;
-        }
-        ar[n] += qz * p1r + (qxh * upr + qyh * upi) - (qxh * dnr - qyh * dni);
-        ai[n] += qz * p1i + (qxh * upi - qyh * upr) - (qxh * dni + qyh * dnr);
-      }
-      p2r = p1r;
-      p2i = p1i;
-      p1r = cr;
-      p1i = ci;
-    }
-  }
-  reduce_store_columns<false>(ar, ai, P, red, M + (int64_t)b * np);
-}
-
-template <int KERN>
-__global__ __launch_bounds__(256) void k_p2l(int P, const int* __restrict__ boxes,
-                                             const int64_t* __restrict__ rng_ptr,
-                                             const int64_t* __restrict__ rng_beg,
-                                             const int64_t* __restrict__ rng_cnt,
-                                             const double* __restrict__ bctr,
-                                             const double* __restrict__ bh, SrcSoA src,
-                                             const double* __restrict__ q,
-                                             double* __restrict__ L) {
-  __shared__ double red[4 * 2 * (kPmax + 2) * 32];
+  __shared__ double res[NMOM][kTriMax][2];
+  const int NT = IRR ? P + KERN : P - KERN;
   const int item = blockIdx.x;
   const int b = boxes[item];
   const int np = (P + 1) * (P + 1);
-  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
-  const int m = lane;
+  const int lane = threadIdx.x;
+  fill_invtab(invtab);
+  for (int i = lane; i < NMOM * kTriMax * 2; i += 64) (&res[0][0][0])[i] = 0.0;
+  __syncthreads();
   const double a = bh[b], inv_a = 1.0 / a;
   const double xb = bctr[3 * b], yb = bctr[3 * b + 1], zb = bctr[3 * b + 2];
-  const int NT = P + KERN;  // highest degree of J needed
-  double ar[kPmax + 2], ai[kPmax + 2];
+  const int64_t r0 = rng_ptr[item], r1 = rng_ptr[item + 1];
+  int64_t ns = 0;
+  for (int64_t r = r0; r < r1; ++r) ns += rng_cnt[r];
+  for (int64_t base = 0; base < ns; base += 64 * K) {
+    // load this lane's sources (flat index base + lane + 64 k over the ranges)
+    double ux[K], uy[K], uz[K], r2[K], ir2[K], w[K][NMOM][2], dr[K], di[K];
 #pragma unroll
-  for (int n = 0; n <= kPmax + 1; ++n) ar[n] = ai[n] = 0.0;
-  for (int64_t r = rng_ptr[item]; r < rng_ptr[item + 1]; ++r) {
-    const int64_t s0 = rng_beg[r], ns = rng_cnt[r];
-    for (int64_t j = grp; j < ns; j += 8) {
-      const int64_t s = s0 + j;
-      const double ux = (src.x[s] - xb) * inv_a, uy = (src.y[s] - yb) * inv_a,
-                   uz = (src.z[s] - zb) * inv_a;
-      const double qq = q[s];
-      const double r2 = ux * ux + uy * uy + uz * uz;
-      const double ir2 = 1.0 / r2;
-      // diagonal J_m^m = J_0^0 prod_{k<=m} -(2k-1)(ux - i uy)/r^2
-      double dr = sqrt(ir2), di = 0.0;
-#pragma unroll
-      for (int k = 1; k <= kPmax + 1; ++k) {
-        if (k <= m) {
-          const double f = -(2.0 * k - 1.0) * ir2;
-          const double nr = f * (dr * ux + di * uy), ni = f * (di * ux - dr * uy);
-          dr = nr;
-          di = ni;
+    for (int k = 0; k < K; ++k) {
+      int64_t f = base + lane + 64 * k;
+      int64_t si = -1;
+      if (f < ns) {
+        for (int64_t r = r0; r < r1; ++r) {
+          if (f < rng_cnt[r]) {
+            si = rng_beg[r] + f;
+            break;
+          }
+          f -= rng_cnt[r];
         }
       }
-      double qz = 0, qxh = 0, qyh = 0;
+      const bool ok = si >= 0;
+      const int64_t sj = ok ? si : rng_beg[r0];
+      ux[k] = (src.x[sj] - xb) * inv_a;
+      uy[k] = (src.y[sj] - yb) * inv_a;
+      uz[k] = (src.z[sj] - zb) * inv_a;
+      r2[k] = fma(ux[k], ux[k], fma(uy[k], uy[k], uz[k] * uz[k]));
+      ir2[k] = IRR ? 1.0 / r2[k] : 0.0;
+      const double qq = ok ? q[sj] : 0.0;
       if (KERN) {
-        qz = qq * src.nz[s] * inv_a;
-        qxh = 0.5 * qq * src.nx[s] * inv_a;
-        qyh = 0.5 * qq * src.ny[s] * inv_a;
+        const double sz = IRR ? -1.0 : 1.0, sy = IRR ? 1.0 : -1.0;
+        w[k][0][0] = sz * qq * src.nz[sj] * inv_a;
+        w[k][0][1] = 0.0;
+        w[k][1][0] = 0.5 * qq * src.nx[sj] * inv_a;
+        w[k][1][1] = sy * 0.5 * qq * src.ny[sj] * inv_a;
+        w[k][NMOM - 1][0] = w[k][1][0];
+        w[k][NMOM - 1][1] = -w[k][1][1];
+      } else {
+        w[k][0][0] = qq;
+        w[k][0][1] = 0.0;
       }
-      double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
+      dr[k] = IRR ? sqrt(ir2[k]) : 1.0;
+      di[k] = 0.0;
+    }
+    for (int m = 0; m <= NT; ++m) {
+      double p1r[K], p1i[K], p2r[K], p2i[K];
 #pragma unroll
-      for (int n = 0; n <= kPmax + 1; ++n) {
-        if (n > NT) continue;  // uniform
-        double cr, ci;
-        if (n < m) {
-          cr = 0.0;
-          ci = 0.0;
-        } else if (n == m) {
-          cr = dr;
-          ci = di;
-        } else {
-          const double c1 = (2.0 * n - 1.0) * uz * ir2;
-          const double c2 = (double)((n - 1) * (n - 1) - m * m) * ir2;
-          cr = c1 * p1r - c2 * p2r;
-          ci = c1 * p1i - c2 * p2i;
+      for (int k = 0; k < K; ++k) {
+        if (m > 0) {
+          double fr, fi;
+          if (IRR) {  // J_m^m = -(2m-1)(x - i y)/r^2 J_{m-1}^{m-1}
+            fr = -(2.0 * m - 1.0) * ux[k] * ir2[k];
+            fi = (2.0 * m - 1.0) * uy[k] * ir2[k];
+          } else {  // R_m^m = -(x + i y)/(2m) R_{m-1}^{m-1}
+            fr = -0.5 / m * ux[k];
+            fi = -0.5 / m * uy[k];
+          }
+          const double nr = fma(dr[k], fr, -di[k] * fi), ni = fma(dr[k], fi, di[k] * fr);
+          dr[k] = nr;
+          di[k] = ni;
         }
-        if (KERN == 0) {
-          ar[n] += qq * cr;
-          ai[n] += qq * ci;
-        } else {
-          // l_{n-1}^m += -qz J_n^m + (qx + i qy)/2 J_n^{m+1} - (qx - i qy)/2 J_n^{m-1}
-          double upr = __shfl_down(cr, 1, 32), upi = __shfl_down(ci, 1, 32);
-          double dnr = __shfl_up(cr, 1, 32), dni = __shfl_up(ci, 1, 32);
-          if (m + 1 > NT) {
-            upr = 0.0;
-            upi = 0.0;
+        p1r[k] = dr[k];
+        p1i[k] = di[k];
+        p2r[k] = 0.0;
+        p2i[k] = 0.0;
+      }
+      for (int N = m; N <= NT; ++N) {
+        double sum[NMOM][2];
+#pragma unroll
+        for (int t = 0; t < NMOM; ++t) sum[t][0] = sum[t][1] = 0.0;
+        const double tt = IRR ? 0.0 : invtab[N * kInvTab + m];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          double hr = p1r[k], hi = p1i[k];
+          if (N > m) {
+            if (IRR) {
+              const double c1 = (2.0 * N - 1.0) * uz[k] * ir2[k];
+              const double c2 = (double)((N - 1) * (N - 1) - m * m) * ir2[k];
+              hr = fma(c1, p1r[k], -c2 * p2r[k]);
+              hi = fma(c1, p1i[k], -c2 * p2i[k]);
+            } else {
+              const double c1 = (2.0 * N - 1.0) * uz[k];
+              hr = fma(c1, p1r[k], -r2[k] * p2r[k]) * tt;
+              hi = fma(c1, p1i[k], -r2[k] * p2i[k]) * tt;
+            }
+            p2r[k] = p1r[k];
+            p2i[k] = p1i[k];
+            p1r[k] = hr;
+            p1i[k] = hi;
           }
-          if (m == 0) {  // J^-1 = -conj(J^1)
-            dnr = -upr;
-            dni = upi;
-          }
-          if (n >= 1) {
-            ar[n - 1] += -qz * cr + (qxh * upr - qyh * upi) - (qxh * dnr + qyh * dni);
-            ai[n - 1] += -qz * ci + (qxh * upi + qyh * upr) - (qxh * dni - qyh * dnr);
+#pragma unroll
+          for (int t = 0; t < NMOM; ++t) {
+            sum[t][0] = fma(w[k][t][0], hr, fma(-w[k][t][1], hi, sum[t][0]));
+            sum[t][1] = fma(w[k][t][0], hi, fma(w[k][t][1], hr, sum[t][1]));
           }
         }
-        p2r = p1r;
-        p2i = p1i;
-        p1r = cr;
-        p1i = ci;
+#pragma unroll
+        for (int t = 0; t < NMOM; ++t) {
+          const double sr = wave_sum(sum[t][0]), si = wave_sum(sum[t][1]);
+          if (lane == 0) {
+            res[t][tri(N, m)][0] += sr;
+            res[t][tri(N, m)][1] += si;
+          }
+        }
       }
     }
   }
-  reduce_store_columns<true>(ar, ai, P, red, L + (int64_t)b * np);
+  __syncthreads();
+  auto mom = [&](int t, int N, int m, int c) -> double { return res[t][tri(N, m)][c]; };
+  double* o = out + (int64_t)b * np;
+  for (int i = lane; i < np; i += 64) {
+    int n = (int)sqrt((double)i);
+    while (n * n > i) --n;
+    while ((n + 1) * (n + 1) <= i) ++n;
+    const int off = i - n * n;
+    const int m = (off + 1) >> 1;
+    const int c = (off == 0) ? 0 : ((off & 1) ? 0 : 1);
+    double v;
+    if (!KERN) {
+      v = mom(0, n, m, c);
+    } else {
+      const int N = IRR ? n + 1 : n - 1;
+      if (N < 0) {
+        v = 0.0;
+      } else {
+        v = (m <= N) ? mom(0, N, m, c) : 0.0;
+        if (m == 0) {
+          v += (N >= 1) ? 2.0 * mom(1, N, 1, 0) : 0.0;
+        } else {
+          if (m + 1 <= N) v += mom(1, N, m + 1, c);
+          if (m - 1 <= N) v -= mom(NMOM - 1, N, m - 1, c);
+        }
+      }
+    }
+    if (IRR)
+      o[i] += v;
+    else
+      o[i] = v;
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -298,10 +259,16 @@ __global__ __launch_bounds__(256) void k_p2l(int P, const int* __restrict__ boxe
 // column blocks (16 accumulator tiles), so each matrix element is read once per tile.  The
 // input expansions are staged in LDS in chunks of kKc coefficients; outputs are added
 // atomically (several classes can target one box).
+// XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, each with its
+// own L2, and tiles are sorted by class; block i therefore takes tile
+// (i % 8) * per_xcd + i / 8, so each XCD walks one contiguous range of classes and reads
+// each class matrix into its L2 once.
 // ------------------------------------------------------------------------------------
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int kKc = 64;
+constexpr int kXs = kTileCols + 1;  // padded LDS row (avoids same-bank staging stores)
+constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 
 __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict__ tile_cls,
                                                    const int* __restrict__ tile_beg,
@@ -310,45 +277,72 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
                                                    const int* __restrict__ pair_dst,
                                                    const double* __restrict__ T,
                                                    const double* __restrict__ X,
-                                                   double* __restrict__ Y) {
-  __shared__ double xs[kKc * kTileCols];  // [k][col]
-  const int t = blockIdx.x;
+                                                   double* __restrict__ Y, int ntile,
+                                                   int per_xcd) {
+  __shared__ double xs[kKc * kXs];  // [k][col]
+  const int t = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (t >= ntile) return;
   const int cls = tile_cls[t], beg = tile_beg[t], cnt = tile_cnt[t];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const double* Tc = T + (int64_t)cls * np * np;
   const int nrb = (np + 15) >> 4;
+  // staging of one K-chunk of the input columns: thread -> (col, kk) pairs
+  constexpr int kStage = kKc * kTileCols / 256;
+  int64_t src_off[kStage];
+#pragma unroll
+  for (int u = 0; u < kStage; ++u) {
+    const int idx = threadIdx.x + 256 * u, col = idx / kKc;
+    src_off[u] = col < cnt ? (int64_t)pair_src[beg + col] * np : -1;
+  }
+  auto load_chunk = [&](int kc, double (&xr)[kStage]) {
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int idx = threadIdx.x + 256 * u, kk = idx % kKc, k = kc + kk;
+      xr[u] = (src_off[u] >= 0 && k < np) ? X[src_off[u] + k] : 0.0;
+    }
+  };
+  auto load_a = [&](int r0, int k, double (&a)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rb = r0 + wave + 4 * i;
+      const int row = rb * 16 + li;
+      a[i] = (rb < nrb && row < np && k < np) ? Tc[(int64_t)k * np + row] : 0.0;
+    }
+  };
   for (int r0 = 0; r0 < nrb; r0 += 16) {
     d4_t acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[i][cb] = (d4_t){0.0, 0.0, 0.0, 0.0};
+    double xr[kStage];
+    load_chunk(0, xr);
+    double a_cur[4];
+    load_a(r0, lk, a_cur);
     for (int kc = 0; kc < np; kc += kKc) {
       __syncthreads();
-      for (int idx = threadIdx.x; idx < kKc * kTileCols; idx += 256) {
-        const int col = idx / kKc, kk = idx - col * kKc;
-        const int k = kc + kk;
-        xs[kk * kTileCols + col] =
-            (col < cnt && k < np) ? X[(int64_t)pair_src[beg + col] * np + k] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int idx = threadIdx.x + 256 * u, col = idx / kKc, kk = idx % kKc;
+        xs[kk * kXs + col] = xr[u];
       }
       __syncthreads();
+      if (kc + kKc < np) load_chunk(kc + kKc, xr);  // in flight during this chunk
       const int kend = min(kKc, np - kc);
-#pragma unroll 2
       for (int k0 = 0; k0 < kend; k0 += 4) {
-        const int k = kc + k0 + lk;
+        double a_next[4];
+        load_a(r0, kc + k0 + 4 + lk, a_next);  // next K-step (next chunk's first at the end)
         double b[4];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) b[cb] = xs[(k0 + lk) * kTileCols + cb * 16 + li];
+        for (int cb = 0; cb < 4; ++cb) b[cb] = xs[(k0 + lk) * kXs + cb * 16 + li];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int rb = r0 + wave + 4 * i;
-          const int row = rb * 16 + li;
-          const double a = (rb < nrb && row < np && k < np) ? Tc[(int64_t)k * np + row] : 0.0;
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int cb = 0; cb < 4; ++cb)
-            acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[cb], acc[i][cb], 0, 0, 0);
-        }
+            acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[i], b[cb], acc[i][cb], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a_cur[i] = a_next[i];
       }
     }
 #pragma unroll
@@ -374,18 +368,28 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
 // P2QBXL: one thread per (center, source slice); sources staged through LDS.
 // ------------------------------------------------------------------------------------
 
+// 1/sqrt(x) for x > 0: hardware estimate refined by two Newton-Raphson steps
+// y <- y (3 - x y^2) / 2, each of which squares the relative error.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x, y * y, 1.5);
+  y = y * fma(-0.5 * x, y * y, 1.5);
+  return y;
+}
+
 template <int Q>
 __device__ __forceinline__ void p2qbxl_single(double dx, double dy, double dz, double qq,
                                               double (&acc)[(Q + 1) * (Q + 1)]) {
   // l_n^m += q J_n^m(s - c), J = conj(I): columns of fixed order m, increasing degree n
   const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  const double ir2 = 1.0 / r2;
+  const double ir = rsqrt_nr(r2);
+  const double ir2 = ir * ir;
   const double zr = dz * ir2;
   double zk[Q + 2];  // (2k - 1) z / r^2
 #pragma unroll
   for (int k = 1; k <= Q + 1; ++k) zk[k] = (2.0 * k - 1.0) * zr;
   const double xr = dx * ir2, yr = dy * ir2;
-  double dr = qq * sqrt(ir2), di = 0.0;
+  double dr = qq * ir, di = 0.0;
 #pragma unroll
   for (int m = 0; m <= Q; ++m) {
     if (m > 0) {  // J_m^m = -(2m-1)(x - i y)/r^2 J_{m-1}^{m-1}
@@ -421,13 +425,14 @@ __device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz, d
   // l_n^m += -qz J_{n+1}^m + qa J_{n+1}^{m+1} - conj(qa) J_{n+1}^{m-1}, qa = (qx + i qy)/2,
   // scattered from each J_N^M (N = n+1 <= Q+1) into the outputs it feeds, as FMA chains.
   const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  const double ir2 = 1.0 / r2;
+  const double ir = rsqrt_nr(r2);
+  const double ir2 = ir * ir;
   const double zr = dz * ir2;
   double zk[Q + 3];
 #pragma unroll
   for (int k = 1; k <= Q + 1; ++k) zk[k] = (2.0 * k - 1.0) * zr;
   const double xr = dx * ir2, yr = dy * ir2;
-  double dr = sqrt(ir2), di = 0.0;
+  double dr = ir, di = 0.0;
 #pragma unroll
   for (int M = 0; M <= Q + 1; ++M) {
     if (M > 0) {
@@ -946,14 +951,21 @@ void launch_strength(hipStream_t s, int64_t n, const int64_t* order, const doubl
   k_strength<<<grid1d(n, 256), 256, 0, s>>>(n, order, w, density, q);
 }
 
-void launch_p2m(hipStream_t s, int kernel, int p, int nbox, const int* boxes,
-                const int64_t* src_start, const int64_t* src_count, const double* bctr,
-                const double* bh, SrcSoA src, const double* q, double* M) {
-  if (nbox <= 0) return;
+template <int KERN, bool IRR>
+static void launch_p2x(hipStream_t s, int p, int nitem, const int* boxes, const int64_t* rp,
+                       const int64_t* rb, const int64_t* rc, const double* bctr,
+                       const double* bh, SrcSoA src, const double* q, double* out) {
+  k_p2x<KERN, IRR><<<nitem, 64, 0, s>>>(p, boxes, rp, rb, rc, bctr, bh, src, q, out);
+}
+
+void launch_p2m(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
+                const int64_t* rng_ptr, const int64_t* rng_beg, const int64_t* rng_cnt,
+                const double* bctr, const double* bh, SrcSoA src, const double* q, double* M) {
+  if (nitem <= 0) return;
   if (kernel)
-    k_p2m<1><<<nbox, 256, 0, s>>>(p, boxes, src_start, src_count, bctr, bh, src, q, M);
+    launch_p2x<1, false>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, M);
   else
-    k_p2m<0><<<nbox, 256, 0, s>>>(p, boxes, src_start, src_count, bctr, bh, src, q, M);
+    launch_p2x<0, false>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, M);
 }
 
 void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
@@ -961,17 +973,18 @@ void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
                 const double* bctr, const double* bh, SrcSoA src, const double* q, double* L) {
   if (nitem <= 0) return;
   if (kernel)
-    k_p2l<1><<<nitem, 256, 0, s>>>(p, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
+    launch_p2x<1, true>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
   else
-    k_p2l<0><<<nitem, 256, 0, s>>>(p, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
+    launch_p2x<0, true>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
 }
 
 void launch_translate(hipStream_t s, int np, int ntile, const int* tile_cls,
                       const int* tile_beg, const int* tile_cnt, const int* pair_src,
                       const int* pair_dst, const double* T, const double* X, double* Y) {
   if (ntile <= 0) return;
-  k_translate<<<ntile, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T, X,
-                                    Y);
+  const int per_xcd = (ntile + kXcds - 1) / kXcds;
+  k_translate<<<per_xcd * kXcds, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src,
+                                              pair_dst, T, X, Y, ntile, per_xcd);
 }
 
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
