@@ -44,6 +44,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="centers evaluated by the CPU oracle (direct QBX) for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain elementwise copy (y = -x) over 1 GiB, so that a "
+                         "hardware-counter pass can scale its byte counters by a kernel of "
+                         "known traffic")
     ap.add_argument("--wfar-direct-max", type=int, default=128,
                     help="Remark 4: List 3 far boxes with at most this many sources are "
                          "evaluated directly (0 disables); 128 is the measured optimum here")
@@ -61,6 +65,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = 1 << 27
+        x = torch.ones(n, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log(f"calibration copy: read {n * 8} B, wrote {n * 8} B")
+        del x, y
     t0 = time.time()
     w = make_workload(args.workload)
     log(f"workload {w.name}: {w.n_src} sources, {w.n_ctr} centers, {w.n_tgt} targets, "

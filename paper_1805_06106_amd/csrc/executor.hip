@@ -74,7 +74,8 @@ struct gq_plan {
   std::vector<TileSet> l2l_levels;  // index: child level
   std::vector<int> p2l_box;
   std::vector<int64_t> p2l_rptr, p2l_rbeg, p2l_rcnt;
-  std::vector<int64_t> near_ptr, near_beg, near_cnt;  // box-indexed CSR of source ranges
+  std::vector<int64_t> near_ptr;  // box-indexed CSR into near_idx
+  std::vector<int> near_idx;      // near sources (tree positions) of each target box
   std::vector<int> k3_box, k3_c0, k3_nc;
   std::vector<int> wf_box;
   std::vector<int> k5_c0, k5_nc, k5_w0, k5_w1;
@@ -96,7 +97,8 @@ struct gq_plan {
   std::array<int*, 5> d_m2l{};
   int *d_p2l_box = nullptr;
   int64_t *d_p2l_rptr = nullptr, *d_p2l_rbeg = nullptr, *d_p2l_rcnt = nullptr;
-  int64_t *d_near_ptr = nullptr, *d_near_beg = nullptr, *d_near_cnt = nullptr;
+  int64_t* d_near_ptr = nullptr;
+  int* d_near_idx = nullptr;
   int *d_k3_box = nullptr, *d_k3_c0 = nullptr, *d_k3_nc = nullptr;
   int* d_wf_box = nullptr;
   int *d_k5_c0 = nullptr, *d_k5_nc = nullptr, *d_k5_w0 = nullptr, *d_k5_w1 = nullptr;
@@ -281,10 +283,8 @@ gq_status build_work(gq_plan* P) {
         }
       }
       merge_ranges(r);
-      for (auto& x : r) {
-        P->near_beg.push_back(x.first);
-        P->near_cnt.push_back(x.second);
-      }
+      for (auto& x : r)
+        for (int64_t k = 0; k < x.second; ++k) P->near_idx.push_back((int)(x.first + k));
       if (!r.empty()) center_items(T, b, 256, P->k3_box, P->k3_c0, P->k3_nc);
       if (on(GQ_LIST_WFAR)) {
         const auto& W = Ls.lst[gq::L_WFAR];
@@ -303,7 +303,28 @@ gq_status build_work(gq_plan* P) {
       }
       center_items(T, b, 64, P->k8_box, P->k8_c0, P->k8_nc);
     }
-    P->near_ptr[b + 1] = (int64_t)P->near_beg.size();
+    P->near_ptr[b + 1] = (int64_t)P->near_idx.size();
+  }
+  // near-field items, most expensive first, so that the longest workgroups start early
+  {
+    const size_t n = P->k3_box.size();
+    std::vector<size_t> ord(n);
+    std::vector<int64_t> cost(n);
+    for (size_t i = 0; i < n; ++i) {
+      ord[i] = i;
+      const int b = P->k3_box[i];
+      cost[i] = (P->near_ptr[b + 1] - P->near_ptr[b]) * (int64_t)P->k3_nc[i];
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<int> bx(n), c0(n), nc(n);
+    for (size_t i = 0; i < n; ++i) {
+      bx[i] = P->k3_box[ord[i]];
+      c0[i] = P->k3_c0[ord[i]];
+      nc[i] = P->k3_nc[ord[i]];
+    }
+    P->k3_box.swap(bx);
+    P->k3_c0.swap(c0);
+    P->k3_nc.swap(nc);
   }
   P->stats.m2l_classes = (int64_t)cls_keys.size();
   // statistics
@@ -371,8 +392,7 @@ gq_status build_work(gq_plan* P) {
   GQ_TRY(upload(P, P->p2l_rbeg, &P->d_p2l_rbeg, s));
   GQ_TRY(upload(P, P->p2l_rcnt, &P->d_p2l_rcnt, s));
   GQ_TRY(upload(P, P->near_ptr, &P->d_near_ptr, s));
-  GQ_TRY(upload(P, P->near_beg, &P->d_near_beg, s));
-  GQ_TRY(upload(P, P->near_cnt, &P->d_near_cnt, s));
+  GQ_TRY(upload(P, P->near_idx, &P->d_near_idx, s));
   GQ_TRY(upload(P, P->k3_box, &P->d_k3_box, s));
   GQ_TRY(upload(P, P->k3_c0, &P->d_k3_c0, s));
   GQ_TRY(upload(P, P->k3_nc, &P->d_k3_nc, s));
@@ -584,10 +604,10 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
     for (int l = T.nlevels - 1; l >= 1; --l) {
       const auto& t = P->m2m_levels[l];
       const auto& dd = P->d_m2m[l];
-      gq::launch_translate(s, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->T_m2m, P->M, P->M);
+      gq::launch_translate(s, 0, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->T_m2m, P->M, P->M);
     }
     GQ_TRY(mark(4));
-    gq::launch_translate(s, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
+    gq::launch_translate(s, 2, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
                          P->d_m2l[3], P->d_m2l[4], P->T_m2l, P->M, P->L);
     GQ_TRY(mark(5));
     gq::launch_p2l(s, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_rptr,
@@ -596,11 +616,11 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
     for (int l = 1; l < T.nlevels; ++l) {
       const auto& t = P->l2l_levels[l];
       const auto& dd = P->d_l2l[l];
-      gq::launch_translate(s, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->T_l2l, P->L, P->L);
+      gq::launch_translate(s, 1, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->T_l2l, P->L, P->L);
     }
     GQ_TRY(mark(7));
     gq::launch_p2qbxl(s, kern, qo, (int)P->k3_box.size(), P->d_k3_box, P->d_k3_c0, P->d_k3_nc,
-                      P->d_near_ptr, P->d_near_beg, P->d_near_cnt, src, P->q, P->cx, P->cy,
+                      P->d_near_ptr, P->d_near_idx, src, P->q, P->cx, P->cy,
                       P->cz, P->Lq, P->n_ctr);
     GQ_TRY(mark(8));
     gq::launch_m2qbxl(s, p, qo, (int)P->k5_c0.size(), P->d_k5_c0, P->d_k5_nc, P->d_k5_w0,

@@ -270,6 +270,9 @@ constexpr int kKc = 64;
 constexpr int kXs = kTileCols + 1;  // padded LDS row (avoids same-bank staging stores)
 constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 
+// KIND (0 M2M, 1 L2L, 2 M2L) only names the instantiation, so that profiles tell the
+// three uses apart; the code is the same.
+template <int KIND>
 __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict__ tile_cls,
                                                    const int* __restrict__ tile_beg,
                                                    const int* __restrict__ tile_cnt,
@@ -287,20 +290,22 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
   const int li = lane & 15, lk = lane >> 4;
   const double* Tc = T + (int64_t)cls * np * np;
   const int nrb = (np + 15) >> 4;
-  // staging of one K-chunk of the input columns: thread -> (col, kk) pairs
-  constexpr int kStage = kKc * kTileCols / 256;
+  // staging of one K-chunk of the input columns: lane -> k, wave w -> columns w + 4u, so
+  // the column offsets are wave-uniform and live in scalar registers
+  static_assert(kKc == 64, "staging maps one lane to one k of a chunk");
+  constexpr int kStage = kTileCols / 4;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   int64_t src_off[kStage];
 #pragma unroll
   for (int u = 0; u < kStage; ++u) {
-    const int idx = threadIdx.x + 256 * u, col = idx / kKc;
+    const int col = wave_u + 4 * u;
     src_off[u] = col < cnt ? (int64_t)pair_src[beg + col] * np : -1;
   }
   auto load_chunk = [&](int kc, double (&xr)[kStage]) {
+    const int k = kc + lane;
 #pragma unroll
-    for (int u = 0; u < kStage; ++u) {
-      const int idx = threadIdx.x + 256 * u, kk = idx % kKc, k = kc + kk;
+    for (int u = 0; u < kStage; ++u)
       xr[u] = (src_off[u] >= 0 && k < np) ? X[src_off[u] + k] : 0.0;
-    }
   };
   auto load_a = [&](int r0, int k, double (&a)[4]) {
 #pragma unroll
@@ -323,10 +328,7 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
     for (int kc = 0; kc < np; kc += kKc) {
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        const int idx = threadIdx.x + 256 * u, col = idx / kKc, kk = idx % kKc;
-        xs[kk * kXs + col] = xr[u];
-      }
+      for (int u = 0; u < kStage; ++u) xs[lane * kXs + wave_u + 4 * u] = xr[u];
       __syncthreads();
       if (kc + kKc < np) load_chunk(kc + kKc, xr);  // in flight during this chunk
       const int kend = min(kKc, np - kc);
@@ -487,9 +489,8 @@ template <int Q, int KERN>
 __global__ __launch_bounds__(256) void k_p2qbxl(const int* __restrict__ it_box,
                                                 const int* __restrict__ it_c0,
                                                 const int* __restrict__ it_nc,
-                                                const int64_t* __restrict__ rng_ptr,
-                                                const int64_t* __restrict__ rng_beg,
-                                                const int64_t* __restrict__ rng_cnt,
+                                                const int64_t* __restrict__ near_ptr,
+                                                const int* __restrict__ near_idx,
                                                 SrcSoA src, const double* __restrict__ qs,
                                                 const double* __restrict__ cx,
                                                 const double* __restrict__ cy,
@@ -512,34 +513,33 @@ __global__ __launch_bounds__(256) void k_p2qbxl(const int* __restrict__ it_box,
   double acc[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
-  for (int64_t r = rng_ptr[b]; r < rng_ptr[b + 1]; ++r) {
-    const int64_t beg = rng_beg[r], cnt = rng_cnt[r];
-    for (int64_t off = 0; off < cnt; off += 256) {
-      const int n = (int)min((int64_t)256, cnt - off);
-      __syncthreads();
-      if (tid < n) {
-        const int64_t s = beg + off + tid;
-        ss[0 * 256 + tid] = src.x[s];
-        ss[1 * 256 + tid] = src.y[s];
-        ss[2 * 256 + tid] = src.z[s];
-        const double qq = qs[s];
-        if (KERN) {
-          ss[3 * 256 + tid] = qq * src.nz[s];
-          ss[4 * 256 + tid] = 0.5 * qq * src.nx[s];
-          ss[5 * 256 + tid] = 0.5 * qq * src.ny[s];
-        } else {
-          ss[3 * 256 + tid] = qq;
-        }
+  // sources in full chunks of 256 (only the box's last chunk is partial)
+  const int64_t fb = near_ptr[b], fe = near_ptr[b + 1];
+  for (int64_t f0 = fb; f0 < fe; f0 += 256) {
+    const int n = (int)min((int64_t)256, fe - f0);
+    __syncthreads();
+    if (tid < n) {
+      const int64_t s = near_idx[f0 + tid];
+      ss[0 * 256 + tid] = src.x[s];
+      ss[1 * 256 + tid] = src.y[s];
+      ss[2 * 256 + tid] = src.z[s];
+      const double qq = qs[s];
+      if (KERN) {
+        ss[3 * 256 + tid] = qq * src.nz[s];
+        ss[4 * 256 + tid] = 0.5 * qq * src.nx[s];
+        ss[5 * 256 + tid] = 0.5 * qq * src.ny[s];
+      } else {
+        ss[3 * 256 + tid] = qq;
       }
-      __syncthreads();
-      if (active) {
-        for (int j = sl; j < n; j += S) {
-          const double dx = ss[j] - xc, dy = ss[256 + j] - yc, dz = ss[512 + j] - zc;
-          if (KERN)
-            p2qbxl_double<Q>(dx, dy, dz, ss[768 + j], ss[1024 + j], ss[1280 + j], acc);
-          else
-            p2qbxl_single<Q>(dx, dy, dz, ss[768 + j], acc);
-        }
+    }
+    __syncthreads();
+    if (active) {
+      for (int j = sl; j < n; j += S) {
+        const double dx = ss[j] - xc, dy = ss[256 + j] - yc, dz = ss[512 + j] - zc;
+        if (KERN)
+          p2qbxl_double<Q>(dx, dy, dz, ss[768 + j], ss[1024 + j], ss[1280 + j], acc);
+        else
+          p2qbxl_single<Q>(dx, dy, dz, ss[768 + j], acc);
       }
     }
   }
@@ -881,15 +881,15 @@ inline dim3 grid1d(int64_t n, int bs) { return dim3((unsigned)((n + bs - 1) / bs
 template <int Q>
 struct P2qbxlGo {
   static void go(hipStream_t s, int kernel, int nitem, const int* it_box, const int* it_c0,
-                 const int* it_nc, const int64_t* rp, const int64_t* rb, const int64_t* rc,
-                 SrcSoA src, const double* qs, const double* cx, const double* cy,
-                 const double* cz, double* Lq, int64_t nctr) {
+                 const int* it_nc, const int64_t* np_, const int* ni, SrcSoA src,
+                 const double* qs, const double* cx, const double* cy, const double* cz,
+                 double* Lq, int64_t nctr) {
     if (kernel)
-      k_p2qbxl<Q, 1><<<nitem, 256, 0, s>>>(it_box, it_c0, it_nc, rp, rb, rc, src, qs, cx, cy,
-                                           cz, Lq, nctr);
+      k_p2qbxl<Q, 1><<<nitem, 256, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, cx, cy, cz,
+                                           Lq, nctr);
     else
-      k_p2qbxl<Q, 0><<<nitem, 256, 0, s>>>(it_box, it_c0, it_nc, rp, rb, rc, src, qs, cx, cy,
-                                           cz, Lq, nctr);
+      k_p2qbxl<Q, 0><<<nitem, 256, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, cx, cy, cz,
+                                           Lq, nctr);
   }
 };
 
@@ -978,23 +978,23 @@ void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
     launch_p2x<0, true>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
 }
 
-void launch_translate(hipStream_t s, int np, int ntile, const int* tile_cls,
+void launch_translate(hipStream_t s, int kind, int np, int ntile, const int* tile_cls,
                       const int* tile_beg, const int* tile_cnt, const int* pair_src,
                       const int* pair_dst, const double* T, const double* X, double* Y) {
   if (ntile <= 0) return;
   const int per_xcd = (ntile + kXcds - 1) / kXcds;
-  k_translate<<<per_xcd * kXcds, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src,
-                                              pair_dst, T, X, Y, ntile, per_xcd);
+  auto k = kind == 0 ? k_translate<0> : kind == 1 ? k_translate<1> : k_translate<2>;
+  k<<<per_xcd * kXcds, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T, X,
+                                    Y, ntile, per_xcd);
 }
 
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
-                   const int* it_c0, const int* it_nc, const int64_t* rng_ptr,
-                   const int64_t* rng_beg, const int64_t* rng_cnt, SrcSoA src,
-                   const double* qs, const double* cx, const double* cy, const double* cz,
-                   double* Lq, int64_t nctr) {
+                   const int* it_c0, const int* it_nc, const int64_t* near_ptr,
+                   const int* near_idx, SrcSoA src, const double* qs, const double* cx,
+                   const double* cy, const double* cz, double* Lq, int64_t nctr) {
   if (nitem <= 0) return;
-  QDispatch<P2qbxlGo>::run(q, s, kernel, nitem, it_box, it_c0, it_nc, rng_ptr, rng_beg,
-                           rng_cnt, src, qs, cx, cy, cz, Lq, nctr);
+  QDispatch<P2qbxlGo>::run(q, s, kernel, nitem, it_box, it_c0, it_nc, near_ptr, near_idx, src,
+                           qs, cx, cy, cz, Lq, nctr);
 }
 
 void launch_m2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_c0,

@@ -34,15 +34,17 @@ void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
                 const double* bctr, const double* bh, SrcSoA src, const double* q, double* L);
 
 // Batched dense translations: for each tile t, Y[dst] += T[cls] X[src] for its pairs.
-void launch_translate(hipStream_t s, int np, int ntile, const int* tile_cls,
+// kind: 0 M2M, 1 L2L, 2 M2L (selects a separately named instantiation).
+void launch_translate(hipStream_t s, int kind, int np, int ntile, const int* tile_cls,
                       const int* tile_beg, const int* tile_cnt, const int* pair_src,
                       const int* pair_dst, const double* T, const double* X, double* Y);
 
 // Stages 3, 5a, 6a: QBX locals from the near sources (U, W-close, X-close).
-// Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]).
+// Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]) (at most 256); the
+// box's near sources are near_idx[near_ptr[b] .. near_ptr[b+1]) (tree positions).
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
-                   const int* it_c0, const int* it_nc, const int64_t* rng_ptr,
-                   const int64_t* rng_beg, const int64_t* rng_cnt, SrcSoA src,
+                   const int* it_c0, const int* it_nc, const int64_t* near_ptr,
+                   const int* near_idx, SrcSoA src,
                    const double* qs, const double* cx, const double* cy, const double* cz,
                    double* Lq, int64_t nctr);
 
