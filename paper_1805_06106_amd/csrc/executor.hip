@@ -285,7 +285,7 @@ gq_status build_work(gq_plan* P) {
       merge_ranges(r);
       for (auto& x : r)
         for (int64_t k = 0; k < x.second; ++k) P->near_idx.push_back((int)(x.first + k));
-      if (!r.empty()) center_items(T, b, 256, P->k3_box, P->k3_c0, P->k3_nc);
+      if (!r.empty()) center_items(T, b, 64, P->k3_box, P->k3_c0, P->k3_nc);
       if (on(GQ_LIST_WFAR)) {
         const auto& W = Ls.lst[gq::L_WFAR];
         const int w0 = (int)P->wf_box.size();

@@ -485,83 +485,97 @@ __device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz, d
   }
 }
 
+// One 64-lane wavefront per item of at most 64 centers of one target box.  With nc
+// centers the wave splits into S = 64 / nc source slices (lane = center + nc * slice), so
+// at least 60 of the 64 lanes are busy for every nc.  The box's near sources (U, W-close,
+// X-close, flattened) are staged through LDS 64 at a time, the next batch being fetched
+// into registers while the current one is evaluated; slices are summed through LDS.
 template <int Q, int KERN>
-__global__ __launch_bounds__(256) void k_p2qbxl(const int* __restrict__ it_box,
-                                                const int* __restrict__ it_c0,
-                                                const int* __restrict__ it_nc,
-                                                const int64_t* __restrict__ near_ptr,
-                                                const int* __restrict__ near_idx,
-                                                SrcSoA src, const double* __restrict__ qs,
-                                                const double* __restrict__ cx,
-                                                const double* __restrict__ cy,
-                                                const double* __restrict__ cz,
-                                                double* __restrict__ Lq, int64_t nctr) {
+__global__ __launch_bounds__(64) void k_p2qbxl(const int* __restrict__ it_box,
+                                               const int* __restrict__ it_c0,
+                                               const int* __restrict__ it_nc,
+                                               const int64_t* __restrict__ near_ptr,
+                                               const int* __restrict__ near_idx,
+                                               SrcSoA src, const double* __restrict__ qs,
+                                               const double* __restrict__ cx,
+                                               const double* __restrict__ cy,
+                                               const double* __restrict__ cz,
+                                               double* __restrict__ Lq, int64_t nctr) {
   constexpr int NQ = (Q + 1) * (Q + 1);
-  constexpr int NF = KERN ? 7 : 4;
+  constexpr int NF = KERN ? 6 : 4;
   constexpr int kRed = 8;
-  __shared__ double ss[NF * 256];
-  __shared__ double red[kRed * 256];
+  __shared__ double ss[NF * 64];
+  __shared__ double red[kRed * 64];
   const int item = blockIdx.x;
   const int b = it_box[item];
   const int c0 = it_c0[item], nc = it_nc[item];
-  const int S = 256 / nc;
-  const int tid = threadIdx.x;
-  const int ci = tid % nc, sl = tid / nc;
+  const int S = 64 / nc;
+  const int lane = threadIdx.x;
+  const int ci = lane % nc, sl = lane / nc;
   const bool active = sl < S;
   const int64_t c = (int64_t)c0 + ci;
   const double xc = cx[c], yc = cy[c], zc = cz[c];
   double acc[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
-  // sources in full chunks of 256 (only the box's last chunk is partial)
   const int64_t fb = near_ptr[b], fe = near_ptr[b + 1];
-  for (int64_t f0 = fb; f0 < fe; f0 += 256) {
-    const int n = (int)min((int64_t)256, fe - f0);
-    __syncthreads();
-    if (tid < n) {
-      const int64_t s = near_idx[f0 + tid];
-      ss[0 * 256 + tid] = src.x[s];
-      ss[1 * 256 + tid] = src.y[s];
-      ss[2 * 256 + tid] = src.z[s];
-      const double qq = qs[s];
+  double pf[NF];
+  auto fetch = [&](int64_t f0) {
+    const int64_t f = f0 + lane;
+    if (f < fe) {
+      const int64_t sidx = near_idx[f];
+      const double qq = qs[sidx];
+      pf[0] = src.x[sidx];
+      pf[1] = src.y[sidx];
+      pf[2] = src.z[sidx];
       if (KERN) {
-        ss[3 * 256 + tid] = qq * src.nz[s];
-        ss[4 * 256 + tid] = 0.5 * qq * src.nx[s];
-        ss[5 * 256 + tid] = 0.5 * qq * src.ny[s];
+        pf[3] = qq * src.nz[sidx];
+        pf[4] = 0.5 * qq * src.nx[sidx];
+        pf[5] = 0.5 * qq * src.ny[sidx];
       } else {
-        ss[3 * 256 + tid] = qq;
+        pf[3] = qq;
       }
     }
+  };
+  fetch(fb);
+  for (int64_t f0 = fb; f0 < fe; f0 += 64) {
+    const int n = (int)min((int64_t)64, fe - f0);
     __syncthreads();
+    if (lane < n) {
+#pragma unroll
+      for (int v = 0; v < NF; ++v) ss[v * 64 + lane] = pf[v];
+    }
+    __syncthreads();
+    if (f0 + 64 < fe) fetch(f0 + 64);
     if (active) {
       for (int j = sl; j < n; j += S) {
-        const double dx = ss[j] - xc, dy = ss[256 + j] - yc, dz = ss[512 + j] - zc;
+        const double dx = ss[j] - xc, dy = ss[64 + j] - yc, dz = ss[128 + j] - zc;
         if (KERN)
-          p2qbxl_double<Q>(dx, dy, dz, ss[768 + j], ss[1024 + j], ss[1280 + j], acc);
+          p2qbxl_double<Q>(dx, dy, dz, ss[192 + j], ss[256 + j], ss[320 + j], acc);
         else
-          p2qbxl_single<Q>(dx, dy, dz, ss[768 + j], acc);
+          p2qbxl_single<Q>(dx, dy, dz, ss[192 + j], acc);
       }
     }
   }
-  // reduce over source slices and add into Lq
   if (S == 1) {
     if (active)
 #pragma unroll
       for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
     return;
   }
+  // sum the S slices of each center through LDS, kRed coefficients at a time
 #pragma unroll
   for (int base = 0; base < NQ; base += kRed) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kRed; ++k)
-      if (base + k < NQ) red[k * 256 + tid] = active ? acc[base + k] : 0.0;
+      if (base + k < NQ) red[k * 64 + lane] = active ? acc[base + k] : 0.0;
     __syncthreads();
     if (sl == 0) {
       for (int k = 0; k < kRed && base + k < NQ; ++k) {
-        double s = 0.0;
-        for (int j = 0; j < S; ++j) s += red[k * 256 + j * nc + ci];
-        Lq[(int64_t)(base + k) * nctr + c] += s;
+        double sum = 0.0;
+        for (int t = 0; t < S; ++t) sum += red[k * 64 + t * nc + ci];
+        Lq[(int64_t)(base + k) * nctr + c] += sum;
       }
     }
   }
@@ -885,11 +899,11 @@ struct P2qbxlGo {
                  const double* qs, const double* cx, const double* cy, const double* cz,
                  double* Lq, int64_t nctr) {
     if (kernel)
-      k_p2qbxl<Q, 1><<<nitem, 256, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, cx, cy, cz,
-                                           Lq, nctr);
+      k_p2qbxl<Q, 1><<<nitem, 64, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, cx, cy, cz,
+                                          Lq, nctr);
     else
-      k_p2qbxl<Q, 0><<<nitem, 256, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, cx, cy, cz,
-                                           Lq, nctr);
+      k_p2qbxl<Q, 0><<<nitem, 64, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, cx, cy, cz,
+                                          Lq, nctr);
   }
 };
 

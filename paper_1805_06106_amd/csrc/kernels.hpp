@@ -40,7 +40,7 @@ void launch_translate(hipStream_t s, int kind, int np, int ntile, const int* til
                       const int* pair_dst, const double* T, const double* X, double* Y);
 
 // Stages 3, 5a, 6a: QBX locals from the near sources (U, W-close, X-close).
-// Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]) (at most 256); the
+// Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]) (at most 64); the
 // box's near sources are near_idx[near_ptr[b] .. near_ptr[b+1]) (tree positions).
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
                    const int* it_c0, const int* it_nc, const int64_t* near_ptr,
