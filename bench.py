@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
 
 def log(msg):
@@ -44,6 +45,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="centers evaluated by the CPU oracle (direct QBX) for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the split-precision (FP32 matrix-core) translation runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain elementwise copy (y = -x) over 1 GiB, so that a "
                          "hardware-counter pass can scale its byte counters by a kernel of "
@@ -78,32 +81,40 @@ def main():
     w = make_workload(args.workload)
     log(f"workload {w.name}: {w.n_src} sources, {w.n_ctr} centers, {w.n_tgt} targets, "
         f"kernel {w.kernel}, p_qbx={w.p_qbx}, p_fmm={w.p_fmm} ({time.time() - t0:.1f}s)")
-    t0 = time.time()
-    plan = Plan.from_workload(w, timing=True, wfar_direct_max=args.wfar_direct_max)
-    plan_wall = time.time() - t0
-    st = plan.stats()
-    log(f"plan: {st['n_boxes']} boxes, {st['n_levels']} levels, pairs {st['pairs']} "
-        f"({plan_wall:.2f}s)")
     dens = torch.tensor(w.density[:1], dtype=torch.float64, device=dev)
-    pot = torch.empty((1, w.n_tgt), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
-    for _ in range(args.warmup):
-        plan.apply(dens, pot, stream=stream)
-    torch.cuda.synchronize()
-    plan.stats()  # closes the warmup timing window
-    log(f"warmup {args.warmup} done; timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.apply(dens, pot, stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    st = plan.stats()
-    k = max(st["timed_applies"], 1)
-    stage_ms = {s: v / k for s, v in st["stage_ms"].items()}
+
+    def run(precision):
+        t0 = time.time()
+        plan = Plan.from_workload(w, timing=True, wfar_direct_max=args.wfar_direct_max,
+                                  precision=precision)
+        plan_wall = time.time() - t0
+        st = plan.stats()
+        log(f"[{precision}] plan: {st['n_boxes']} boxes, {st['n_levels']} levels, pairs "
+            f"{st['pairs']} ({plan_wall:.2f}s)")
+        pot = torch.empty((1, w.n_tgt), dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            plan.apply(dens, pot, stream=stream)
+        torch.cuda.synchronize()
+        plan.stats()  # closes the warmup timing window
+        log(f"[{precision}] warmup {args.warmup} done; timing {args.steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.apply(dens, pot, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms_per_step = (t1 - t0) * 1e3 / args.steps
+        st = plan.stats()
+        k = max(st["timed_applies"], 1)
+        stage_ms = {s: v / k for s, v in st["stage_ms"].items()}
+        log(f"[{precision}] {ms_per_step:.2f} ms/step, {w.n_tgt / (ms_per_step * 1e-3):.4g} "
+            f"target evals/s; stage ms {stage_ms}")
+        plan.close()
+        return ms_per_step, stage_ms, st, plan_wall, pot
+
+    ms_per_step, stage_ms, st, plan_wall, pot = run("fp64")
     value = w.n_tgt / (ms_per_step * 1e-3)
-    log(f"{ms_per_step:.2f} ms/step, {value:.4g} target evals/s; stage ms {stage_ms}")
 
     flops = CM.apply_flops(st, w.p_fmm, w.p_qbx, w.kernel)
     kern_stage = {"p2qbxl": "p2qbxl", "m2qbxl": "m2qbxl", "m2l": "m2l", "l2qbxl": "l2qbxl"}
@@ -122,6 +133,27 @@ def main():
            "tflops": per_stage["m2l"]["tflops"],
            "frac_of_fp64_mfma_peak": round(per_stage["m2l"]["tflops"] / PEAK_FP64_VALU_TFLOPS, 4)
            if per_stage["m2l"]["tflops"] else None}
+
+    # split-precision translations (FP32 matrix cores), with and without the hi/lo correction
+    m2l_gemm_flops = flops["m2l"]
+    split = {}
+    if not args.no_fp32:
+        p64 = pot[0].clone()
+        for prec, products in (("fp32_split", 3), ("fp32", 1)):
+            ms_p, sm_p, _, _, pot_p = run(prec)
+            err = float((pot_p[0] - p64).abs().max() / p64.abs().max())
+            m2l_ms = sm_p["m2l"]
+            eff = m2l_gemm_flops / (m2l_ms * 1e-3) / 1e12
+            split[prec] = {
+                "value": round(w.n_tgt / (ms_p * 1e-3), 1), "ms_per_step": round(ms_p, 4),
+                "rel_err_vs_fp64_path": err,
+                "m2l": {"ms": round(m2l_ms, 4), "mfma_products": products,
+                        "executed_tflops": round(eff * products, 3),
+                        "effective_tflops": round(eff, 3),
+                        "frac_of_fp32_mfma_peak": round(eff * products / PEAK_FP32_MFMA_TFLOPS, 4)},
+                "stage_ms": {s: round(v, 4) for s, v in sm_p.items()},
+            }
+            log(f"[{prec}] rel err vs fp64 path {err:.3e}")
 
     cpu = None
     err_direct = None
@@ -164,13 +196,13 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "m2l": m2l,
+        "split_precision": split,
         "stages": per_stage,
         "stage_ms": {s: round(v, 4) for s, v in stage_ms.items()},
         "plan_seconds": round(plan_wall, 3),
         "tree": {"boxes": st["n_boxes"], "levels": st["n_levels"], "pairs": st["pairs"]},
     }
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

@@ -44,7 +44,14 @@ typedef enum {
 } gq_status;
 
 typedef enum { GQ_KERNEL_S = 0, GQ_KERNEL_D = 1 } gq_kernel;
-typedef enum { GQ_FP64 = 0 } gq_precision;
+/* Arithmetic of the dense translations (M2M, M2L, L2L; Stages 2, 4, 7).  Every other
+   stage, the expansions in memory and the final potential are FP64 in all modes.
+   GQ_FP64        FP64 matrix cores.
+   GQ_FP32_SPLIT  FP32 matrix cores on T = T_hi + T_lo and x = x_hi + x_lo, adding the
+                  correction products T_hi x_lo + T_lo x_hi; FP32 accumulation, result
+                  added to the FP64 expansions.
+   GQ_FP32        as GQ_FP32_SPLIT without the correction products (T_hi x_hi only). */
+typedef enum { GQ_FP64 = 0, GQ_FP32_SPLIT = 1, GQ_FP32 = 2 } gq_precision;
 
 /* gq_params.flags */
 #define GQ_FLAG_HOST_ONLY (1u << 0) /* plan on the host only: no device memory, no apply */

@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libgigaqbx.so")
 GQ_OK, GQ_EINVAL, GQ_ENOMEM, GQ_EDEVICE, GQ_EUNSUPPORTED = 0, 1, 2, 3, 4
 GQ_KERNEL_S, GQ_KERNEL_D = 0, 1
 GQ_FP64 = 0
+GQ_FP32_SPLIT = 1
+GQ_FP32 = 2
+PRECISIONS = {"fp64": GQ_FP64, "fp32_split": GQ_FP32_SPLIT, "fp32": GQ_FP32}
 GQ_FLAG_HOST_ONLY = 1 << 0
 GQ_FLAG_TIMING = 1 << 1
 GQ_LIST_U = 1 << 8
@@ -129,12 +132,13 @@ def gq_last_error():
 
 
 def make_params(p_qbx, p_fmm, nmax=512, tcf=0.9, kernel="S", n_densities=1, flags=0,
-                lists=None, wfar_direct_max=0):
+                lists=None, wfar_direct_max=0, precision="fp64"):
     k = {"S": GQ_KERNEL_S, "D": GQ_KERNEL_D}.get(kernel, kernel)
+    prec = PRECISIONS.get(precision, precision)
     if lists is not None:
         for nm in lists:
             flags |= LIST_BITS[nm]
-    return gq_params(int(p_qbx), int(p_fmm), int(nmax), float(tcf), int(k), GQ_FP64,
+    return gq_params(int(p_qbx), int(p_fmm), int(nmax), float(tcf), int(k), int(prec),
                      int(n_densities), int(flags), int(wfar_direct_max))
 
 

@@ -104,6 +104,9 @@ struct gq_plan {
   int *d_k5_c0 = nullptr, *d_k5_nc = nullptr, *d_k5_w0 = nullptr, *d_k5_w1 = nullptr;
   int *d_k8_box = nullptr, *d_k8_c0 = nullptr, *d_k8_nc = nullptr;
   double *T_m2m = nullptr, *T_l2l = nullptr, *T_m2l = nullptr;
+  float *T32_m2m[2] = {nullptr, nullptr}, *T32_l2l[2] = {nullptr, nullptr},
+        *T32_m2l[2] = {nullptr, nullptr};  // (hi, lo)
+  gq::TransMats tm_m2m{}, tm_l2l{}, tm_m2l{};
   double *q = nullptr, *M = nullptr, *L = nullptr, *Lq = nullptr;
   // per-stage timing: one event set per density pass, summed by gq_stats()
   std::vector<std::array<hipEvent_t, 12>> ev_sets;
@@ -365,9 +368,44 @@ gq_status build_work(gq_plan* P) {
   if (P->prm.flags & GQ_FLAG_HOST_ONLY) return GQ_OK;
 
   hipStream_t s = P->last_stream;
-  GQ_TRY(upload(P, Tm, &P->T_m2m, s));
-  GQ_TRY(upload(P, Tl, &P->T_l2l, s));
-  GQ_TRY(upload(P, Tv, &P->T_m2l, s));
+  // device layout: padded column-major (trans_ld rows, trans_kd columns, zero padding)
+  auto pad = [&](std::vector<double>& T) {
+    const int ld = gq::trans_ld(np), kd = gq::trans_kd(np);
+    const size_t nm = T.size() / ((size_t)np * np);
+    std::vector<double> out(nm * ld * kd, 0.0);
+    for (size_t m = 0; m < nm; ++m)
+      for (int c = 0; c < np; ++c)
+        for (int r = 0; r < np; ++r)
+          out[m * ld * kd + (size_t)c * ld + r] = T[m * np * np + (size_t)c * np + r];
+    T.swap(out);
+  };
+  pad(Tm);
+  pad(Tl);
+  pad(Tv);
+  if (P->prm.precision == GQ_FP64) {
+    GQ_TRY(upload(P, Tm, &P->T_m2m, s));
+    GQ_TRY(upload(P, Tl, &P->T_l2l, s));
+    GQ_TRY(upload(P, Tv, &P->T_m2l, s));
+  } else {
+    // T = hi + lo with hi = fl32(T), lo = fl32(T - hi)
+    auto split = [&](const std::vector<double>& T64, float** d) -> gq_status {
+      std::vector<float> hi(T64.size()), lo(T64.size());
+      for (size_t i = 0; i < T64.size(); ++i) {
+        hi[i] = (float)T64[i];
+        lo[i] = (float)(T64[i] - (double)hi[i]);
+      }
+      GQ_TRY(upload(P, hi, &d[0], s));
+      if (P->prm.precision == GQ_FP32_SPLIT) GQ_TRY(upload(P, lo, &d[1], s));
+      GQ_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+      return GQ_OK;
+    };
+    GQ_TRY(split(Tm, P->T32_m2m));
+    GQ_TRY(split(Tl, P->T32_l2l));
+    GQ_TRY(split(Tv, P->T32_m2l));
+  }
+  P->tm_m2m = {P->T_m2m, P->T32_m2m[0], P->T32_m2m[1]};
+  P->tm_l2l = {P->T_l2l, P->T32_l2l[0], P->T32_l2l[1]};
+  P->tm_m2l = {P->T_m2l, P->T32_m2l[0], P->T32_m2l[1]};
   GQ_TRY(upload(P, P->p2m_boxes, &P->d_p2m_boxes, s));
   GQ_TRY(upload(P, P->p2m_rptr, &P->d_p2m_rptr, s));
   GQ_TRY(upload(P, P->p2m_rbeg, &P->d_p2m_rbeg, s));
@@ -404,6 +442,7 @@ gq_status build_work(gq_plan* P) {
   GQ_TRY(upload(P, P->k8_box, &P->d_k8_box, s));
   GQ_TRY(upload(P, P->k8_c0, &P->d_k8_c0, s));
   GQ_TRY(upload(P, P->k8_nc, &P->d_k8_nc, s));
+  GQ_HIP(hipStreamSynchronize(s));  // the matrices above are host temporaries
   return GQ_OK;
 }
 
@@ -435,7 +474,8 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     return fail(GQ_EINVAL, "target confinement factor outside [0, 2 sqrt(3) - 2)");
   if (prm->kernel != GQ_KERNEL_S && prm->kernel != GQ_KERNEL_D)
     return fail(GQ_EINVAL, "unknown kernel");
-  if (prm->precision != GQ_FP64) return fail(GQ_EUNSUPPORTED, "only GQ_FP64 is available");
+  if (prm->precision != GQ_FP64 && prm->precision != GQ_FP32_SPLIT && prm->precision != GQ_FP32)
+    return fail(GQ_EINVAL, "unknown precision");
   if (prm->n_densities < 1) return fail(GQ_EINVAL, "n_densities must be >= 1");
   if (prm->wfar_direct_max < 0) return fail(GQ_EINVAL, "wfar_direct_max must be >= 0");
   if (prm->kernel == GQ_KERNEL_D && !src_normal) return fail(GQ_EINVAL, "double layer needs normals");
@@ -575,6 +615,7 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
   const gq::Tree& T = P->tree;
   const int p = P->prm.p_fmm, qo = P->prm.p_qbx, np = P->np;
   const int kern = P->prm.kernel;
+  const int prec = P->prm.precision;
   const bool timing = (P->prm.flags & GQ_FLAG_TIMING) != 0;
   gq::SrcSoA src{P->sx, P->sy, P->sz, P->snx, P->sny, P->snz};
   hipEvent_t* ev = nullptr;
@@ -604,11 +645,12 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
     for (int l = T.nlevels - 1; l >= 1; --l) {
       const auto& t = P->m2m_levels[l];
       const auto& dd = P->d_m2m[l];
-      gq::launch_translate(s, 0, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->T_m2m, P->M, P->M);
+      gq::launch_translate(s, 0, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_m2m,
+                           P->M, P->M);
     }
     GQ_TRY(mark(4));
-    gq::launch_translate(s, 2, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
-                         P->d_m2l[3], P->d_m2l[4], P->T_m2l, P->M, P->L);
+    gq::launch_translate(s, 2, prec, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
+                         P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L);
     GQ_TRY(mark(5));
     gq::launch_p2l(s, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_rptr,
                    P->d_p2l_rbeg, P->d_p2l_rcnt, P->bctr, P->bh, src, P->q, P->L);
@@ -616,7 +658,8 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
     for (int l = 1; l < T.nlevels; ++l) {
       const auto& t = P->l2l_levels[l];
       const auto& dd = P->d_l2l[l];
-      gq::launch_translate(s, 1, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->T_l2l, P->L, P->L);
+      gq::launch_translate(s, 1, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_l2l,
+                           P->L, P->L);
     }
     GQ_TRY(mark(7));
     gq::launch_p2qbxl(s, kern, qo, (int)P->k3_box.size(), P->d_k3_box, P->d_k3_c0, P->d_k3_nc,

@@ -266,9 +266,11 @@ __global__ __launch_bounds__(64) void k_p2x(int P, const int* __restrict__ boxes
 // ------------------------------------------------------------------------------------
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
-constexpr int kKc = 64;
+constexpr int kKc = kTransKc;
 constexpr int kXs = kTileCols + 1;  // padded LDS row (avoids same-bank staging stores)
 constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kPf64 = 2;            // K-steps of matrix prefetch, FP64 kernel
+constexpr int kPf32 = 4;            // K-steps of matrix prefetch, FP32 kernel
 
 // KIND (0 M2M, 1 L2L, 2 M2L) only names the instantiation, so that profiles tell the
 // three uses apart; the code is the same.
@@ -282,14 +284,15 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
                                                    const double* __restrict__ X,
                                                    double* __restrict__ Y, int ntile,
                                                    int per_xcd) {
-  __shared__ double xs[kKc * kXs];  // [k][col]
+  __shared__ double xs[2][kKc * kXs];  // double-buffered [k][col]
   const int t = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
   if (t >= ntile) return;
   const int cls = tile_cls[t], beg = tile_beg[t], cnt = tile_cnt[t];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const double* Tc = T + (int64_t)cls * np * np;
-  const int nrb = (np + 15) >> 4;
+  const int ld = trans_ld(np), kd = trans_kd(np);
+  const double* Tc = T + (int64_t)cls * ld * kd;
+  const int nrb = ld >> 4;
   // staging of one K-chunk of the input columns: lane -> k, wave w -> columns w + 4u, so
   // the column offsets are wave-uniform and live in scalar registers
   static_assert(kKc == 64, "staging maps one lane to one k of a chunk");
@@ -301,19 +304,26 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
     const int col = wave_u + 4 * u;
     src_off[u] = col < cnt ? (int64_t)pair_src[beg + col] * np : -1;
   }
-  auto load_chunk = [&](int kc, double (&xr)[kStage]) {
+  // the next chunk is fetched in two halves of kStage / 2 columns per wave
+  constexpr int kHalf = kStage / 2;
+  auto load_half = [&](int kc, int h, double (&xr)[kHalf]) {
     const int k = kc + lane;
 #pragma unroll
-    for (int u = 0; u < kStage; ++u)
-      xr[u] = (src_off[u] >= 0 && k < np) ? X[src_off[u] + k] : 0.0;
-  };
-  auto load_a = [&](int r0, int k, double (&a)[4]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int rb = r0 + wave + 4 * i;
-      const int row = rb * 16 + li;
-      a[i] = (rb < nrb && row < np && k < np) ? Tc[(int64_t)k * np + row] : 0.0;
+    for (int u = 0; u < kHalf; ++u) {
+      const int64_t o = src_off[h * kHalf + u];
+      xr[u] = (o >= 0 && k < np) ? X[o + k] : 0.0;
     }
+  };
+  auto store_half = [&](double* xb, int h, const double (&xr)[kHalf]) {
+#pragma unroll
+    for (int u = 0; u < kHalf; ++u) xb[lane * kXs + wave_u + 4 * (h * kHalf + u)] = xr[u];
+  };
+  // matrices are zero-padded to ld rows and kd columns; row blocks past the end and
+  // prefetches past the last column are clamped to valid addresses (and never used)
+  auto load_a = [&](int r0, int k, double (&a)[4]) {
+    const double* col = Tc + (int64_t)min(k, kd - 1) * ld + li;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = col[min(r0 + wave_u + 4 * i, nrb - 1) * 16];
   };
   for (int r0 = 0; r0 < nrb; r0 += 16) {
     d4_t acc[4][4];
@@ -321,31 +331,50 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[i][cb] = (d4_t){0.0, 0.0, 0.0, 0.0};
-    double xr[kStage];
-    load_chunk(0, xr);
-    double a_cur[4];
-    load_a(r0, lk, a_cur);
-    for (int kc = 0; kc < np; kc += kKc) {
-      __syncthreads();
+    double xr[kHalf];
+    __syncthreads();  // the previous row pass has finished reading both buffers
+    load_half(0, 0, xr);
+    store_half(xs[0], 0, xr);
+    load_half(0, 1, xr);
+    store_half(xs[0], 1, xr);
+    // matrix fragments of the next kPf64 K-steps are in flight while a step's MFMAs run
+    double a[kPf64][4];
 #pragma unroll
-      for (int u = 0; u < kStage; ++u) xs[lane * kXs + wave_u + 4 * u] = xr[u];
-      __syncthreads();
-      if (kc + kKc < np) load_chunk(kc + kKc, xr);  // in flight during this chunk
-      const int kend = min(kKc, np - kc);
-      for (int k0 = 0; k0 < kend; k0 += 4) {
-        double a_next[4];
-        load_a(r0, kc + k0 + 4 + lk, a_next);  // next K-step (next chunk's first at the end)
-        double b[4];
+    for (int d = 0; d < kPf64; ++d) load_a(r0, 4 * d + lk, a[d]);
+    __syncthreads();
+    int cur = 0;
+    auto steps = [&](int kc, int g0, int g1) {
+      const double* xb = xs[cur];
+#pragma unroll 1
+      for (int g = g0; g < g1; g += kPf64) {
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) b[cb] = xs[(k0 + lk) * kXs + cb * 16 + li];
+        for (int d = 0; d < kPf64; ++d) {
+          const int st = g + d;
+          double b[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+          for (int cb = 0; cb < 4; ++cb) b[cb] = xb[(4 * st + lk) * kXs + cb * 16 + li];
 #pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-            acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[i], b[cb], acc[i][cb], 0, 0, 0);
+          for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a_cur[i] = a_next[i];
+            for (int cb = 0; cb < 4; ++cb)
+              acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d][i], b[cb], acc[i][cb], 0, 0, 0);
+          load_a(r0, kc + 4 * (st + kPf64) + lk, a[d]);
+        }
       }
+    };
+    // all kKc/4 steps of every chunk (past np both operands are zero); the next chunk is
+    // fetched into the other buffer meanwhile
+    for (int kc = 0; kc < np; kc += kKc, cur ^= 1) {
+      const bool more = kc + kKc < np;
+      if (more) load_half(kc + kKc, 0, xr);
+      steps(kc, 0, kKc / 8);
+      if (more) {
+        store_half(xs[cur ^ 1], 0, xr);
+        load_half(kc + kKc, 1, xr);
+      }
+      steps(kc, kKc / 8, kKc / 4);
+      if (more) store_half(xs[cur ^ 1], 1, xr);
+      __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -360,6 +389,144 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
         for (int r = 0; r < 4; ++r) {
           const int row = rb * 16 + lk + 4 * r;
           if (row < np) unsafeAtomicAdd(&y[row], acc[i][cb][r]);
+        }
+      }
+    }
+  }
+}
+
+// Split-precision translations on FP32 MFMA (v_mfma_f32_16x16x4f32).  Same tiling as
+// k_translate.  The matrix is stored as T = T_hi + T_lo (two FP32 arrays) and each input
+// coefficient is split on the fly into x = x_hi + x_lo; SPLIT adds the two correction
+// products, T_hi x_lo + T_lo x_hi, to T_hi x_hi (the dropped T_lo x_lo term is below FP32
+// rounding).  Products accumulate in FP32 over the whole contraction; the result is added
+// to the FP64 expansions.  Without SPLIT only T_hi x_hi is used.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <int KIND, bool SPLIT>
+__global__ __launch_bounds__(256) void k_translate32(int np, const int* __restrict__ tile_cls,
+                                                     const int* __restrict__ tile_beg,
+                                                     const int* __restrict__ tile_cnt,
+                                                     const int* __restrict__ pair_src,
+                                                     const int* __restrict__ pair_dst,
+                                                     const float* __restrict__ Thi,
+                                                     const float* __restrict__ Tlo,
+                                                     const double* __restrict__ X,
+                                                     double* __restrict__ Y, int ntile,
+                                                     int per_xcd) {
+  __shared__ float2 xs[2][kKc * kXs];  // double-buffered [k][col] = (hi, lo)
+  const int t = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (t >= ntile) return;
+  const int cls = tile_cls[t], beg = tile_beg[t], cnt = tile_cnt[t];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ld = trans_ld(np), kd = trans_kd(np);
+  const int64_t moff = (int64_t)cls * ld * kd;
+  const int nrb = ld >> 4;
+  static_assert(kKc == 64, "staging maps one lane to one k of a chunk");
+  constexpr int kStage = kTileCols / 4;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  int64_t src_off[kStage];
+#pragma unroll
+  for (int u = 0; u < kStage; ++u) {
+    const int col = wave_u + 4 * u;
+    src_off[u] = col < cnt ? (int64_t)pair_src[beg + col] * np : -1;
+  }
+  constexpr int kHalf = kStage / 2;
+  auto load_half = [&](int kc, int h, double (&xr)[kHalf]) {
+    const int k = kc + lane;
+#pragma unroll
+    for (int u = 0; u < kHalf; ++u) {
+      const int64_t o = src_off[h * kHalf + u];
+      xr[u] = (o >= 0 && k < np) ? X[o + k] : 0.0;
+    }
+  };
+  auto store_half = [&](float2* xb, int h, const double (&xr)[kHalf]) {
+#pragma unroll
+    for (int u = 0; u < kHalf; ++u) {
+      const float hi = (float)xr[u];
+      const float lo = (float)(xr[u] - (double)hi);
+      xb[lane * kXs + wave_u + 4 * (h * kHalf + u)] = make_float2(hi, lo);
+    }
+  };
+  auto load_a = [&](int r0, int k, float (&ah)[4], float (&al)[4]) {
+    const int64_t col = moff + (int64_t)min(k, kd - 1) * ld + li;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t off = col + min(r0 + wave_u + 4 * i, nrb - 1) * 16;
+      ah[i] = Thi[off];
+      al[i] = SPLIT ? Tlo[off] : 0.0f;
+    }
+  };
+  for (int r0 = 0; r0 < nrb; r0 += 16) {
+    f4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[i][cb] = (f4_t){0.f, 0.f, 0.f, 0.f};
+    double xr[kHalf];
+    __syncthreads();  // the previous row pass has finished reading both buffers
+    load_half(0, 0, xr);
+    store_half(xs[0], 0, xr);
+    load_half(0, 1, xr);
+    store_half(xs[0], 1, xr);
+    float ah[kPf32][4], al[kPf32][4];
+#pragma unroll
+    for (int d = 0; d < kPf32; ++d) load_a(r0, 4 * d + lk, ah[d], al[d]);
+    __syncthreads();
+    int cur = 0;
+    auto steps = [&](int kc, int g0, int g1) {
+      const float2* xb = xs[cur];
+#pragma unroll 1
+      for (int g = g0; g < g1; g += kPf32) {
+#pragma unroll
+        for (int d = 0; d < kPf32; ++d) {
+          const int st = g + d;
+          float2 b[4];
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) b[cb] = xb[(4 * st + lk) * kXs + cb * 16 + li];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              if (SPLIT) {
+                acc[i][cb] =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(ah[d][i], b[cb].y, acc[i][cb], 0, 0, 0);
+                acc[i][cb] =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(al[d][i], b[cb].x, acc[i][cb], 0, 0, 0);
+              }
+              acc[i][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[d][i], b[cb].x, acc[i][cb], 0, 0, 0);
+            }
+          load_a(r0, kc + 4 * (st + kPf32) + lk, ah[d], al[d]);
+        }
+      }
+    };
+    for (int kc = 0; kc < np; kc += kKc, cur ^= 1) {
+      const bool more = kc + kKc < np;
+      if (more) load_half(kc + kKc, 0, xr);
+      steps(kc, 0, kKc / 8);
+      if (more) {
+        store_half(xs[cur ^ 1], 0, xr);
+        load_half(kc + kKc, 1, xr);
+      }
+      steps(kc, kKc / 8, kKc / 4);
+      if (more) store_half(xs[cur ^ 1], 1, xr);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rb = r0 + wave + 4 * i;
+      if (rb >= nrb) continue;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int col = cb * 16 + li;
+        if (col >= cnt) continue;
+        double* y = Y + (int64_t)pair_dst[beg + col] * np;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          // FP32 16x16x4 accumulator layout: register r of lane l holds D[4 (l/16) + r][l%16]
+          const int row = rb * 16 + 4 * lk + r;
+          if (row < np) unsafeAtomicAdd(&y[row], (double)acc[i][cb][r]);
         }
       }
     }
@@ -992,14 +1159,30 @@ void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
     launch_p2x<0, true>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
 }
 
-void launch_translate(hipStream_t s, int kind, int np, int ntile, const int* tile_cls,
-                      const int* tile_beg, const int* tile_cnt, const int* pair_src,
-                      const int* pair_dst, const double* T, const double* X, double* Y) {
+void launch_translate(hipStream_t s, int kind, int prec, int np, int ntile,
+                      const int* tile_cls, const int* tile_beg, const int* tile_cnt,
+                      const int* pair_src, const int* pair_dst, const TransMats& T,
+                      const double* X, double* Y) {
   if (ntile <= 0) return;
   const int per_xcd = (ntile + kXcds - 1) / kXcds;
-  auto k = kind == 0 ? k_translate<0> : kind == 1 ? k_translate<1> : k_translate<2>;
-  k<<<per_xcd * kXcds, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T, X,
-                                    Y, ntile, per_xcd);
+  const dim3 grid(per_xcd * kXcds);
+  if (prec == 0) {
+    auto k = kind == 0 ? k_translate<0> : kind == 1 ? k_translate<1> : k_translate<2>;
+    k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.t64, X, Y,
+                           ntile, per_xcd);
+  } else if (prec == 1) {
+    auto k = kind == 0   ? k_translate32<0, true>
+             : kind == 1 ? k_translate32<1, true>
+                         : k_translate32<2, true>;
+    k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo, X,
+                           Y, ntile, per_xcd);
+  } else {
+    auto k = kind == 0   ? k_translate32<0, false>
+             : kind == 1 ? k_translate32<1, false>
+                         : k_translate32<2, false>;
+    k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo, X,
+                           Y, ntile, per_xcd);
+  }
 }
 
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,

@@ -10,6 +10,12 @@ namespace gq {
 constexpr int kPmax = 20;  // highest FMM order supported by the device kernels
 constexpr int kQmax = 10;  // highest QBX order supported by the device kernels
 constexpr int kTileCols = 64;  // expansions per translation tile
+constexpr int kTransKc = 64;   // K-chunk of the translation kernels
+
+// Device layout of a translation matrix of order n_p = (p+1)^2: column-major with the
+// rows padded to trans_ld and the columns to trans_kd, zeros in the padding.
+__host__ __device__ inline int trans_ld(int np) { return (np + 15) / 16 * 16; }
+__host__ __device__ inline int trans_kd(int np) { return (np + kTransKc - 1) / kTransKc * kTransKc; }
 
 struct SrcSoA {
   const double *x, *y, *z, *nx, *ny, *nz;
@@ -33,11 +39,20 @@ void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
                 const int64_t* rng_ptr, const int64_t* rng_beg, const int64_t* rng_cnt,
                 const double* bctr, const double* bh, SrcSoA src, const double* q, double* L);
 
+// Translation matrices of one kind, column-major n_p x n_p per class: FP64 (t64) or the
+// FP32 pair T = hi + lo.
+struct TransMats {
+  const double* t64;
+  const float *hi, *lo;
+};
+
 // Batched dense translations: for each tile t, Y[dst] += T[cls] X[src] for its pairs.
 // kind: 0 M2M, 1 L2L, 2 M2L (selects a separately named instantiation).
-void launch_translate(hipStream_t s, int kind, int np, int ntile, const int* tile_cls,
-                      const int* tile_beg, const int* tile_cnt, const int* pair_src,
-                      const int* pair_dst, const double* T, const double* X, double* Y);
+// prec: 0 FP64 MFMA; 1 FP32 MFMA with the hi/lo split correction; 2 FP32 MFMA, hi only.
+void launch_translate(hipStream_t s, int kind, int prec, int np, int ntile,
+                      const int* tile_cls, const int* tile_beg, const int* tile_cnt,
+                      const int* pair_src, const int* pair_dst, const TransMats& T,
+                      const double* X, double* Y);
 
 // Stages 3, 5a, 6a: QBX locals from the near sources (U, W-close, X-close).
 // Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]) (at most 64); the

@@ -24,14 +24,15 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-def _gpu(w, thr, densities=None):
+def _gpu(w, thr, densities=None, precision="fp64"):
     import torch
 
     import paper_1805_06106_amd  # noqa: F401  (fails loudly without the library)
     from paper_1805_06106_amd import Plan
 
     dens = w.density if densities is None else densities
-    P = Plan.from_workload(w, n_densities=dens.shape[0], wfar_direct_max=thr)
+    P = Plan.from_workload(w, n_densities=dens.shape[0], wfar_direct_max=thr,
+                           precision=precision)
     d = torch.tensor(dens, dtype=torch.float64, device="cuda:0")
     pot = P.apply(d)
     torch.cuda.synchronize()
@@ -63,6 +64,22 @@ def test_urchin_sampled_vs_tier_b_and_a(urchin):
     err_a = rel(pot[tA], refA)
     print(f"[gpu] urchin vs Tier A (acceleration error): {err_a:.3e}", flush=True)
     assert err_a <= 0.75 ** (w.p_fmm + 1)
+
+
+def test_urchin_fp32_split_full_size(urchin):
+    # every target of the full problem: the split-precision translations against FP64, and
+    # sampled centers against the oracle
+    w = urchin
+    print("[gpu] urchin fp32_split vs fp64, all targets", flush=True)
+    p64 = _gpu(w, BENCH_WFAR_DIRECT_MAX)[0]
+    p32 = _gpu(w, BENCH_WFAR_DIRECT_MAX, precision="fp32_split")[0]
+    err = rel(p32, p64)
+    print(f"[gpu] urchin fp32_split vs fp64: {err:.3e}", flush=True)
+    assert err < 1e-6
+    rng = np.random.default_rng(22)
+    cs = np.sort(rng.choice(w.n_ctr, 24, replace=False))
+    tids, ref, _ = OracleFMM(w, wfar_direct_max=BENCH_WFAR_DIRECT_MAX).evaluate(centers=cs)
+    assert rel(p32[tids], ref) < 1e-6
 
 
 def test_urchin_linearity_full_size(urchin):

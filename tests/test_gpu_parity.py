@@ -161,3 +161,29 @@ def test_zero_density_and_linearity(dev):
     d2 = torch.tensor(np.random.default_rng(5).standard_normal((1, w.n_src)), device=dev)
     p1, p2, p12 = P.apply(d1).cpu().numpy(), P.apply(d2).cpu().numpy(), P.apply(2 * d1 - d2).cpu().numpy()
     assert rel(p12, 2 * p1 - p2) < 1e-12
+
+
+# --- split-precision translations ---------------------------------------------------------
+# Bar for the FP32 matrix-core translations: 1e-6 relative against the FP64 oracle.
+
+@pytest.mark.parametrize("case", ["D-l1-n32", "D-l2-q5p15", "S-l2-q8p20"])
+def test_fp32_split_translations_vs_tier_b(dev, case):
+    w = workload_tiny(**CASES[case])
+    F = OracleFMM(w)
+    tids, ref, _ = F.evaluate()
+    errs = {}
+    for prec in ("fp32_split", "fp32"):
+        print(f"[gpu] case={case} precision={prec}", flush=True)
+        _, pot = run_gpu(w, dev, precision=prec)
+        errs[prec] = rel(pot[0][tids], ref)
+    print(f"[gpu] {case}: fp32_split {errs['fp32_split']:.3e}, fp32 {errs['fp32']:.3e}", flush=True)
+    assert errs["fp32_split"] < 1e-6
+    assert errs["fp32"] < 1e-6
+
+
+def test_fp32_split_c1_vs_tier_b(dev):
+    w = workload_c1()
+    print("[gpu] C1 fp32_split", flush=True)
+    _, pot = run_gpu(w, dev, precision="fp32_split")
+    tids, ref, _ = OracleFMM(w).evaluate()
+    assert rel(pot[0][tids], ref) < 1e-6
