@@ -56,6 +56,15 @@ typedef enum { GQ_FP64 = 0, GQ_FP32_SPLIT = 1, GQ_FP32 = 2 } gq_precision;
 /* gq_params.flags */
 #define GQ_FLAG_HOST_ONLY (1u << 0) /* plan on the host only: no device memory, no apply */
 #define GQ_FLAG_TIMING (1u << 1)    /* record per-stage HIP events in gq_apply (gq_stats) */
+/* Run gq_apply as one HIP graph: the first call with a given (density, potential) pair
+   captures every kernel of the apply on a stream of the plan's own and later calls with
+   the same pair replay it with one launch on the caller's stream (a new pair is captured
+   anew).  Exclusive with GQ_FLAG_TIMING. */
+#define GQ_FLAG_GRAPH (1u << 2)
+/* At plan creation, time the Stage 4 (M2L) launch for tile widths 64 and 32 and for
+   XCD-aware or plain tile order on the plan's own tiles, and keep the fastest (reported in
+   gq_stats_t).  Without it: width 64, XCD-aware order. */
+#define GQ_FLAG_AUTOTUNE (1u << 3)
 /* Which interaction lists contribute (testing aid).  0 in bits 8..13 means all. */
 #define GQ_LIST_U (1u << 8)       /* List 1 (direct)            Stage 3 */
 #define GQ_LIST_V (1u << 9)       /* List 2 (M2L, then L2L)     Stages 4, 7, 8 */
@@ -97,6 +106,8 @@ typedef struct {
      9 QBXL2P, 10 fill, 11 total */
   double stage_ms[12];
   int64_t timed_applies;
+  int32_t m2l_tile_cols;    /* M2L tile width in use (64 or 32) */
+  int32_t m2l_xcd_order;    /* 1: XCD-aware M2L tile order, 0: plain */
 } gq_stats_t;
 
 /*
@@ -131,6 +142,24 @@ gq_status gq_apply(gq_plan* plan, const double* density, double* potential, void
 /* Copy plan statistics.  With GQ_FLAG_TIMING this waits for the timed applies, sums
    their stage times into out->stage_ms and starts a new timing window. */
 gq_status gq_stats(gq_plan* plan, gq_stats_t* out);
+
+/*
+ * Merge plans into one batch plan (the many-surface form of Algorithm 5): each stage then
+ * runs as one launch over every member's work, and the members' M2L pairs share the
+ * offset-class matrices, so tiles fill across surfaces.
+ *   plans[n_plans]  members; they must share p_qbx, p_fmm, kernel, precision and
+ *                   n_densities and must not be host-only.  Their geometry and work lists
+ *                   are copied: members may be destroyed or used on their own afterwards.
+ *   flags           GQ_FLAG_TIMING or GQ_FLAG_GRAPH (or 0) for the batch plan.
+ * The batch plan is applied with gq_apply and released with gq_plan_destroy.  Its density
+ * is [n_densities][sum of member n_src] and its potential [n_densities][sum of member
+ * n_tgt], members concatenated in the order given (member k's sources of density d at
+ * d * sum_n_src + (n_src of members before k)).  Errors: GQ_EINVAL for mismatched or
+ * host-only members, a member listed twice, or bad flags; GQ_EUNSUPPORTED beyond 2^31
+ * boxes, sources or centers.
+ */
+gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, void* hip_stream,
+                          gq_plan** out);
 
 /* Release a plan (NULL is ignored).  Synchronizes with outstanding device work. */
 void gq_plan_destroy(gq_plan* plan);

@@ -24,6 +24,8 @@ GQ_FP32 = 2
 PRECISIONS = {"fp64": GQ_FP64, "fp32_split": GQ_FP32_SPLIT, "fp32": GQ_FP32}
 GQ_FLAG_HOST_ONLY = 1 << 0
 GQ_FLAG_TIMING = 1 << 1
+GQ_FLAG_GRAPH = 1 << 2
+GQ_FLAG_AUTOTUNE = 1 << 3
 GQ_LIST_U = 1 << 8
 GQ_LIST_V = 1 << 9
 GQ_LIST_WCLOSE = 1 << 10
@@ -37,7 +39,8 @@ STAGES = ("strength", "p2m", "m2m", "m2l", "p2l", "l2l", "p2qbxl", "m2qbxl", "l2
           "qbxl2p", "fill", "total")
 
 EXPORTED = ("gq_plan_create", "gq_apply", "gq_stats", "gq_plan_destroy", "gq_last_error",
-            "gq_tree_export", "gq_list_export", "gq_qbx_locals", "gq_translation_matrix")
+            "gq_tree_export", "gq_list_export", "gq_qbx_locals", "gq_translation_matrix",
+            "gq_batch_create")
 
 
 class gq_params(ctypes.Structure):
@@ -54,7 +57,8 @@ class gq_stats_t(ctypes.Structure):
                 ("n_suspended_centers", ctypes.c_int64),
                 ("list_entries", ctypes.c_int64 * 6), ("pairs", ctypes.c_int64 * 6),
                 ("m2l_classes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
-                ("stage_ms", ctypes.c_double * 12), ("timed_applies", ctypes.c_int64)]
+                ("stage_ms", ctypes.c_double * 12), ("timed_applies", ctypes.c_int64),
+                ("m2l_tile_cols", ctypes.c_int32), ("m2l_xcd_order", ctypes.c_int32)]
 
 
 class GQError(RuntimeError):
@@ -92,6 +96,8 @@ def lib():
         L.gq_list_export.argtypes = [P, i32, P, P, ctypes.POINTER(ctypes.c_int64)]
         L.gq_qbx_locals.restype = i32
         L.gq_qbx_locals.argtypes = [P, P]
+        L.gq_batch_create.restype = i32
+        L.gq_batch_create.argtypes = [i32, P, ctypes.c_uint, P, ctypes.POINTER(ctypes.c_void_p)]
         L.gq_translation_matrix.restype = i32
         L.gq_translation_matrix.argtypes = [i32, i32, i32, i32, i32, P]
         _lib = L
@@ -158,6 +164,15 @@ def gq_plan_create(params, src_xyz, src_w, src_normal, ctr_xyz, ctr_radius, tgt_
     return out.value
 
 
+def gq_batch_create(plans, flags=0, stream=None):
+    """Merge plan handles into one batch plan handle."""
+    arr = (ctypes.c_void_p * len(plans))(*plans)
+    out = ctypes.c_void_p()
+    _check(lib().gq_batch_create(len(plans), ctypes.cast(arr, ctypes.c_void_p), int(flags),
+                                 _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
 def gq_apply(plan, density, potential, stream=None):
     """density: device [n_densities, n_src] float64; potential: device [n_densities, n_tgt]."""
     _check(lib().gq_apply(ctypes.c_void_p(plan), _dptr(density), _dptr(potential),
@@ -176,6 +191,7 @@ def gq_stats(plan):
         "m2l_classes": s.m2l_classes, "plan_seconds": s.plan_seconds,
         "stage_ms": dict(zip(STAGES, list(s.stage_ms))),
         "timed_applies": s.timed_applies,
+        "m2l_tile_cols": s.m2l_tile_cols, "m2l_xcd_order": bool(s.m2l_xcd_order),
     }
 
 

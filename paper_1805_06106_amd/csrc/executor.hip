@@ -36,14 +36,14 @@ struct TileSet {
   int ntile() const { return (int)cls.size(); }
 };
 
-// pairs (cls, src, dst) -> tiles grouped by class
-void make_tiles(std::vector<std::array<int, 3>> pairs, TileSet& ts) {
+// pairs (cls, src, dst) -> tiles of at most `width` pairs, grouped by class
+void make_tiles(std::vector<std::array<int, 3>> pairs, TileSet& ts, int width = gq::kTileCols) {
   std::stable_sort(pairs.begin(), pairs.end(),
                    [](const std::array<int, 3>& a, const std::array<int, 3>& b) { return a[0] < b[0]; });
   size_t i = 0;
   while (i < pairs.size()) {
     size_t j = i;
-    while (j < pairs.size() && pairs[j][0] == pairs[i][0] && j - i < (size_t)gq::kTileCols) ++j;
+    while (j < pairs.size() && pairs[j][0] == pairs[i][0] && j - i < (size_t)width) ++j;
     ts.cls.push_back(pairs[i][0]);
     ts.beg.push_back((int)ts.src.size());
     ts.cnt.push_back((int)(j - i));
@@ -80,6 +80,10 @@ struct gq_plan {
   std::vector<int> wf_box;
   std::vector<int> k5_c0, k5_nc, k5_w0, k5_w1;
   std::vector<int> k8_box, k8_c0, k8_nc;
+  std::vector<int> cls_keys;           // M2L class index -> offset key
+  int m2l_cols = gq::kTileCols;        // M2L tile width (32 or 64)
+  bool m2l_xcd = true;                 // XCD-aware M2L tile order
+  std::vector<int64_t> h_tgt_ctr, h_tgt_out;  // host copies of tgt_ctr / tgt_out
 
   // device memory
   std::vector<void*> allocs;
@@ -108,12 +112,20 @@ struct gq_plan {
         *T32_m2l[2] = {nullptr, nullptr};  // (hi, lo)
   gq::TransMats tm_m2m{}, tm_l2l{}, tm_m2l{};
   double *q = nullptr, *M = nullptr, *L = nullptr, *Lq = nullptr;
+  // GQ_FLAG_GRAPH: the passes of one apply captured once per (density, potential) pair
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  const double* graph_density = nullptr;
+  double* graph_potential = nullptr;
+  int64_t graph_launches = 0;
   // per-stage timing: one event set per density pass, summed by gq_stats()
   std::vector<std::array<hipEvent_t, 12>> ev_sets;
   size_t ev_used = 0;
   int64_t timed_applies = 0;
 
   ~gq_plan() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& set : ev_sets)
       for (auto& e : set) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
@@ -176,6 +188,28 @@ void center_items(const gq::Tree& T, int b, int chunk, std::vector<int>& box,
   }
 }
 
+// Near-field items, most expensive first, so that the longest workgroups start early.
+void sort_near_items(gq_plan* P) {
+  const size_t n = P->k3_box.size();
+  std::vector<size_t> ord(n);
+  std::vector<int64_t> cost(n);
+  for (size_t i = 0; i < n; ++i) {
+    ord[i] = i;
+    const int b = P->k3_box[i];
+    cost[i] = (P->near_ptr[b + 1] - P->near_ptr[b]) * (int64_t)P->k3_nc[i];
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<int> bx(n), c0(n), nc(n);
+  for (size_t i = 0; i < n; ++i) {
+    bx[i] = P->k3_box[ord[i]];
+    c0[i] = P->k3_c0[ord[i]];
+    nc[i] = P->k3_nc[ord[i]];
+  }
+  P->k3_box.swap(bx);
+  P->k3_c0.swap(c0);
+  P->k3_nc.swap(nc);
+}
+
 gq_status build_work(gq_plan* P) {
   const gq::Tree& T = P->tree;
   const gq::Lists& Ls = P->lists;
@@ -209,7 +243,7 @@ gq_status build_work(gq_plan* P) {
   }
   // Stage 4
   std::map<int, int> cls_index;
-  std::vector<int> cls_keys;
+  std::vector<int>& cls_keys = P->cls_keys;
   if (on(GQ_LIST_V)) {
     std::vector<std::array<int, 3>> pairs;
     for (int b = 0; b < nb; ++b) {
@@ -308,27 +342,7 @@ gq_status build_work(gq_plan* P) {
     }
     P->near_ptr[b + 1] = (int64_t)P->near_idx.size();
   }
-  // near-field items, most expensive first, so that the longest workgroups start early
-  {
-    const size_t n = P->k3_box.size();
-    std::vector<size_t> ord(n);
-    std::vector<int64_t> cost(n);
-    for (size_t i = 0; i < n; ++i) {
-      ord[i] = i;
-      const int b = P->k3_box[i];
-      cost[i] = (P->near_ptr[b + 1] - P->near_ptr[b]) * (int64_t)P->k3_nc[i];
-    }
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<int> bx(n), c0(n), nc(n);
-    for (size_t i = 0; i < n; ++i) {
-      bx[i] = P->k3_box[ord[i]];
-      c0[i] = P->k3_c0[ord[i]];
-      nc[i] = P->k3_nc[ord[i]];
-    }
-    P->k3_box.swap(bx);
-    P->k3_c0.swap(c0);
-    P->k3_nc.swap(nc);
-  }
+  sort_near_items(P);
   P->stats.m2l_classes = (int64_t)cls_keys.size();
   // statistics
   gq_stats_t& S = P->stats;
@@ -353,6 +367,14 @@ gq_status build_work(gq_plan* P) {
       if (l == gq::L_XFAR) S.pairs[l] += nsrc;
     }
   }
+  return GQ_OK;
+}
+
+// Translation matrices for the plan's classes and the upload of every work list.
+gq_status upload_work(gq_plan* P) {
+  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return GQ_OK;
+  const gq::Tree& T = P->tree;
+  const std::vector<int>& cls_keys = P->cls_keys;
   // translation matrices
   const int p = P->prm.p_fmm, np = P->np;
   std::vector<double> Tm((size_t)8 * np * np), Tl((size_t)8 * np * np);
@@ -365,7 +387,6 @@ gq_status build_work(gq_plan* P) {
     int key = cls_keys[c];
     gq::m2l_matrix(p, key / 121 - 5, (key / 11) % 11 - 5, key % 11 - 5, Tv.data() + c * np * np);
   }
-  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return GQ_OK;
 
   hipStream_t s = P->last_stream;
   // device layout: padded column-major (trans_ld rows, trans_kd columns, zero padding)
@@ -446,6 +467,231 @@ gq_status build_work(gq_plan* P) {
   return GQ_OK;
 }
 
+
+// ------------------------------------------------------------------------------------
+// Batches: several plans merged into one plan whose stages each run as one launch over
+// every member's work.  Box, source, center and target indices of member k are shifted by
+// the member totals before it; M2L tiles are re-formed over the union of the members'
+// offset classes, so members share translation matrices and fill tiles together.
+// ------------------------------------------------------------------------------------
+
+template <class T>
+void append_shifted(std::vector<T>& dst, const std::vector<T>& src, T shift) {
+  for (const T& v : src) dst.push_back(v + shift);
+}
+
+// ptr: CSR offsets (size n+1) of member items appended after `base` existing items
+void append_ptr(std::vector<int64_t>& dst, const std::vector<int64_t>& src, int64_t base) {
+  for (size_t i = 1; i < src.size(); ++i) dst.push_back(base + src[i]);
+}
+
+void tiles_to_pairs(const TileSet& t, int shift, const std::vector<int>* cls_map,
+                    std::vector<std::array<int, 3>>& out) {
+  for (int i = 0; i < t.ntile(); ++i) {
+    const int c = cls_map ? (*cls_map)[t.cls[i]] : t.cls[i];
+    for (int j = t.beg[i]; j < t.beg[i] + t.cnt[i]; ++j)
+      out.push_back({c, t.src[j] + shift, t.dst[j] + shift});
+  }
+}
+
+gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
+  gq::Tree& TB = B->tree;
+  int nlev = 0;
+  for (int k = 0; k < n; ++k) nlev = std::max(nlev, plans[k]->tree.nlevels);
+  TB.nlevels = nlev;
+  std::vector<std::vector<std::array<int, 3>>> m2m(nlev), l2l(nlev);
+  std::vector<std::array<int, 3>> m2l;
+  std::map<int, int> cls_index;
+  B->p2m_rptr.push_back(0);
+  B->p2l_rptr.push_back(0);
+  B->near_ptr.push_back(0);
+  int64_t boff = 0, soff = 0, coff = 0, toff = 0;
+  int woff = 0;
+  gq_stats_t& S = B->stats;
+  for (int k = 0; k < n; ++k) {
+    const gq_plan* P = plans[k];
+    const gq::Tree& T = P->tree;
+    const int bo = (int)boff, co = (int)coff;
+    TB.center.insert(TB.center.end(), T.center.begin(), T.center.end());
+    TB.h.insert(TB.h.end(), T.h.begin(), T.h.end());
+    append_shifted(TB.src_order, T.src_order, soff);  // index into the concatenated density
+    append_shifted(B->h_tgt_ctr, P->h_tgt_ctr, coff);
+    append_shifted(B->h_tgt_out, P->h_tgt_out, toff);
+    // Stage 2a and 6b source ranges
+    append_ptr(B->p2m_rptr, P->p2m_rptr, (int64_t)B->p2m_rbeg.size());
+    append_shifted(B->p2m_boxes, P->p2m_boxes, bo);
+    append_shifted(B->p2m_rbeg, P->p2m_rbeg, soff);
+    B->p2m_rcnt.insert(B->p2m_rcnt.end(), P->p2m_rcnt.begin(), P->p2m_rcnt.end());
+    append_ptr(B->p2l_rptr, P->p2l_rptr, (int64_t)B->p2l_rbeg.size());
+    append_shifted(B->p2l_box, P->p2l_box, bo);
+    append_shifted(B->p2l_rbeg, P->p2l_rbeg, soff);
+    B->p2l_rcnt.insert(B->p2l_rcnt.end(), P->p2l_rcnt.begin(), P->p2l_rcnt.end());
+    // translations: M2M/L2L by level, M2L by offset class
+    for (int l = 0; l < T.nlevels; ++l) {
+      tiles_to_pairs(P->m2m_levels[l], bo, nullptr, m2m[l]);
+      tiles_to_pairs(P->l2l_levels[l], bo, nullptr, l2l[l]);
+    }
+    std::vector<int> cmap(P->cls_keys.size());
+    for (size_t c = 0; c < P->cls_keys.size(); ++c) {
+      auto it = cls_index.find(P->cls_keys[c]);
+      if (it == cls_index.end()) {
+        it = cls_index.emplace(P->cls_keys[c], (int)B->cls_keys.size()).first;
+        B->cls_keys.push_back(P->cls_keys[c]);
+      }
+      cmap[c] = it->second;
+    }
+    tiles_to_pairs(P->m2l, bo, &cmap, m2l);
+    // near field, W-far, L2QBXL items
+    append_ptr(B->near_ptr, P->near_ptr, (int64_t)B->near_idx.size());
+    append_shifted(B->near_idx, P->near_idx, (int)soff);
+    append_shifted(B->k3_box, P->k3_box, bo);
+    append_shifted(B->k3_c0, P->k3_c0, co);
+    B->k3_nc.insert(B->k3_nc.end(), P->k3_nc.begin(), P->k3_nc.end());
+    append_shifted(B->wf_box, P->wf_box, bo);
+    append_shifted(B->k5_c0, P->k5_c0, co);
+    B->k5_nc.insert(B->k5_nc.end(), P->k5_nc.begin(), P->k5_nc.end());
+    append_shifted(B->k5_w0, P->k5_w0, woff);
+    append_shifted(B->k5_w1, P->k5_w1, woff);
+    append_shifted(B->k8_box, P->k8_box, bo);
+    append_shifted(B->k8_c0, P->k8_c0, co);
+    B->k8_nc.insert(B->k8_nc.end(), P->k8_nc.begin(), P->k8_nc.end());
+    // statistics
+    const gq_stats_t& Q = P->stats;
+    S.n_sources += Q.n_sources;
+    S.n_centers += Q.n_centers;
+    S.n_targets += Q.n_targets;
+    S.n_boxes += Q.n_boxes;
+    S.n_target_boxes += Q.n_target_boxes;
+    S.n_suspended_centers += Q.n_suspended_centers;
+    for (int l = 0; l < 6; ++l) {
+      S.list_entries[l] += Q.list_entries[l];
+      S.pairs[l] += Q.pairs[l];
+    }
+    boff += T.nboxes;
+    soff += P->n_src;
+    coff += P->n_ctr;
+    toff += P->n_tgt;
+    woff += (int)P->wf_box.size();
+  }
+  if (boff > INT32_MAX || soff > INT32_MAX || coff > INT32_MAX)
+    return fail(GQ_EUNSUPPORTED, "batch exceeds 2^31 boxes, sources or centers");
+  TB.nboxes = (int)boff;
+  S.n_levels = nlev;
+  S.m2l_classes = (int64_t)B->cls_keys.size();
+  B->m2m_levels.assign(nlev, TileSet());
+  B->l2l_levels.assign(nlev, TileSet());
+  for (int l = 0; l < nlev; ++l) {
+    make_tiles(m2m[l], B->m2m_levels[l]);
+    make_tiles(l2l[l], B->l2l_levels[l]);
+  }
+  make_tiles(m2l, B->m2l);
+  sort_near_items(B);
+  return GQ_OK;
+}
+
+// Device geometry of a merged plan: member arrays copied device to device.
+gq_status merge_geometry(gq_plan* B, gq_plan* const* plans, int n, hipStream_t s) {
+  struct Field {
+    double* gq_plan::*arr;
+    int which;  // 0 sources, 1 centers, 2 targets
+  };
+  const Field fields[] = {{&gq_plan::sx, 0}, {&gq_plan::sy, 0}, {&gq_plan::sz, 0},
+                          {&gq_plan::snx, 0}, {&gq_plan::sny, 0}, {&gq_plan::snz, 0},
+                          {&gq_plan::sw, 0}, {&gq_plan::cx, 1}, {&gq_plan::cy, 1},
+                          {&gq_plan::cz, 1}, {&gq_plan::tx, 2}, {&gq_plan::ty, 2},
+                          {&gq_plan::tz, 2}};
+  for (const Field& f : fields) {
+    const int64_t total = f.which == 0 ? B->n_src : f.which == 1 ? B->n_ctr : B->n_tgt;
+    GQ_TRY(alloc(B, (size_t)total, &(B->*f.arr)));
+    int64_t off = 0;
+    for (int k = 0; k < n; ++k) {
+      const gq_plan* P = plans[k];
+      const int64_t m = f.which == 0 ? P->n_src : f.which == 1 ? P->n_ctr : P->n_tgt;
+      if (m > 0)
+        GQ_HIP(hipMemcpyAsync(B->*f.arr + off, P->*f.arr, (size_t)m * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+      off += m;
+    }
+  }
+  const gq::Tree& T = B->tree;
+  GQ_TRY(upload(B, T.src_order, &B->src_order, s));
+  GQ_TRY(upload(B, B->h_tgt_ctr, &B->tgt_ctr, s));
+  GQ_TRY(upload(B, B->h_tgt_out, &B->tgt_out, s));
+  GQ_TRY(upload(B, T.center, &B->bctr, s));
+  GQ_TRY(upload(B, T.h, &B->bh, s));
+  GQ_TRY(alloc(B, (size_t)B->n_src, &B->q));
+  GQ_TRY(alloc(B, (size_t)T.nboxes * B->np, &B->M));
+  GQ_TRY(alloc(B, (size_t)T.nboxes * B->np, &B->L));
+  GQ_TRY(alloc(B, (size_t)B->n_ctr * B->nq, &B->Lq));
+  GQ_HIP(hipStreamSynchronize(s));
+  return GQ_OK;
+}
+
+// GQ_FLAG_AUTOTUNE: time the M2L launch (Stage 4) on this plan's own tiles for tile widths
+// 64 and 32 and for XCD-aware or plain tile order, and keep the fastest.  The timed
+// launches read zeroed multipoles; the box locals are cleared by every apply.
+gq_status autotune_m2l(gq_plan* P, hipStream_t s) {
+  if (P->m2l.ntile() == 0) return GQ_OK;
+  std::vector<std::array<int, 3>> pairs;
+  tiles_to_pairs(P->m2l, 0, nullptr, pairs);
+  struct Cand {
+    TileSet ts;
+    std::array<int*, 5> d{};
+  } cand[2];
+  const int widths[2] = {64, 32};
+  for (int w = 0; w < 2; ++w) {
+    make_tiles(pairs, cand[w].ts, widths[w]);
+    const TileSet& t = cand[w].ts;
+    GQ_TRY(upload(P, t.cls, &cand[w].d[0], s));
+    GQ_TRY(upload(P, t.beg, &cand[w].d[1], s));
+    GQ_TRY(upload(P, t.cnt, &cand[w].d[2], s));
+    GQ_TRY(upload(P, t.src, &cand[w].d[3], s));
+    GQ_TRY(upload(P, t.dst, &cand[w].d[4], s));
+  }
+  gq::launch_fill(s, P->M, (int64_t)P->tree.nboxes * P->np, 0.0);
+  gq::launch_fill(s, P->L, (int64_t)P->tree.nboxes * P->np, 0.0);
+  hipEvent_t e0, e1;
+  GQ_HIP(hipEventCreate(&e0));
+  GQ_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bw = 0;
+  bool bx = true;
+  gq_status st = GQ_OK;
+  for (int w = 0; w < 2 && st == GQ_OK; ++w)
+    for (int x = 0; x < 2; ++x) {
+      const bool xcd = x == 0;
+      auto run = [&]() {
+        const auto& d = cand[w].d;
+        gq::launch_translate(s, 2, P->prm.precision, P->np, cand[w].ts.ntile(), d[0], d[1], d[2],
+                             d[3], d[4], P->tm_m2l, P->M, P->L, widths[w], xcd);
+      };
+      run();  // warm-up
+      hipError_t e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3; ++r) run();
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = fail(GQ_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        bw = w;
+        bx = xcd;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GQ_OK) return st;
+  P->m2l = cand[bw].ts;
+  P->d_m2l = cand[bw].d;
+  P->m2l_cols = widths[bw];
+  P->m2l_xcd = bx;
+  return GQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -478,6 +724,8 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     return fail(GQ_EINVAL, "unknown precision");
   if (prm->n_densities < 1) return fail(GQ_EINVAL, "n_densities must be >= 1");
   if (prm->wfar_direct_max < 0) return fail(GQ_EINVAL, "wfar_direct_max must be >= 0");
+  if ((prm->flags & GQ_FLAG_TIMING) && (prm->flags & GQ_FLAG_GRAPH))
+    return fail(GQ_EINVAL, "GQ_FLAG_TIMING and GQ_FLAG_GRAPH are exclusive");
   if (prm->kernel == GQ_KERNEL_D && !src_normal) return fail(GQ_EINVAL, "double layer needs normals");
   if (!finite3(src_xyz, n_src) || !finite3(ctr_xyz, n_ctr) || !finite3(tgt_xyz, n_tgt))
     return fail(GQ_EINVAL, "non-finite coordinates");
@@ -519,6 +767,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
   P->stats.n_centers = n_ctr;
   P->stats.n_targets = n_tgt;
   gq_status st = build_work(P);
+  if (st == GQ_OK) st = upload_work(P);
   if (st != GQ_OK) {
     delete P;
     return st;
@@ -582,6 +831,8 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
       GQ_TRY(upload(P, tz, &P->tz, s));
       GQ_TRY(upload(P, tc, &P->tgt_ctr, s));
       GQ_TRY(upload(P, tord, &P->tgt_out, s));
+      P->h_tgt_ctr.swap(tc);
+      P->h_tgt_out.swap(tord);
       GQ_TRY(upload(P, T.center, &P->bctr, s));
       GQ_TRY(upload(P, T.h, &P->bh, s));
       GQ_TRY(upload(P, T.src_start, &P->src_start, s));
@@ -594,6 +845,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
       return GQ_OK;
     };
     st = go();
+    if (st == GQ_OK && (prm->flags & GQ_FLAG_AUTOTUNE)) st = autotune_m2l(P, s);
     if (st != GQ_OK) {
       delete P;
       return st;
@@ -605,18 +857,18 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
   return GQ_OK;
 }
 
-gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* hip_stream) {
-  g_err.clear();
-  if (!P) return fail(GQ_EINVAL, "NULL plan");
-  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
-  if (!density || !potential) return fail(GQ_EINVAL, "NULL device buffer");
-  hipStream_t s = (hipStream_t)hip_stream;
-  P->last_stream = s;
+}  // extern "C"
+
+namespace {
+
+// Enqueues every density pass of one apply on stream s (eager launches, or the launches
+// being captured into a graph).
+gq_status apply_passes(gq_plan* P, const double* density, double* potential, hipStream_t s,
+                       bool timing) {
   const gq::Tree& T = P->tree;
   const int p = P->prm.p_fmm, qo = P->prm.p_qbx, np = P->np;
   const int kern = P->prm.kernel;
   const int prec = P->prm.precision;
-  const bool timing = (P->prm.flags & GQ_FLAG_TIMING) != 0;
   gq::SrcSoA src{P->sx, P->sy, P->sz, P->snx, P->sny, P->snz};
   hipEvent_t* ev = nullptr;
   auto mark = [&](int i) -> gq_status {
@@ -650,7 +902,8 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
     }
     GQ_TRY(mark(4));
     gq::launch_translate(s, 2, prec, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
-                         P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L);
+                         P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L, P->m2l_cols,
+                         P->m2l_xcd);
     GQ_TRY(mark(5));
     gq::launch_p2l(s, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_rptr,
                    P->d_p2l_rbeg, P->d_p2l_rcnt, P->bctr, P->bh, src, P->q, P->L);
@@ -678,7 +931,51 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
     GQ_TRY(mark(11));
     GQ_HIP(hipGetLastError());
   }
-  if (timing) P->timed_applies += 1;
+  return GQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* hip_stream) {
+  g_err.clear();
+  if (!P) return fail(GQ_EINVAL, "NULL plan");
+  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
+  if (!density || !potential) return fail(GQ_EINVAL, "NULL device buffer");
+  hipStream_t s = (hipStream_t)hip_stream;
+  P->last_stream = s;
+  const bool timing = (P->prm.flags & GQ_FLAG_TIMING) != 0;
+  if (!(P->prm.flags & GQ_FLAG_GRAPH)) {
+    GQ_TRY(apply_passes(P, density, potential, s, timing));
+    if (timing) P->timed_applies += 1;
+    return GQ_OK;
+  }
+  // graph mode: capture on the plan's own stream, launch on the caller's
+  if (!P->graph_exec || P->graph_density != density || P->graph_potential != potential) {
+    if (P->graph_exec) {
+      GQ_HIP(hipStreamSynchronize(s));
+      GQ_HIP(hipGraphExecDestroy(P->graph_exec));
+      P->graph_exec = nullptr;
+    }
+    if (!P->cap_stream) GQ_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    GQ_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    gq_status st = apply_passes(P, density, potential, P->cap_stream, false);
+    hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+    if (st != GQ_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(GQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(GQ_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    P->graph_density = density;
+    P->graph_potential = potential;
+  }
+  GQ_HIP(hipGraphLaunch(P->graph_exec, s));
+  P->graph_launches += 1;
   return GQ_OK;
 }
 
@@ -705,7 +1002,57 @@ gq_status gq_stats(gq_plan* P, gq_stats_t* out) {
     P->ev_used = 0;
     P->timed_applies = 0;
   }
+  P->stats.m2l_tile_cols = P->m2l_cols;
+  P->stats.m2l_xcd_order = P->m2l_xcd ? 1 : 0;
   *out = P->stats;
+  return GQ_OK;
+}
+
+gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, void* hip_stream,
+                          gq_plan** out) {
+  g_err.clear();
+  auto t0 = std::chrono::steady_clock::now();
+  if (!plans || !out || n_plans < 1) return fail(GQ_EINVAL, "need at least one plan");
+  const unsigned allowed = GQ_FLAG_TIMING | GQ_FLAG_GRAPH | GQ_FLAG_AUTOTUNE;
+  if (flags & ~allowed) return fail(GQ_EINVAL, "unsupported batch flag");
+  if ((flags & GQ_FLAG_TIMING) && (flags & GQ_FLAG_GRAPH))
+    return fail(GQ_EINVAL, "GQ_FLAG_TIMING and GQ_FLAG_GRAPH are exclusive");
+  const gq_plan* P0 = plans[0];
+  for (int k = 0; k < n_plans; ++k) {
+    const gq_plan* P = plans[k];
+    if (!P) return fail(GQ_EINVAL, "NULL plan in batch");
+    if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "host-only plan in batch");
+    if (P->prm.p_qbx != P0->prm.p_qbx || P->prm.p_fmm != P0->prm.p_fmm ||
+        P->prm.kernel != P0->prm.kernel || P->prm.precision != P0->prm.precision ||
+        P->prm.n_densities != P0->prm.n_densities)
+      return fail(GQ_EINVAL, "batch members must share p_qbx, p_fmm, kernel, precision and "
+                             "n_densities");
+    for (int j = 0; j < k; ++j)
+      if (plans[j] == P) return fail(GQ_EINVAL, "plan listed twice in batch");
+  }
+  gq_plan* B = new (std::nothrow) gq_plan();
+  if (!B) return fail(GQ_ENOMEM, "host allocation failed");
+  B->prm = P0->prm;
+  B->prm.flags = (P0->prm.flags & ~(GQ_FLAG_TIMING | GQ_FLAG_GRAPH | GQ_FLAG_AUTOTUNE)) | flags;
+  B->np = P0->np;
+  B->nq = P0->nq;
+  for (int k = 0; k < n_plans; ++k) {
+    B->n_src += plans[k]->n_src;
+    B->n_ctr += plans[k]->n_ctr;
+    B->n_tgt += plans[k]->n_tgt;
+  }
+  B->last_stream = (hipStream_t)hip_stream;
+  gq_status st = merge_plans(B, plans, n_plans);
+  if (st == GQ_OK) st = merge_geometry(B, plans, n_plans, B->last_stream);
+  if (st == GQ_OK) st = upload_work(B);
+  if (st == GQ_OK && (flags & GQ_FLAG_AUTOTUNE)) st = autotune_m2l(B, B->last_stream);
+  if (st != GQ_OK) {
+    delete B;
+    return st;
+  }
+  B->stats.plan_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = B;
   return GQ_OK;
 }
 

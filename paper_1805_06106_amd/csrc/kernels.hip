@@ -254,10 +254,12 @@ __global__ __launch_bounds__(64) void k_p2x(int P, const int* __restrict__ boxes
 // pairs of one matrix class) Y[dst_c] += T X[src_c], T column-major np x np.
 // v_mfma_f64_16x16x4f64: D(16x16) += A(16x4) B(4x16); lane l supplies A[l%16][l/16] and
 // B[l/16][l%16] and holds D[l/16 + 4r][l%16], r = 0..3 (register r, lane l).
-// M = matrix rows, N = pairs, K = input coefficients.  A block (4 waves) walks the rows in
-// rounds of 16 row-blocks; wave w owns row-blocks w, w+4, w+8, w+12 of the round and all 4
-// column blocks (16 accumulator tiles), so each matrix element is read once per tile.  The
-// input expansions are staged in LDS in chunks of kKc coefficients; outputs are added
+// The product is formed transposed, Y^T = X^T T^T (inputs as the A operand, matrix as the
+// B operand), so that the 16 lanes sharing a register hold 16 consecutive output
+// coefficients of one destination and its atomic adds coalesce.  A block (4 waves) walks the
+// matrix rows in rounds of 16 row-blocks; wave w owns row-blocks w, w+4, w+8, w+12 of the
+// round and all column blocks of the tile, so each matrix element is read once per tile.
+// The input expansions are staged in LDS in chunks of kKc coefficients; outputs are added
 // atomically (several classes can target one box).
 // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, each with its
 // own L2, and tiles are sorted by class; block i therefore takes tile
@@ -267,14 +269,13 @@ __global__ __launch_bounds__(64) void k_p2x(int P, const int* __restrict__ boxes
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int kKc = kTransKc;
-constexpr int kXs = kTileCols + 1;  // padded LDS row (avoids same-bank staging stores)
 constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kPf64 = 2;            // K-steps of matrix prefetch, FP64 kernel
 constexpr int kPf32 = 4;            // K-steps of matrix prefetch, FP32 kernel
 
 // KIND (0 M2M, 1 L2L, 2 M2L) only names the instantiation, so that profiles tell the
 // three uses apart; the code is the same.
-template <int KIND>
+template <int KIND, int CB>
 __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict__ tile_cls,
                                                    const int* __restrict__ tile_beg,
                                                    const int* __restrict__ tile_cnt,
@@ -284,8 +285,10 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
                                                    const double* __restrict__ X,
                                                    double* __restrict__ Y, int ntile,
                                                    int per_xcd) {
+  constexpr int kXs = 16 * CB + 1;  // padded LDS row
   __shared__ double xs[2][kKc * kXs];  // double-buffered [k][col]
-  const int t = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  const int t = per_xcd ? (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds)
+                        : (int)blockIdx.x;
   if (t >= ntile) return;
   const int cls = tile_cls[t], beg = tile_beg[t], cnt = tile_cnt[t];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -296,7 +299,7 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
   // staging of one K-chunk of the input columns: lane -> k, wave w -> columns w + 4u, so
   // the column offsets are wave-uniform and live in scalar registers
   static_assert(kKc == 64, "staging maps one lane to one k of a chunk");
-  constexpr int kStage = kTileCols / 4;
+  constexpr int kStage = 16 * CB / 4;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   int64_t src_off[kStage];
 #pragma unroll
@@ -326,11 +329,11 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
     for (int i = 0; i < 4; ++i) a[i] = col[min(r0 + wave_u + 4 * i, nrb - 1) * 16];
   };
   for (int r0 = 0; r0 < nrb; r0 += 16) {
-    d4_t acc[4][4];
+    d4_t acc[4][CB];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) acc[i][cb] = (d4_t){0.0, 0.0, 0.0, 0.0};
+      for (int cb = 0; cb < CB; ++cb) acc[i][cb] = (d4_t){0.0, 0.0, 0.0, 0.0};
     double xr[kHalf];
     __syncthreads();  // the previous row pass has finished reading both buffers
     load_half(0, 0, xr);
@@ -352,12 +355,12 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
           const int st = g + d;
           double b[4];
 #pragma unroll
-          for (int cb = 0; cb < 4; ++cb) b[cb] = xb[(4 * st + lk) * kXs + cb * 16 + li];
+          for (int cb = 0; cb < CB; ++cb) b[cb] = xb[(4 * st + lk) * kXs + cb * 16 + li];
 #pragma unroll
           for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-              acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d][i], b[cb], acc[i][cb], 0, 0, 0);
+            for (int cb = 0; cb < CB; ++cb)
+              acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[cb], a[d][i], acc[i][cb], 0, 0, 0);
           load_a(r0, kc + 4 * (st + kPf64) + lk, a[d]);
         }
       }
@@ -380,17 +383,17 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
     for (int i = 0; i < 4; ++i) {
       const int rb = r0 + wave + 4 * i;
       if (rb >= nrb) continue;
+      const int row = rb * 16 + li;
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const int col = cb * 16 + li;
-        if (col >= cnt) continue;
-        double* y = Y + (int64_t)pair_dst[beg + col] * np;
+      for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = rb * 16 + lk + 4 * r;
-          if (row < np) unsafeAtomicAdd(&y[row], acc[i][cb][r]);
+          // transposed product: register r of lane l holds (pair l/16 + 4r, row l%16), so
+          // 16 lanes add 16 consecutive coefficients of one destination
+          const int col = cb * 16 + lk + 4 * r;
+          if (col < cnt && row < np)
+            unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + col] * np + row], acc[i][cb][r]);
         }
-      }
     }
   }
 }
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
 // to the FP64 expansions.  Without SPLIT only T_hi x_hi is used.
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
-template <int KIND, bool SPLIT>
+template <int KIND, int CB, bool SPLIT>
 __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restrict__ tile_cls,
                                                      const int* __restrict__ tile_beg,
                                                      const int* __restrict__ tile_cnt,
@@ -414,8 +417,10 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
                                                      const double* __restrict__ X,
                                                      double* __restrict__ Y, int ntile,
                                                      int per_xcd) {
+  constexpr int kXs = 16 * CB + 1;  // padded LDS row
   __shared__ float2 xs[2][kKc * kXs];  // double-buffered [k][col] = (hi, lo)
-  const int t = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  const int t = per_xcd ? (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds)
+                        : (int)blockIdx.x;
   if (t >= ntile) return;
   const int cls = tile_cls[t], beg = tile_beg[t], cnt = tile_cnt[t];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -424,7 +429,7 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
   const int64_t moff = (int64_t)cls * ld * kd;
   const int nrb = ld >> 4;
   static_assert(kKc == 64, "staging maps one lane to one k of a chunk");
-  constexpr int kStage = kTileCols / 4;
+  constexpr int kStage = 16 * CB / 4;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   int64_t src_off[kStage];
 #pragma unroll
@@ -459,11 +464,11 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
     }
   };
   for (int r0 = 0; r0 < nrb; r0 += 16) {
-    f4_t acc[4][4];
+    f4_t acc[4][CB];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) acc[i][cb] = (f4_t){0.f, 0.f, 0.f, 0.f};
+      for (int cb = 0; cb < CB; ++cb) acc[i][cb] = (f4_t){0.f, 0.f, 0.f, 0.f};
     double xr[kHalf];
     __syncthreads();  // the previous row pass has finished reading both buffers
     load_half(0, 0, xr);
@@ -484,18 +489,18 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
           const int st = g + d;
           float2 b[4];
 #pragma unroll
-          for (int cb = 0; cb < 4; ++cb) b[cb] = xb[(4 * st + lk) * kXs + cb * 16 + li];
+          for (int cb = 0; cb < CB; ++cb) b[cb] = xb[(4 * st + lk) * kXs + cb * 16 + li];
 #pragma unroll
           for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
+            for (int cb = 0; cb < CB; ++cb) {
               if (SPLIT) {
                 acc[i][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(ah[d][i], b[cb].y, acc[i][cb], 0, 0, 0);
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].y, ah[d][i], acc[i][cb], 0, 0, 0);
                 acc[i][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(al[d][i], b[cb].x, acc[i][cb], 0, 0, 0);
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].x, al[d][i], acc[i][cb], 0, 0, 0);
               }
-              acc[i][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[d][i], b[cb].x, acc[i][cb], 0, 0, 0);
+              acc[i][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].x, ah[d][i], acc[i][cb], 0, 0, 0);
             }
           load_a(r0, kc + 4 * (st + kPf32) + lk, ah[d], al[d]);
         }
@@ -517,18 +522,17 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
     for (int i = 0; i < 4; ++i) {
       const int rb = r0 + wave + 4 * i;
       if (rb >= nrb) continue;
+      const int row = rb * 16 + li;
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const int col = cb * 16 + li;
-        if (col >= cnt) continue;
-        double* y = Y + (int64_t)pair_dst[beg + col] * np;
+      for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          // FP32 16x16x4 accumulator layout: register r of lane l holds D[4 (l/16) + r][l%16]
-          const int row = rb * 16 + 4 * lk + r;
-          if (row < np) unsafeAtomicAdd(&y[row], (double)acc[i][cb][r]);
+          // transposed product, FP32 accumulator layout: register r of lane l holds
+          // (pair 4 (l/16) + r, row l%16)
+          const int col = cb * 16 + 4 * lk + r;
+          if (col < cnt && row < np)
+            unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + col] * np + row], (double)acc[i][cb][r]);
         }
-      }
     }
   }
 }
@@ -1159,30 +1163,45 @@ void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
     launch_p2x<0, true>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
 }
 
-void launch_translate(hipStream_t s, int kind, int prec, int np, int ntile,
-                      const int* tile_cls, const int* tile_beg, const int* tile_cnt,
-                      const int* pair_src, const int* pair_dst, const TransMats& T,
-                      const double* X, double* Y) {
-  if (ntile <= 0) return;
-  const int per_xcd = (ntile + kXcds - 1) / kXcds;
-  const dim3 grid(per_xcd * kXcds);
+template <int CB>
+void launch_translate_cb(hipStream_t s, int kind, int prec, int np, int ntile,
+                         const int* tile_cls, const int* tile_beg, const int* tile_cnt,
+                         const int* pair_src, const int* pair_dst, const TransMats& T,
+                         const double* X, double* Y, bool xcd_order) {
+  // xcd_order: blocks are dealt round-robin over the XCDs, so tile t runs on XCD t % 8
+  // unless remapped; per_xcd = 1 with a grid of ntile reproduces plain order (t = block)
+  const int per_xcd = xcd_order ? (ntile + kXcds - 1) / kXcds : 0;
+  const dim3 grid(xcd_order ? per_xcd * kXcds : ntile);
   if (prec == 0) {
-    auto k = kind == 0 ? k_translate<0> : kind == 1 ? k_translate<1> : k_translate<2>;
+    auto k = kind == 0 ? k_translate<0, CB> : kind == 1 ? k_translate<1, CB> : k_translate<2, CB>;
     k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.t64, X, Y,
                            ntile, per_xcd);
   } else if (prec == 1) {
-    auto k = kind == 0   ? k_translate32<0, true>
-             : kind == 1 ? k_translate32<1, true>
-                         : k_translate32<2, true>;
+    auto k = kind == 0   ? k_translate32<0, CB, true>
+             : kind == 1 ? k_translate32<1, CB, true>
+                         : k_translate32<2, CB, true>;
     k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo, X,
                            Y, ntile, per_xcd);
   } else {
-    auto k = kind == 0   ? k_translate32<0, false>
-             : kind == 1 ? k_translate32<1, false>
-                         : k_translate32<2, false>;
+    auto k = kind == 0   ? k_translate32<0, CB, false>
+             : kind == 1 ? k_translate32<1, CB, false>
+                         : k_translate32<2, CB, false>;
     k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo, X,
                            Y, ntile, per_xcd);
   }
+}
+
+void launch_translate(hipStream_t s, int kind, int prec, int np, int ntile,
+                      const int* tile_cls, const int* tile_beg, const int* tile_cnt,
+                      const int* pair_src, const int* pair_dst, const TransMats& T,
+                      const double* X, double* Y, int tile_cols, bool xcd_order) {
+  if (ntile <= 0) return;
+  if (tile_cols == 32)
+    launch_translate_cb<2>(s, kind, prec, np, ntile, tile_cls, tile_beg, tile_cnt, pair_src,
+                           pair_dst, T, X, Y, xcd_order);
+  else
+    launch_translate_cb<4>(s, kind, prec, np, ntile, tile_cls, tile_beg, tile_cnt, pair_src,
+                           pair_dst, T, X, Y, xcd_order);
 }
 
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,

@@ -9,7 +9,7 @@ namespace gq {
 
 constexpr int kPmax = 20;  // highest FMM order supported by the device kernels
 constexpr int kQmax = 10;  // highest QBX order supported by the device kernels
-constexpr int kTileCols = 64;  // expansions per translation tile
+constexpr int kTileCols = 64;  // expansions per translation tile (default; 32 also built)
 constexpr int kTransKc = 64;   // K-chunk of the translation kernels
 
 // Device layout of a translation matrix of order n_p = (p+1)^2: column-major with the
@@ -49,10 +49,13 @@ struct TransMats {
 // Batched dense translations: for each tile t, Y[dst] += T[cls] X[src] for its pairs.
 // kind: 0 M2M, 1 L2L, 2 M2L (selects a separately named instantiation).
 // prec: 0 FP64 MFMA; 1 FP32 MFMA with the hi/lo split correction; 2 FP32 MFMA, hi only.
+// tile_cols: 32 or 64, the tile width the tiles were formed with; xcd_order: map
+// consecutive tiles to one XCD (else plain block order).
 void launch_translate(hipStream_t s, int kind, int prec, int np, int ntile,
                       const int* tile_cls, const int* tile_beg, const int* tile_cnt,
                       const int* pair_src, const int* pair_dst, const TransMats& T,
-                      const double* X, double* Y);
+                      const double* X, double* Y, int tile_cols = kTileCols,
+                      bool xcd_order = true);
 
 // Stages 3, 5a, 6a: QBX locals from the near sources (U, W-close, X-close).
 // Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]) (at most 64); the

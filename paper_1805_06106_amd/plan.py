@@ -15,8 +15,9 @@ class Plan:
     def __init__(self, *, src_xyz, src_w, src_normal, ctr_xyz, ctr_radius, tgt_xyz, tgt_center,
                  p_qbx, p_fmm, kernel="S", nmax=512, tcf=0.9, n_densities=1, timing=False,
                  host_only=False, lists=None, wfar_direct_max=0, precision="fp64",
-                 stream=None):
-        flags = (C.GQ_FLAG_TIMING if timing else 0) | (C.GQ_FLAG_HOST_ONLY if host_only else 0)
+                 graph=False, autotune=False, stream=None):
+        flags = ((C.GQ_FLAG_TIMING if timing else 0) | (C.GQ_FLAG_HOST_ONLY if host_only else 0)
+                 | (C.GQ_FLAG_GRAPH if graph else 0) | (C.GQ_FLAG_AUTOTUNE if autotune else 0))
         self.params = C.make_params(p_qbx, p_fmm, nmax=nmax, tcf=tcf, kernel=kernel,
                                     n_densities=n_densities, flags=flags, lists=lists,
                                     wfar_direct_max=wfar_direct_max, precision=precision)
@@ -35,6 +36,23 @@ class Plan:
         args.update(kw)
         return cls(src_xyz=w.src_xyz, src_w=w.src_w, src_normal=w.src_normal, ctr_xyz=w.ctr_xyz,
                    ctr_radius=w.ctr_radius, tgt_xyz=w.tgt_xyz, tgt_center=w.tgt_center, **args)
+
+    @classmethod
+    def batch(cls, plans, *, timing=False, graph=False, autotune=False, stream=None):
+        """Merge plans (same orders, kernel, precision and density count) into one plan whose
+        density/potential rows are the members' rows concatenated in the order given."""
+        self = cls.__new__(cls)
+        flags = ((C.GQ_FLAG_TIMING if timing else 0) | (C.GQ_FLAG_GRAPH if graph else 0)
+                 | (C.GQ_FLAG_AUTOTUNE if autotune else 0))
+        self.handle = None
+        self.handle = C.gq_batch_create([p.handle for p in plans], flags, stream=stream)
+        self.params = plans[0].params
+        self.n_src = sum(p.n_src for p in plans)
+        self.n_ctr = sum(p.n_ctr for p in plans)
+        self.n_tgt = sum(p.n_tgt for p in plans)
+        self.p_qbx = plans[0].p_qbx
+        self.n_densities = plans[0].n_densities
+        return self
 
     def apply(self, density, potential=None, stream=None):
         import torch

@@ -206,3 +206,17 @@ def test_single_box_plan(gq):
     assert s["n_boxes"] == 1
     assert s["pairs"]["U"] == w.n_src * w.n_ctr
     assert all(s["pairs"][k] == 0 for k in ("V", "Wclose", "Wfar", "Xclose", "Xfar"))
+
+
+def test_batch_and_graph_validation(gq):
+    w = workload_tiny(level=0, order=2, kernel="D", p_qbx=2, p_fmm=4, nmax=16)
+    G = gq
+    P = G.Plan(**_args(w))  # host-only
+    with pytest.raises(G.GQError) as e:
+        G.Plan.batch([P])
+    assert e.value.status == 1 and "host-only" in str(e.value)
+    with pytest.raises(G.GQError):
+        G.Plan.batch([])
+    with pytest.raises(G.GQError) as e:
+        G.Plan(**_args(w, timing=True, graph=True))
+    assert "exclusive" in str(e.value)
