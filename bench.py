@@ -41,7 +41,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "c3"],
+                    help="c2: the urchin (default); c3: the many-urchin batch (see --surfaces)")
+    ap.add_argument("--surfaces", type=int, default=8,
+                    help="c3 only: how many of the 64 batch surfaces to evaluate")
     ap.add_argument("--cpu-sample", type=int, default=128,
                     help="centers evaluated by the CPU oracle (direct QBX) for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -68,6 +71,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "c3":
+        return bench_batch(args, dev)
     if args.calibrate_copy:
         n = 1 << 27
         x = torch.ones(n, dtype=torch.float64, device=dev)
@@ -201,6 +206,93 @@ def main():
         "stage_ms": {s: round(v, 4) for s, v in stage_ms.items()},
         "plan_seconds": round(plan_wall, 3),
         "tree": {"boxes": st["n_boxes"], "levels": st["n_levels"], "pairs": st["pairs"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, dev):
+    """Many surfaces with 8 densities each: plain FP64 (one plan per surface, applied one
+    after another) against one batch plan (FP32 split translations, HIP graph, autotuned
+    M2L), and the batch plan in FP64 for reference."""
+    import numpy as np
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from workloads import workload_c3
+
+    t0 = time.time()
+    ws = [workload_c3(i) for i in range(args.surfaces)]
+    nd = ws[0].density.shape[0]
+    n_tgt = sum(w.n_tgt for w in ws)
+    n_src = sum(w.n_src for w in ws)
+    log(f"batch workload: {len(ws)} surfaces, {n_src} sources, {n_tgt} targets, {nd} densities "
+        f"({time.time() - t0:.1f}s)")
+    dens = [torch.tensor(w.density, device=dev) for w in ws]
+
+    def timed(fn, k):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / k
+
+    # plain FP64: one plan per surface
+    t0 = time.time()
+    plans = [Plan.from_workload(w, n_densities=nd, wfar_direct_max=args.wfar_direct_max)
+             for w in ws]
+    plan64_s = time.time() - t0
+    outs = [torch.empty((nd, w.n_tgt), dtype=torch.float64, device=dev) for w in ws]
+
+    def plain():
+        for P, d, o in zip(plans, dens, outs):
+            P.apply(d, o)
+
+    ms_plain = timed(plain, args.steps)
+    ref = torch.cat(outs, dim=1)
+    log(f"plain fp64: {ms_plain:.2f} ms per batch apply")
+    dall = torch.cat(dens, dim=1).contiguous()
+    res = {}
+    for prec in ("fp64", "fp32_split"):
+        t0 = time.time()
+        members = plans if prec == "fp64" else [
+            Plan.from_workload(w, n_densities=nd, wfar_direct_max=args.wfar_direct_max,
+                               precision=prec) for w in ws]
+        B = Plan.batch(members, graph=True, autotune=True)
+        if prec != "fp64":
+            for P in members:
+                P.close()
+        plan_s = time.time() - t0
+        st = B.stats()
+        out = torch.empty((nd, n_tgt), dtype=torch.float64, device=dev)
+        ms = timed(lambda: B.apply(dall, out), args.steps)
+        err = float((out - ref).abs().max() / ref.abs().max())
+        res[prec] = {"value": round(nd * n_tgt / (ms * 1e-3), 1), "ms_per_apply": round(ms, 3),
+                     "rel_err_vs_plain_fp64": err, "plan_seconds": round(plan_s, 2),
+                     "m2l_tile_cols": st["m2l_tile_cols"], "m2l_xcd_order": st["m2l_xcd_order"],
+                     "m2l_classes": st["m2l_classes"]}
+        log(f"batched {prec} + graph: {ms:.2f} ms per apply, rel err vs plain fp64 {err:.3e}")
+        B.close()
+    out = {
+        "metric": "QBX-FMM target evals/sec, batched FP32-split translations (hipGraph) vs "
+                  "plain FP64",
+        "value": res["fp32_split"]["value"],
+        "unit": "target evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["fp32_split"]["ms_per_apply"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"urchin-batch-{len(ws)}-of-64", "kernel": "D", "p_qbx": 5,
+                   "p_fmm": 15, "n_surfaces": len(ws), "n_densities": nd,
+                   "n_sources": n_src, "n_targets": n_tgt,
+                   "levels": [w.meta["level"] for w in ws],
+                   "wfar_direct_max": args.wfar_direct_max},
+        "plain_fp64": {"value": round(nd * n_tgt / (ms_plain * 1e-3), 1),
+                       "ms_per_apply": round(ms_plain, 3), "plan_seconds": round(plan64_s, 2)},
+        "batched_fp64_graph": res["fp64"],
+        "batched_fp32_split_graph": res["fp32_split"],
     }
     print(json.dumps(out), flush=True)
 

@@ -120,3 +120,21 @@ def test_batch_fp32_split(members):
         tids, o, _ = OracleFMM(w).evaluate(density_index=1)
         assert rel(pot[1, off:off + w.n_tgt][tids], o) < 1e-6
         off += w.n_tgt
+
+
+def test_autotuned_plan_matches_default(members):
+    import torch
+
+    from paper_1805_06106_amd import Plan
+
+    dev = torch.device("cuda:0")
+    w = members[1]
+    d = torch.tensor(w.density, device=dev)
+    ref = Plan.from_workload(w, n_densities=2).apply(d).cpu().numpy()
+    for prec in ("fp64", "fp32_split"):
+        print(f"[gpu] autotune {prec}", flush=True)
+        P = Plan.from_workload(w, n_densities=2, autotune=True, precision=prec)
+        st = P.stats()
+        assert st["m2l_tile_cols"] in (32, 64)
+        got = P.apply(d).cpu().numpy()
+        assert rel(got, ref) < (1e-13 if prec == "fp64" else 1e-6)

@@ -11,6 +11,8 @@ from .geometry import (  # noqa: F401
     make_workload,
     workload_c1,
     workload_c2,
+    workload_c3,
+    c3_surface_params,
     workload_c4,
     workload_tiny,
 )

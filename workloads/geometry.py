@@ -275,9 +275,15 @@ def _nodes(level: int, order: int, spec: SurfaceSpec):
 def _density_lowpass(rng, n_dens, pdir, unit_w, lmax=16):
     """Uniform(-1,1) node values smoothed by projection onto real Y_l^m, l <= lmax."""
     n = pdir.shape[0]
+    return _lowpass_project([rng.uniform(-1.0, 1.0, n) for _ in range(n_dens)], pdir, unit_w,
+                            lmax)
+
+
+def _lowpass_project(raw, pdir, unit_w, lmax=16):
+    n = pdir.shape[0]
+    n_dens = len(raw)
     out = np.empty((n_dens, n))
     nb = (lmax + 1) ** 2
-    raw = [rng.uniform(-1.0, 1.0, n) for _ in range(n_dens)]
     coef = np.zeros((n_dens, nb))
     chunk = 1 << 17
     for s in range(0, n, chunk):
@@ -349,6 +355,39 @@ def workload_c4(n_densities=1, seed=4, nmax=512):
                                           scale=(3.0, 1.0, 1.0)),
                          kernel="S", p_qbx=8, p_fmm=20, nmax=nmax, seed=seed,
                          n_densities=n_densities, density="lowpass")
+
+
+def c3_surface_params(i: int):
+    """Surface i (0..63) of the 64-surface batch: bump order k ~ U{2..10} with m = k // 2,
+    amplitude ~ U(0.05, 0.25), icosphere level ~ U{3..6}; seeded by 3000 + i."""
+    rng = np.random.default_rng(3000 + i)
+    k = int(rng.integers(2, 11))
+    amp = float(rng.uniform(0.05, 0.25))
+    level = int(rng.integers(3, 7))
+    return k, k // 2, amp, level
+
+
+def workload_c3(i: int, n_densities=8, nmax=512):
+    """Surface i of the 64-urchin batch: 28-node rule, D, 5/15; density d of surface i is
+    the smoothed recipe seeded by 3000 + 64 + 8 i + d."""
+    k, m, amp, level = c3_surface_params(i)
+    spec = SurfaceSpec(curved=True, bump_k=k, bump_m=m, bump_a=amp)
+    w = make_workload(f"urchin{k}-{20 * 4 ** level}-s{i}", level=level, order=6, spec=spec,
+                      kernel="D", p_qbx=5, p_fmm=15, nmax=nmax, seed=3000 + i, n_densities=1,
+                      density="ones")
+    raw = [np.random.default_rng(3000 + 64 + 8 * i + d).uniform(-1.0, 1.0, w.n_src)
+           for d in range(n_densities)]
+    w.density = np.ascontiguousarray(_lowpass_project(raw, w.src_dir, _unit_weights(level, 6)))
+    w.meta["density"] = "lowpass"
+    return w
+
+
+def _unit_weights(level, order):
+    verts, faces = icosphere(level)
+    A, B, C = verts[faces[:, 0]], verts[faces[:, 1]], verts[faces[:, 2]]
+    x, y, w = duffy_rule(order)
+    _, _, Fux, Fuy = _map_and_jacobian(SurfaceSpec(curved=True), A, B, C, x, y)
+    return (w[None, :] * np.linalg.norm(np.cross(Fux, Fuy), axis=2)).ravel()
 
 
 def workload_tiny(level=1, order=2, kernel="S", p_qbx=3, p_fmm=6, nmax=32, tcf=0.9,
