@@ -25,6 +25,30 @@ PEAK_FP64_VALU_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
+# HBM bytes per launch (read + write) of the main kernels on the default workload, from two
+# rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy measured in the
+# same process (profiles/hbm_traffic_urchin20480_D_q5p15.md).  Valid only for the kernel
+# source they were measured on: reported while its sha256 matches, else null.
+COUNTER_TRAFFIC = {
+    "kernels_sha256": "271d667719848b5f8c916b784a0943793e2e7fe80085e0ea2515116fcaac49e1",
+    "workload": "urchin8-20480", "wfar_direct_max": 128, "precision": "fp64",
+    "bytes_per_launch": {"p2qbxl": 5975.39e6, "m2l": 13430.74e6, "m2qbxl": 263.47e6,
+                         "l2qbxl": 938.65e6},
+}
+
+
+def counter_traffic(kernel, workload, wfar_direct_max):
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1805_06106_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    c = COUNTER_TRAFFIC
+    if (h != c["kernels_sha256"] or workload != c["workload"]
+            or wfar_direct_max != c["wfar_direct_max"]):
+        return None
+    return c["bytes_per_launch"].get(kernel)
+
 
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -128,7 +152,8 @@ def main():
     achieved = flops[dominant] / (dom_ms * 1e-3) / 1e12
     roofline = {"kernel": dominant, "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
+                "traffic": counter_traffic(dominant, w.name, args.wfar_direct_max),
                 "flops_per_launch": flops[dominant], "ms_per_launch": round(dom_ms, 4)}
     per_stage = {}
     for s, f in flops.items():
