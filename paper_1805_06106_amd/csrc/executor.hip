@@ -68,12 +68,14 @@ struct gq_plan {
 
   // host work description
   std::vector<int> p2m_boxes;
-  std::vector<int64_t> p2m_rptr, p2m_rbeg, p2m_rcnt;
+  std::vector<int64_t> p2m_ptr;  // item -> sources p2m_idx[ptr[i] .. ptr[i+1])
+  std::vector<int> p2m_idx;
   std::vector<TileSet> m2m_levels;  // index: child level
   TileSet m2l;
   std::vector<TileSet> l2l_levels;  // index: child level
   std::vector<int> p2l_box;
-  std::vector<int64_t> p2l_rptr, p2l_rbeg, p2l_rcnt;
+  std::vector<int64_t> p2l_ptr;
+  std::vector<int> p2l_idx;
   std::vector<int64_t> near_ptr;  // box-indexed CSR into near_idx
   std::vector<int> near_idx;      // near sources (tree positions) of each target box
   std::vector<int> k3_box, k3_c0, k3_nc;
@@ -96,11 +98,13 @@ struct gq_plan {
   double *bctr = nullptr, *bh = nullptr;
   int64_t *src_start = nullptr, *src_count = nullptr;
   int* d_p2m_boxes = nullptr;
-  int64_t *d_p2m_rptr = nullptr, *d_p2m_rbeg = nullptr, *d_p2m_rcnt = nullptr;
+  int64_t* d_p2m_ptr = nullptr;
+  int* d_p2m_idx = nullptr;
   std::vector<std::array<int*, 5>> d_m2m, d_l2l;
   std::array<int*, 5> d_m2l{};
   int *d_p2l_box = nullptr;
-  int64_t *d_p2l_rptr = nullptr, *d_p2l_rbeg = nullptr, *d_p2l_rcnt = nullptr;
+  int64_t* d_p2l_ptr = nullptr;
+  int* d_p2l_idx = nullptr;
   int64_t* d_near_ptr = nullptr;
   int* d_near_idx = nullptr;
   int *d_k3_box = nullptr, *d_k3_c0 = nullptr, *d_k3_nc = nullptr;
@@ -219,13 +223,12 @@ gq_status build_work(gq_plan* P) {
   auto on = [&](unsigned bit) { return (mask & (bit >> 8)) != 0; };
 
   // Stage 2a
-  P->p2m_rptr.push_back(0);
+  P->p2m_ptr.push_back(0);
   for (int b = 0; b < nb; ++b)
     if (T.is_leaf(b) && T.src_count[b] > 0) {
       P->p2m_boxes.push_back(b);
-      P->p2m_rbeg.push_back(T.src_start[b]);
-      P->p2m_rcnt.push_back(T.src_count[b]);
-      P->p2m_rptr.push_back((int64_t)P->p2m_rbeg.size());
+      for (int64_t k = 0; k < T.src_count[b]; ++k) P->p2m_idx.push_back((int)(T.src_start[b] + k));
+      P->p2m_ptr.push_back((int64_t)P->p2m_idx.size());
     }
   // Stage 2b, per child level (deepest first when launched)
   P->m2m_levels.assign(T.nlevels, TileSet());
@@ -273,7 +276,7 @@ gq_status build_work(gq_plan* P) {
   // Stage 6b
   if (on(GQ_LIST_XFAR)) {
     const auto& X = Ls.lst[gq::L_XFAR];
-    P->p2l_rptr.push_back(0);
+    P->p2l_ptr.push_back(0);
     for (int b = 0; b < nb; ++b) {
       if (X.size(b) == 0) continue;
       std::vector<std::pair<int64_t, int64_t>> r;
@@ -283,11 +286,9 @@ gq_status build_work(gq_plan* P) {
       }
       merge_ranges(r);
       P->p2l_box.push_back(b);
-      for (auto& x : r) {
-        P->p2l_rbeg.push_back(x.first);
-        P->p2l_rcnt.push_back(x.second);
-      }
-      P->p2l_rptr.push_back((int64_t)P->p2l_rbeg.size());
+      for (auto& x : r)
+        for (int64_t k = 0; k < x.second; ++k) P->p2l_idx.push_back((int)(x.first + k));
+      P->p2l_ptr.push_back((int64_t)P->p2l_idx.size());
     }
   }
   // Stage 7, per child level
@@ -428,9 +429,8 @@ gq_status upload_work(gq_plan* P) {
   P->tm_l2l = {P->T_l2l, P->T32_l2l[0], P->T32_l2l[1]};
   P->tm_m2l = {P->T_m2l, P->T32_m2l[0], P->T32_m2l[1]};
   GQ_TRY(upload(P, P->p2m_boxes, &P->d_p2m_boxes, s));
-  GQ_TRY(upload(P, P->p2m_rptr, &P->d_p2m_rptr, s));
-  GQ_TRY(upload(P, P->p2m_rbeg, &P->d_p2m_rbeg, s));
-  GQ_TRY(upload(P, P->p2m_rcnt, &P->d_p2m_rcnt, s));
+  GQ_TRY(upload(P, P->p2m_ptr, &P->d_p2m_ptr, s));
+  GQ_TRY(upload(P, P->p2m_idx, &P->d_p2m_idx, s));
   auto up_tiles = [&](const TileSet& t, std::array<int*, 5>& d) -> gq_status {
     GQ_TRY(upload(P, t.cls, &d[0], s));
     GQ_TRY(upload(P, t.beg, &d[1], s));
@@ -447,9 +447,8 @@ gq_status upload_work(gq_plan* P) {
   }
   GQ_TRY(up_tiles(P->m2l, P->d_m2l));
   GQ_TRY(upload(P, P->p2l_box, &P->d_p2l_box, s));
-  GQ_TRY(upload(P, P->p2l_rptr, &P->d_p2l_rptr, s));
-  GQ_TRY(upload(P, P->p2l_rbeg, &P->d_p2l_rbeg, s));
-  GQ_TRY(upload(P, P->p2l_rcnt, &P->d_p2l_rcnt, s));
+  GQ_TRY(upload(P, P->p2l_ptr, &P->d_p2l_ptr, s));
+  GQ_TRY(upload(P, P->p2l_idx, &P->d_p2l_idx, s));
   GQ_TRY(upload(P, P->near_ptr, &P->d_near_ptr, s));
   GQ_TRY(upload(P, P->near_idx, &P->d_near_idx, s));
   GQ_TRY(upload(P, P->k3_box, &P->d_k3_box, s));
@@ -502,8 +501,8 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
   std::vector<std::vector<std::array<int, 3>>> m2m(nlev), l2l(nlev);
   std::vector<std::array<int, 3>> m2l;
   std::map<int, int> cls_index;
-  B->p2m_rptr.push_back(0);
-  B->p2l_rptr.push_back(0);
+  B->p2m_ptr.push_back(0);
+  B->p2l_ptr.push_back(0);
   B->near_ptr.push_back(0);
   int64_t boff = 0, soff = 0, coff = 0, toff = 0;
   int woff = 0;
@@ -518,14 +517,12 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
     append_shifted(B->h_tgt_ctr, P->h_tgt_ctr, coff);
     append_shifted(B->h_tgt_out, P->h_tgt_out, toff);
     // Stage 2a and 6b source ranges
-    append_ptr(B->p2m_rptr, P->p2m_rptr, (int64_t)B->p2m_rbeg.size());
+    append_ptr(B->p2m_ptr, P->p2m_ptr, (int64_t)B->p2m_idx.size());
     append_shifted(B->p2m_boxes, P->p2m_boxes, bo);
-    append_shifted(B->p2m_rbeg, P->p2m_rbeg, soff);
-    B->p2m_rcnt.insert(B->p2m_rcnt.end(), P->p2m_rcnt.begin(), P->p2m_rcnt.end());
-    append_ptr(B->p2l_rptr, P->p2l_rptr, (int64_t)B->p2l_rbeg.size());
+    append_shifted(B->p2m_idx, P->p2m_idx, (int)soff);
+    append_ptr(B->p2l_ptr, P->p2l_ptr, (int64_t)B->p2l_idx.size());
     append_shifted(B->p2l_box, P->p2l_box, bo);
-    append_shifted(B->p2l_rbeg, P->p2l_rbeg, soff);
-    B->p2l_rcnt.insert(B->p2l_rcnt.end(), P->p2l_rcnt.begin(), P->p2l_rcnt.end());
+    append_shifted(B->p2l_idx, P->p2l_idx, (int)soff);
     // translations: M2M/L2L by level, M2L by offset class
     for (int l = 0; l < T.nlevels; ++l) {
       tiles_to_pairs(P->m2m_levels[l], bo, nullptr, m2m[l]);
@@ -891,8 +888,8 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     gq::launch_fill(s, P->L, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->Lq, (int64_t)P->n_ctr * P->nq, 0.0);
     GQ_TRY(mark(2));
-    gq::launch_p2m(s, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_rptr,
-                   P->d_p2m_rbeg, P->d_p2m_rcnt, P->bctr, P->bh, src, P->q, P->M);
+    gq::launch_p2m(s, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_ptr,
+                   P->d_p2m_idx, P->bctr, P->bh, src, P->q, P->M);
     GQ_TRY(mark(3));
     for (int l = T.nlevels - 1; l >= 1; --l) {
       const auto& t = P->m2m_levels[l];
@@ -905,8 +902,8 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
                          P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L, P->m2l_cols,
                          P->m2l_xcd);
     GQ_TRY(mark(5));
-    gq::launch_p2l(s, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_rptr,
-                   P->d_p2l_rbeg, P->d_p2l_rcnt, P->bctr, P->bh, src, P->q, P->L);
+    gq::launch_p2l(s, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_ptr,
+                   P->d_p2l_idx, P->bctr, P->bh, src, P->q, P->L);
     GQ_TRY(mark(6));
     for (int l = 1; l < T.nlevels; ++l) {
       const auto& t = P->l2l_levels[l];

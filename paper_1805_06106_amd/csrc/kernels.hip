@@ -61,194 +61,6 @@ __device__ __forceinline__ void fill_invtab(double* tab) {
   }
 }
 
-// Source-to-box expansions (P2M of leaf boxes, P2L of List 4 far boxes).
-//
-// One wavefront per box; each lane owns up to kSrcPerLane sources of the current batch.
-// The loops over order m and degree N of the solid-harmonic table H (H = R for P2M,
-// J = conj(I) for P2L, degrees 0..NT) are uniform across the wave: every lane advances the
-// recurrences of its own sources, the entry H_N^m weighted by each source's moment weights
-// is summed over the lane's sources, reduced across the wave with xor shuffles and added by
-// lane 0 into an LDS table.  Moments:
-//   single layer:  A = sum q H
-//   double layer:  A = sum w_z H, B = sum beta H, C = sum conj(beta) H, combined as
-//     P2M:  mu_n^m = A_{n-1}^m + B_{n-1}^{m+1} - C_{n-1}^{m-1}  (w_z = q n_z / a,
-//           beta = q (n_x - i n_y) / (2a); R ladders)
-//     P2L:  l_n^m  = A_{n+1}^m + B_{n+1}^{m+1} - C_{n+1}^{m-1}  (w_z = -q n_z / a,
-//           beta = q (n_x + i n_y) / (2a); J ladders)
-//   with H^-1 = -conj(H^1), so the order-0 output is A^0 + 2 Re(B^1).
-constexpr int kSrcPerLane = 4;
-constexpr int kTriMax = (kPmax + 2) * (kPmax + 3) / 2;  // entries with 0 <= m <= N <= kPmax+1
-
-__device__ __forceinline__ int tri(int N, int m) { return N * (N + 1) / 2 + m; }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-template <int KERN, bool IRR>
-__global__ __launch_bounds__(64) void k_p2x(int P, const int* __restrict__ boxes,
-                                            const int64_t* __restrict__ rng_ptr,
-                                            const int64_t* __restrict__ rng_beg,
-                                            const int64_t* __restrict__ rng_cnt,
-                                            const double* __restrict__ bctr,
-                                            const double* __restrict__ bh, SrcSoA src,
-                                            const double* __restrict__ q,
-                                            double* __restrict__ out) {
-  constexpr int NMOM = KERN ? 3 : 1;
-  constexpr int K = kSrcPerLane;
-  __shared__ double invtab[kInvTab * kInvTab];
-  __shared__ double res[NMOM][kTriMax][2];
-  const int NT = IRR ? P + KERN : P - KERN;
-  const int item = blockIdx.x;
-  const int b = boxes[item];
-  const int np = (P + 1) * (P + 1);
-  const int lane = threadIdx.x;
-  fill_invtab(invtab);
-  for (int i = lane; i < NMOM * kTriMax * 2; i += 64) (&res[0][0][0])[i] = 0.0;
-  __syncthreads();
-  const double a = bh[b], inv_a = 1.0 / a;
-  const double xb = bctr[3 * b], yb = bctr[3 * b + 1], zb = bctr[3 * b + 2];
-  const int64_t r0 = rng_ptr[item], r1 = rng_ptr[item + 1];
-  int64_t ns = 0;
-  for (int64_t r = r0; r < r1; ++r) ns += rng_cnt[r];
-  for (int64_t base = 0; base < ns; base += 64 * K) {
-    // load this lane's sources (flat index base + lane + 64 k over the ranges)
-    double ux[K], uy[K], uz[K], r2[K], ir2[K], w[K][NMOM][2], dr[K], di[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      int64_t f = base + lane + 64 * k;
-      int64_t si = -1;
-      if (f < ns) {
-        for (int64_t r = r0; r < r1; ++r) {
-          if (f < rng_cnt[r]) {
-            si = rng_beg[r] + f;
-            break;
-          }
-          f -= rng_cnt[r];
-        }
-      }
-      const bool ok = si >= 0;
-      const int64_t sj = ok ? si : rng_beg[r0];
-      ux[k] = (src.x[sj] - xb) * inv_a;
-      uy[k] = (src.y[sj] - yb) * inv_a;
-      uz[k] = (src.z[sj] - zb) * inv_a;
-      r2[k] = fma(ux[k], ux[k], fma(uy[k], uy[k], uz[k] * uz[k]));
-      ir2[k] = IRR ? 1.0 / r2[k] : 0.0;
-      const double qq = ok ? q[sj] : 0.0;
-      if (KERN) {
-        const double sz = IRR ? -1.0 : 1.0, sy = IRR ? 1.0 : -1.0;
-        w[k][0][0] = sz * qq * src.nz[sj] * inv_a;
-        w[k][0][1] = 0.0;
-        w[k][1][0] = 0.5 * qq * src.nx[sj] * inv_a;
-        w[k][1][1] = sy * 0.5 * qq * src.ny[sj] * inv_a;
-        w[k][NMOM - 1][0] = w[k][1][0];
-        w[k][NMOM - 1][1] = -w[k][1][1];
-      } else {
-        w[k][0][0] = qq;
-        w[k][0][1] = 0.0;
-      }
-      dr[k] = IRR ? sqrt(ir2[k]) : 1.0;
-      di[k] = 0.0;
-    }
-    for (int m = 0; m <= NT; ++m) {
-      double p1r[K], p1i[K], p2r[K], p2i[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (m > 0) {
-          double fr, fi;
-          if (IRR) {  // J_m^m = -(2m-1)(x - i y)/r^2 J_{m-1}^{m-1}
-            fr = -(2.0 * m - 1.0) * ux[k] * ir2[k];
-            fi = (2.0 * m - 1.0) * uy[k] * ir2[k];
-          } else {  // R_m^m = -(x + i y)/(2m) R_{m-1}^{m-1}
-            fr = -0.5 / m * ux[k];
-            fi = -0.5 / m * uy[k];
-          }
-          const double nr = fma(dr[k], fr, -di[k] * fi), ni = fma(dr[k], fi, di[k] * fr);
-          dr[k] = nr;
-          di[k] = ni;
-        }
-        p1r[k] = dr[k];
-        p1i[k] = di[k];
-        p2r[k] = 0.0;
-        p2i[k] = 0.0;
-      }
-      for (int N = m; N <= NT; ++N) {
-        double sum[NMOM][2];
-#pragma unroll
-        for (int t = 0; t < NMOM; ++t) sum[t][0] = sum[t][1] = 0.0;
-        const double tt = IRR ? 0.0 : invtab[N * kInvTab + m];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          double hr = p1r[k], hi = p1i[k];
-          if (N > m) {
-            if (IRR) {
-              const double c1 = (2.0 * N - 1.0) * uz[k] * ir2[k];
-              const double c2 = (double)((N - 1) * (N - 1) - m * m) * ir2[k];
-              hr = fma(c1, p1r[k], -c2 * p2r[k]);
-              hi = fma(c1, p1i[k], -c2 * p2i[k]);
-            } else {
-              const double c1 = (2.0 * N - 1.0) * uz[k];
-              hr = fma(c1, p1r[k], -r2[k] * p2r[k]) * tt;
-              hi = fma(c1, p1i[k], -r2[k] * p2i[k]) * tt;
-            }
-            p2r[k] = p1r[k];
-            p2i[k] = p1i[k];
-            p1r[k] = hr;
-            p1i[k] = hi;
-          }
-#pragma unroll
-          for (int t = 0; t < NMOM; ++t) {
-            sum[t][0] = fma(w[k][t][0], hr, fma(-w[k][t][1], hi, sum[t][0]));
-            sum[t][1] = fma(w[k][t][0], hi, fma(w[k][t][1], hr, sum[t][1]));
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < NMOM; ++t) {
-          const double sr = wave_sum(sum[t][0]), si = wave_sum(sum[t][1]);
-          if (lane == 0) {
-            res[t][tri(N, m)][0] += sr;
-            res[t][tri(N, m)][1] += si;
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  auto mom = [&](int t, int N, int m, int c) -> double { return res[t][tri(N, m)][c]; };
-  double* o = out + (int64_t)b * np;
-  for (int i = lane; i < np; i += 64) {
-    int n = (int)sqrt((double)i);
-    while (n * n > i) --n;
-    while ((n + 1) * (n + 1) <= i) ++n;
-    const int off = i - n * n;
-    const int m = (off + 1) >> 1;
-    const int c = (off == 0) ? 0 : ((off & 1) ? 0 : 1);
-    double v;
-    if (!KERN) {
-      v = mom(0, n, m, c);
-    } else {
-      const int N = IRR ? n + 1 : n - 1;
-      if (N < 0) {
-        v = 0.0;
-      } else {
-        v = (m <= N) ? mom(0, N, m, c) : 0.0;
-        if (m == 0) {
-          v += (N >= 1) ? 2.0 * mom(1, N, 1, 0) : 0.0;
-        } else {
-          if (m + 1 <= N) v += mom(1, N, m + 1, c);
-          if (m - 1 <= N) v -= mom(NMOM - 1, N, m - 1, c);
-        }
-      }
-    }
-    if (IRR)
-      o[i] += v;
-    else
-      o[i] = v;
-  }
-}
-
 // ------------------------------------------------------------------------------------
 // Batched dense translation on the FP64 matrix cores: for each tile (up to kTileCols = 64
 // pairs of one matrix class) Y[dst_c] += T X[src_c], T column-major np x np.
@@ -699,7 +511,7 @@ __global__ __launch_bounds__(64) void k_p2qbxl(const int* __restrict__ it_box,
       pf[0] = src.x[sidx];
       pf[1] = src.y[sidx];
       pf[2] = src.z[sidx];
-      if (KERN) {
+      if constexpr (KERN != 0) {
         pf[3] = qq * src.nz[sidx];
         pf[4] = 0.5 * qq * src.nx[sidx];
         pf[5] = 0.5 * qq * src.ny[sidx];
@@ -1134,33 +946,6 @@ void launch_strength(hipStream_t s, int64_t n, const int64_t* order, const doubl
                      const double* density, double* q) {
   if (n <= 0) return;
   k_strength<<<grid1d(n, 256), 256, 0, s>>>(n, order, w, density, q);
-}
-
-template <int KERN, bool IRR>
-static void launch_p2x(hipStream_t s, int p, int nitem, const int* boxes, const int64_t* rp,
-                       const int64_t* rb, const int64_t* rc, const double* bctr,
-                       const double* bh, SrcSoA src, const double* q, double* out) {
-  k_p2x<KERN, IRR><<<nitem, 64, 0, s>>>(p, boxes, rp, rb, rc, bctr, bh, src, q, out);
-}
-
-void launch_p2m(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
-                const int64_t* rng_ptr, const int64_t* rng_beg, const int64_t* rng_cnt,
-                const double* bctr, const double* bh, SrcSoA src, const double* q, double* M) {
-  if (nitem <= 0) return;
-  if (kernel)
-    launch_p2x<1, false>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, M);
-  else
-    launch_p2x<0, false>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, M);
-}
-
-void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
-                const int64_t* rng_ptr, const int64_t* rng_beg, const int64_t* rng_cnt,
-                const double* bctr, const double* bh, SrcSoA src, const double* q, double* L) {
-  if (nitem <= 0) return;
-  if (kernel)
-    launch_p2x<1, true>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
-  else
-    launch_p2x<0, true>(s, p, nitem, boxes, rng_ptr, rng_beg, rng_cnt, bctr, bh, src, q, L);
 }
 
 template <int CB>

@@ -26,18 +26,17 @@ void launch_strength(hipStream_t s, int64_t n, const int64_t* order, const doubl
                      const double* density, double* q);
 void launch_fill(hipStream_t s, double* p, int64_t n, double v);
 
-// Stage 2a: multipoles (scaled) of leaf boxes from their own sources; item i: box
-// boxes[i], source ranges [rng_ptr[i], rng_ptr[i+1]) of (rng_beg, rng_cnt).  Overwrites.
+// Stage 2a: multipoles (scaled) of leaf boxes from their own sources.  Item i: box
+// boxes[i], sources idx[ptr[i] .. ptr[i+1]) (tree positions).  Overwrites.  (kernels_p2x.hip)
 void launch_p2m(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
-                const int64_t* rng_ptr, const int64_t* rng_beg, const int64_t* rng_cnt,
-                const double* bctr, const double* bh, SrcSoA src, const double* q, double* M);
+                const int64_t* ptr, const int* idx, const double* bctr, const double* bh,
+                SrcSoA src, const double* q, double* M);
 
 // Stage 6b: box locals (scaled) of target boxes from the sources of their X-far boxes.
-// Item i: box boxes[i], source ranges [rng_ptr[i], rng_ptr[i+1]) of (rng_beg, rng_cnt).
-// Accumulates into L.
+// Item i: box boxes[i], sources idx[ptr[i] .. ptr[i+1]).  Accumulates into L.
 void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
-                const int64_t* rng_ptr, const int64_t* rng_beg, const int64_t* rng_cnt,
-                const double* bctr, const double* bh, SrcSoA src, const double* q, double* L);
+                const int64_t* ptr, const int* idx, const double* bctr, const double* bh,
+                SrcSoA src, const double* q, double* L);
 
 // Translation matrices of one kind, column-major n_p x n_p per class: FP64 (t64) or the
 // FP32 pair T = hi + lo.
