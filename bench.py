@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "c3"],
                     help="c2: the urchin (default); c3: the many-urchin batch (see --surfaces)")
+    ap.add_argument("--study", choices=["greens"], default=None,
+                    help="greens: Green's-formula accuracy sweep over p_fmm x p_qbx on the "
+                         "urchin instead of the timing run")
     ap.add_argument("--surfaces", type=int, default=8,
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
     ap.add_argument("--cpu-sample", type=int, default=128,
@@ -95,6 +98,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.study == "greens":
+        return study_greens(args, dev)
     if args.workload == "c3":
         return bench_batch(args, dev)
     if args.calibrate_copy:
@@ -233,6 +238,50 @@ def main():
         "tree": {"boxes": st["n_boxes"], "levels": st["n_levels"], "pairs": st["pairs"]},
     }
     print(json.dumps(out), flush=True)
+
+
+def study_greens(args, dev):
+    """Green's formula on the urchin (the accuracy experiment of Section 6.1): for u the
+    potential of a unit charge at (3, 1, 2), outside the surface, u = S(du/dn) - D(u) holds
+    inside, so at every node x, evaluated through its interior center,
+        E(x) = S(du/dn)(x) - D(u)(x) - u(x)
+    vanishes up to the discretization, truncation and acceleration errors.  Reported:
+    max |E| / max |u| for each p_fmm x p_qbx (p_qbx <= p_fmm), beside the a-priori factor
+    (3/4)^(p_fmm + 1) of the acceleration error."""
+    import numpy as np
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from workloads import workload_c2
+
+    w = workload_c2()
+    x0 = np.array([3.0, 1.0, 2.0])
+    d = w.src_xyz - x0
+    r = np.linalg.norm(d, axis=1)
+    u = 1.0 / r
+    dudn = -np.sum(d * w.src_normal, axis=1) / r ** 3
+    interior = np.arange(1, w.n_tgt, 2)  # targets through the centers x - r n
+    utgt = u[interior // 2]
+    rows = []
+    for p_fmm in (3, 5, 10, 15, 20):
+        for p_qbx in (3, 5, 7, 9):
+            if p_qbx > p_fmm:
+                continue
+            t0 = time.time()
+            pots = {}
+            for kern, dens in (("S", dudn), ("D", u)):
+                P = Plan.from_workload(w, kernel=kern, p_fmm=p_fmm, p_qbx=p_qbx,
+                                       wfar_direct_max=args.wfar_direct_max)
+                pots[kern] = P.apply(torch.tensor(dens[None, :], device=dev))[0].cpu().numpy()
+                P.close()
+            E = pots["S"][interior] - pots["D"][interior] - utgt
+            err = float(np.max(np.abs(E)) / np.max(np.abs(utgt)))
+            rows.append({"p_fmm": p_fmm, "p_qbx": p_qbx, "rel_err": err,
+                         "bound_factor": 0.75 ** (p_fmm + 1)})
+            log(f"p_fmm={p_fmm:2d} p_qbx={p_qbx}: {err:.3e}  ({time.time() - t0:.1f}s)")
+    print(json.dumps({"study": "greens_formula", "workload": w.name, "charge": x0.tolist(),
+                      "nmax": w.nmax, "tcf": w.tcf, "wfar_direct_max": args.wfar_direct_max,
+                      "rows": rows}), flush=True)
 
 
 def bench_batch(args, dev):
