@@ -25,6 +25,11 @@ library.  Readings taken where the paper is silent (each is listed in the design
   * Remark 4 (optional, parameter wfar_direct_max, 0 = off): a List 3 far box whose
     subtree holds at most that many sources is removed from List 3 far and its source
     leaves are added to List 3 close.
+  * The l_inf target confinement region of the earlier two-dimensional algorithm, used for
+    the cost comparison of Section 6 (parameter tcr_norm="linf"): TCR(b) is the closed box
+    of half-width |b|(1 + t_f) about x_b; a center moves to a child iff
+    |c - x_child|_inf + r_c <= |child|(1 + t_f); and a < TCR(b) iff the l_inf distance from
+    x_a to the boundary of TCR(b) is at least 3|a|: |x_a - x_b|_inf - |b|(1+t_f) >= 3|a|.
 
 Numerical steps in the order of Algorithm 5 (all coefficients complex, paper form):
   Stage 2: multipole of every needed box.  M2M of an order-p multipole is exact for the
@@ -76,9 +81,12 @@ def _dyadic_root(lo, hi):
 class OracleTree:
     """Stage 1: octree with target-confinement-restricted centers."""
 
-    def __init__(self, src, ctr, crad, tgt, nmax, tcf):
+    def __init__(self, src, ctr, crad, tgt, nmax, tcf, tcr_norm="l2"):
         src, ctr, crad, tgt = _f64(src), _f64(ctr), _f64(crad), _f64(tgt)
         self.tcf = float(tcf)
+        if tcr_norm not in ("l2", "linf"):
+            raise ValueError(tcr_norm)
+        self.linf = tcr_norm == "linf"
         self.nmax = int(nmax)
         lo = np.minimum(np.minimum(src.min(0), tgt.min(0)), (ctr - crad[:, None]).min(0))
         hi = np.maximum(np.maximum(src.max(0), tgt.max(0)), (ctr + crad[:, None]).max(0))
@@ -113,8 +121,12 @@ class OracleTree:
                 cc = np.array([child_center(o) for o in range(8)])
                 cpos = ctr[own_c[b]]
                 d = cpos - cc[oc_]
-                dist = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
-                fits = dist + crad[own_c[b]] <= (SQRT3 * hc) * (1.0 + self.tcf)
+                if self.linf:
+                    dist = np.max(np.abs(d), axis=1)
+                    fits = dist + crad[own_c[b]] <= hc * (1.0 + self.tcf)
+                else:
+                    dist = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
+                    fits = dist + crad[own_c[b]] <= (SQRT3 * hc) * (1.0 + self.tcf)
                 if len(own_s[b]) + len(own_t[b]) + int(fits.sum()) == 0:
                     continue  # subdividing would only produce empty children
                 for o in range(8):
@@ -219,7 +231,11 @@ class OracleTree:
         return m
 
     def prec_tcr(self, a, b):
-        """a < TCR(b): l2 distance from x_a to the boundary of TCR(b) is at least 3|a|."""
+        """a < TCR(b): l2 distance from x_a to the boundary of TCR(b) is at least 3|a|
+        (l_inf distance to the box-shaped TCR in the l_inf variant)."""
+        if self.linf:
+            dinf = float(np.max(np.abs(self.center[a] - self.center[b])))
+            return dinf - self.h[b] * (1.0 + self.tcf) >= 3.0 * self.h[a]
         d = self.center[a] - self.center[b]
         dist = math.sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])
         return dist - (SQRT3 * self.h[b]) * (1.0 + self.tcf) >= 3.0 * self.h[a]
@@ -408,7 +424,7 @@ class OracleFMM:
     """Tier B: GIGAQBX evaluation of the S or D layer potential."""
 
     def __init__(self, w, nmax=None, tcf=None, p_fmm=None, p_qbx=None, nthreads=0,
-                 wfar_direct_max=0):
+                 wfar_direct_max=0, tcr_norm="l2"):
         self.w = w
         self.kernel = w.kernel
         self.p = int(w.p_fmm if p_fmm is None else p_fmm)
@@ -416,7 +432,7 @@ class OracleFMM:
         self.nthreads = nthreads
         self.tree = OracleTree(w.src_xyz, w.ctr_xyz, w.ctr_radius, w.tgt_xyz,
                                w.nmax if nmax is None else nmax,
-                               w.tcf if tcf is None else tcf)
+                               w.tcf if tcf is None else tcf, tcr_norm)
         self.lists = OracleLists(self.tree, wfar_direct_max)
         self._mpole = {}
 

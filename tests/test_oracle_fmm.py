@@ -170,3 +170,37 @@ def test_remark4_partition_and_value(thr):
     ref = _tier_a(w)
     tids, pot, _ = F.evaluate()
     assert np.max(np.abs(pot - ref[tids])) / np.max(np.abs(ref)) <= 0.75 ** (w.p_fmm + 1)
+
+
+# --- the l_inf target confinement region (cost comparison of Section 6) --------------------
+
+@pytest.mark.parametrize("case", ["S-l1", "D-l2-flat", "S-l2-tf05"])
+def test_linf_tcr_partition_confinement_and_accuracy(case):
+    """With the box-shaped TCR the lists still reach every source leaf exactly once, every
+    owned center's ball lies in its box's TCR, the box TCR sits inside the ball TCR (so
+    fewer centers descend), and the result stays within the acceleration bound."""
+    w = workload_tiny(**CASES[case])
+    F = OracleFMM(w, tcr_norm="linf")
+    t = F.tree
+    for b in F.list_owner_boxes():
+        missing, multi = F.partition_check(b)
+        assert not missing and not multi, (b, missing, multi)
+    for c in range(w.n_ctr):
+        b = t.ctr_owner[c]
+        if b != 0:
+            d = w.ctr_xyz[c] - t.center[b]
+            assert np.max(np.abs(d)) + w.ctr_radius[c] <= t.h[b] * (1 + t.tcf) * (1 + 1e-15)
+            # the box TCR lies inside the ball TCR of the same box
+            assert np.linalg.norm(d) + w.ctr_radius[c] <= SQRT3 * t.h[b] * (1 + t.tcf) * (1 + 1e-15)
+    ref = _tier_a(w)
+    tids, pot, _ = F.evaluate()
+    assert np.max(np.abs(pot - ref[tids])) / np.max(np.abs(ref)) <= 0.75 ** (w.p_fmm + 1)
+
+
+def test_linf_prec_tcr_is_the_box_distance():
+    w = workload_tiny(**CASES["S-l1"])
+    t = OracleFMM(w, tcr_norm="linf").tree
+    for a in range(t.nboxes):
+        for b in range(t.nboxes):
+            dinf = np.max(np.abs(t.center[a] - t.center[b]))
+            assert t.prec_tcr(a, b) == (dinf - t.h[b] * (1 + t.tcf) >= 3 * t.h[a])
