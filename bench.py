@@ -67,9 +67,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "c3"],
                     help="c2: the urchin (default); c3: the many-urchin batch (see --surfaces)")
-    ap.add_argument("--study", choices=["greens"], default=None,
+    ap.add_argument("--study", choices=["greens", "tcr"], default=None,
                     help="greens: Green's-formula accuracy sweep over p_fmm x p_qbx on the "
-                         "urchin instead of the timing run")
+                         "urchin; tcr: modeled cost and time of the ball-shaped vs the "
+                         "box-shaped target confinement region; instead of the timing run")
     ap.add_argument("--surfaces", type=int, default=8,
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
     ap.add_argument("--cpu-sample", type=int, default=128,
@@ -100,6 +101,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.study == "greens":
         return study_greens(args, dev)
+    if args.study == "tcr":
+        return study_tcr(args, dev)
     if args.workload == "c3":
         return bench_batch(args, dev)
     if args.calibrate_copy:
@@ -282,6 +285,54 @@ def study_greens(args, dev):
     print(json.dumps({"study": "greens_formula", "workload": w.name, "charge": x0.tolist(),
                       "nmax": w.nmax, "tcf": w.tcf, "wfar_direct_max": args.wfar_direct_max,
                       "rows": rows}), flush=True)
+
+
+def study_tcr(args, dev):
+    """The cost comparison of Section 6 (Table 8) on the urchin: modeled operation counts
+    per interaction list (Table 7 model) and measured apply time, for the ball-shaped TCR
+    of this method and the box-shaped TCR of the earlier algorithm.  Remark 4 is off for
+    both, so the lists are the plain ones."""
+    import numpy as np
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from paper_1805_06106_amd import costmodel as CM
+    from workloads import workload_c2
+
+    w = workload_c2()
+    dens = torch.tensor(w.density[:1], device=dev)
+    out = {"study": "tcr_shape", "workload": w.name, "p_fmm": w.p_fmm, "p_qbx": w.p_qbx,
+           "nmax": w.nmax, "tcf": w.tcf, "rows": {}}
+    pots = {}
+    for tcr in ("linf", "l2"):
+        P = Plan.from_workload(w, tcr_norm=tcr, timing=True)
+        st = P.stats()
+        model = CM.paper_list_model(st, w.p_fmm, w.p_qbx)
+        pot = torch.empty((1, w.n_tgt), dtype=torch.float64, device=dev)
+        P.apply(dens, pot)
+        torch.cuda.synchronize()
+        P.stats()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            P.apply(dens, pot)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        st2 = P.stats()
+        k = max(st2["timed_applies"], 1)
+        pots[tcr] = pot[0].cpu().numpy()
+        out["rows"][tcr] = {"model": model, "ms_per_apply": round(ms, 3),
+                            "stage_ms": {s: round(v / k, 3) for s, v in st2["stage_ms"].items()},
+                            "n_boxes": st["n_boxes"], "n_suspended_centers":
+                            st["n_suspended_centers"], "pairs": st["pairs"]}
+        log(f"{tcr}: modeled {model['total_lists']:.3e}, {ms:.2f} ms/apply")
+        P.close()
+    out["model_ratio_l2_over_linf"] = (out["rows"]["l2"]["model"]["total_lists"]
+                                       / out["rows"]["linf"]["model"]["total_lists"])
+    out["time_ratio_l2_over_linf"] = (out["rows"]["l2"]["ms_per_apply"]
+                                      / out["rows"]["linf"]["ms_per_apply"])
+    out["rel_diff_potentials"] = float(np.max(np.abs(pots["l2"] - pots["linf"]))
+                                       / np.max(np.abs(pots["l2"])))
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args, dev):

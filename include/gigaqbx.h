@@ -86,6 +86,11 @@ typedef struct {
      sources is evaluated directly instead (its source leaves join List 3 close).  Exact
      replacement of an approximated interaction by a direct one; 0 disables it. */
   int wfar_direct_max;
+  /* Shape of the target confinement region (Section 5.2.2): 0 the ball of radius
+     sqrt(3)|b|(1 + t_f) of this method; 1 the box of half-width |b|(1 + t_f) of the
+     earlier two-dimensional algorithm, kept for the cost comparison of Section 6 (Theorem 1
+     is stated for the ball). */
+  int tcr_norm;
 } gq_params;
 
 typedef struct gq_plan gq_plan; /* opaque */

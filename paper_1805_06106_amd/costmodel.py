@@ -94,3 +94,20 @@ def apply_flops(stats: dict, p: int, q: int, kernel: str) -> dict:
         "l2qbxl": stats["n_centers"] * l2qbxl_center(p, q),
         "qbxl2p": stats["n_targets"] * qbxl2p_target(q),
     }
+
+
+def paper_list_model(stats: dict, p: int, q: int) -> dict:
+    """The per-list cost model of Section 6 (Table 7): for one (source box, target box)
+    entry, q^2 n_s n_t for Lists 1, 3-close and 4-close, p^3 for List 2, p^3 n_t for
+    List 3-far and p^2 n_s for List 4-far, summed over the plan's lists."""
+    pr = stats["pairs"]
+    out = {
+        "U": q * q * pr["U"],
+        "V": p ** 3 * pr["V"],
+        "Wclose": q * q * pr["Wclose"],
+        "Wfar": p ** 3 * pr["Wfar"],
+        "Xclose": q * q * pr["Xclose"],
+        "Xfar": p * p * pr["Xfar"],
+    }
+    out["total_lists"] = sum(out.values())
+    return out

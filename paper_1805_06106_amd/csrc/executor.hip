@@ -721,6 +721,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     return fail(GQ_EINVAL, "unknown precision");
   if (prm->n_densities < 1) return fail(GQ_EINVAL, "n_densities must be >= 1");
   if (prm->wfar_direct_max < 0) return fail(GQ_EINVAL, "wfar_direct_max must be >= 0");
+  if (prm->tcr_norm != 0 && prm->tcr_norm != 1) return fail(GQ_EINVAL, "tcr_norm must be 0 or 1");
   if ((prm->flags & GQ_FLAG_TIMING) && (prm->flags & GQ_FLAG_GRAPH))
     return fail(GQ_EINVAL, "GQ_FLAG_TIMING and GQ_FLAG_GRAPH are exclusive");
   if (prm->kernel == GQ_KERNEL_D && !src_normal) return fail(GQ_EINVAL, "double layer needs normals");
@@ -753,13 +754,14 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
   gq::TreeParams tp;
   tp.nmax = prm->nmax;
   tp.tcf = prm->tcf;
+  tp.tcr_linf = prm->tcr_norm == 1;
   std::string msg = gq::build_tree(tp, n_src, src_xyz, n_ctr, ctr_xyz, ctr_radius, n_tgt,
                                    tgt_xyz, P->tree);
   if (!msg.empty()) {
     delete P;
     return fail(GQ_EINVAL, msg);
   }
-  gq::build_lists(P->tree, prm->tcf, prm->wfar_direct_max, P->lists);
+  gq::build_lists(P->tree, prm->tcf, prm->wfar_direct_max, P->lists, tp.tcr_linf);
   P->stats.n_sources = n_src;
   P->stats.n_centers = n_ctr;
   P->stats.n_targets = n_tgt;

@@ -13,6 +13,9 @@
 //  * k-colleagues exclude the box itself; List 3's descendants are strict;
 //  * adjacent: closed cubes touch and neither box contains the other;
 //  * list entries are restricted to boxes whose subtree holds a source.
+//  * box-shaped TCR variant (tcr_linf): TCR(b) is the closed box of half-width |b|(1+t_f);
+//    a center descends iff |c - x_child|_inf + r_c <= |child|(1 + t_f), and
+//    a < TCR(b) iff |x_a - x_b|_inf - |b|(1+t_f) >= 3|a|.
 #include "planner.hpp"
 
 #include <algorithm>
@@ -122,7 +125,7 @@ std::string build_tree(const TreeParams& prm, int64_t n_src, const double* src,
         cc[o][1] = xb[1] + ((o & 2) ? hc : -hc);
         cc[o][2] = xb[2] + ((o & 4) ? hc : -hc);
       }
-      const double conf = (kSqrt3 * hc) * (1.0 + prm.tcf);
+      const double conf = prm.tcr_linf ? hc * (1.0 + prm.tcf) : (kSqrt3 * hc) * (1.0 + prm.tcf);
       std::vector<int64_t> cs[8], ct[8], cc_[8], stay;
       for (int64_t i : own_s[b]) cs[octant(src + 3 * i, xb)].push_back(i);
       for (int64_t i : own_t[b]) ct[octant(tgt + 3 * i, xb)].push_back(i);
@@ -131,7 +134,9 @@ std::string build_tree(const TreeParams& prm, int64_t n_src, const double* src,
         const double* p = ctr + 3 * i;
         int o = octant(p, xb);
         double dx = p[0] - cc[o][0], dy = p[1] - cc[o][1], dz = p[2] - cc[o][2];
-        double dist = std::sqrt((dx * dx + dy * dy) + dz * dz);
+        double dist = prm.tcr_linf
+                          ? std::max(std::fabs(dx), std::max(std::fabs(dy), std::fabs(dz)))
+                          : std::sqrt((dx * dx + dy * dy) + dz * dz);
         if (dist + crad[i] <= conf) {
           cc_[o].push_back(i);
           ++moved_c;
@@ -219,9 +224,10 @@ namespace {
 struct ListBuilder {
   const Tree& T;
   double tcf;
+  bool linf;
   std::unordered_map<CellKey, int, CellHash> cell;
 
-  ListBuilder(const Tree& t, double tf) : T(t), tcf(tf) {
+  ListBuilder(const Tree& t, double tf, bool tcr_linf) : T(t), tcf(tf), linf(tcr_linf) {
     cell.reserve(2 * T.nboxes);
     for (int b = 0; b < T.nboxes; ++b) cell[{T.level[b], T.ix[b], T.iy[b], T.iz[b]}] = b;
   }
@@ -263,6 +269,7 @@ struct ListBuilder {
   }
 
   bool prec_tcr(int a, int b) const {  // a < TCR(b)
+    if (linf) return dinf(a, b) - T.h[b] * (1.0 + tcf) >= 3.0 * T.h[a];
     double dx = T.center[3 * a] - T.center[3 * b];
     double dy = T.center[3 * a + 1] - T.center[3 * b + 1];
     double dz = T.center[3 * a + 2] - T.center[3 * b + 2];
@@ -385,9 +392,9 @@ void sort_unique(std::vector<int>& v) {
 
 }  // namespace
 
-void build_lists(const Tree& T, double tcf, int wfar_direct_max, Lists& out) {
+void build_lists(const Tree& T, double tcf, int wfar_direct_max, Lists& out, bool tcr_linf) {
   const int nb = T.nboxes;
-  ListBuilder B(T, tcf);
+  ListBuilder B(T, tcf, tcr_linf);
   out.is_target.assign(nb, 0);
   out.is_owner.assign(nb, 0);
   for (int b = 0; b < nb; ++b)

@@ -14,6 +14,7 @@ struct TreeParams {
   int nmax = 512;
   double tcf = 0.9;
   int max_level = 30;
+  bool tcr_linf = false;  // box-shaped target confinement region (cost comparison only)
 };
 
 // Octree.  Boxes are numbered breadth-first, children in octant order (bit 0: x upper,
@@ -66,7 +67,10 @@ std::string build_tree(const TreeParams& prm, int64_t n_src, const double* src_x
 // Builds all interaction lists for target and target-ancestor boxes.
 // wfar_direct_max > 0: List 3 far boxes with at most that many sources are replaced by
 // their source leaves in List 3 close (Remark 4).
-void build_lists(const Tree& tree, double tcf, int wfar_direct_max, Lists& lists);
+// tcr_linf: box-shaped TCR of half-width |b|(1 + t_f) instead of the ball of radius
+// sqrt(3)|b|(1 + t_f) (List 3 close/far split).
+void build_lists(const Tree& tree, double tcf, int wfar_direct_max, Lists& lists,
+                 bool tcr_linf = false);
 
 // Dense real-packed translation matrices in scaled form (see translations.cpp).
 int ncoef(int p);

@@ -187,3 +187,13 @@ def test_fp32_split_c1_vs_tier_b(dev):
     _, pot = run_gpu(w, dev, precision="fp32_split")
     tids, ref, _ = OracleFMM(w).evaluate()
     assert rel(pot[0][tids], ref) < 1e-6
+
+
+@pytest.mark.parametrize("case", ["S-l1-n32", "D-l2-flat", "S-l2-tf05"])
+def test_gpu_linf_tcr_vs_tier_b(dev, case):
+    """The box-shaped TCR of the cost comparison: same kernels, other lists."""
+    w = workload_tiny(**CASES[case])
+    print(f"[gpu] case={case} tcr=linf", flush=True)
+    _, pot = run_gpu(w, dev, tcr_norm="linf")
+    tids, ref, _ = OracleFMM(w, tcr_norm="linf").evaluate()
+    assert rel(pot[0][tids], ref) < TOL
