@@ -67,10 +67,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "c3"],
                     help="c2: the urchin (default); c3: the many-urchin batch (see --surfaces)")
-    ap.add_argument("--study", choices=["greens", "tcr"], default=None,
+    ap.add_argument("--study", choices=["greens", "tcr", "scaling"], default=None,
                     help="greens: Green's-formula accuracy sweep over p_fmm x p_qbx on the "
                          "urchin; tcr: modeled cost and time of the ball-shaped vs the "
-                         "box-shaped target confinement region; instead of the timing run")
+                         "box-shaped target confinement region; scaling: modeled cost (and "
+                         "time, with a GPU) over urchins of growing size; instead of the "
+                         "timing run")
     ap.add_argument("--surfaces", type=int, default=8,
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
     ap.add_argument("--cpu-sample", type=int, default=128,
@@ -97,6 +99,8 @@ def main():
     from paper_1805_06106_amd import Plan
     from paper_1805_06106_amd import costmodel as CM
 
+    if args.study == "scaling":
+        return study_scaling(args)
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.study == "greens":
@@ -284,6 +288,51 @@ def study_greens(args, dev):
             log(f"p_fmm={p_fmm:2d} p_qbx={p_qbx}: {err:.3e}  ({time.time() - t0:.1f}s)")
     print(json.dumps({"study": "greens_formula", "workload": w.name, "charge": x0.tolist(),
                       "nmax": w.nmax, "tcf": w.tcf, "wfar_direct_max": args.wfar_direct_max,
+                      "rows": rows}), flush=True)
+
+
+def study_scaling(args):
+    """Cost scaling over the urchin family (Section 6, modeled operation counts over
+    gamma_2 ... gamma_10): bump orders k = 2..10, icosphere levels growing with k, single
+    layer, p_qbx = 5, p_fmm = 15, nmax 512, t_f 0.9, Remark 4 off.  Reports the Table 7
+    model per list and per source (host plans); with a GPU also the measured apply time."""
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from paper_1805_06106_amd import costmodel as CM
+    from workloads.geometry import SurfaceSpec, make_workload
+
+    gpu = torch.cuda.is_available()
+    rows = []
+    for k, level in ((2, 3), (4, 4), (6, 4), (8, 5), (10, 5), (10, 6)):
+        w = make_workload(f"urchin{k}-L{level}", level=level, order=6,
+                          spec=SurfaceSpec(curved=True, bump_k=k, bump_m=k // 2, bump_a=0.2),
+                          kernel="S", p_qbx=5, p_fmm=15, seed=100 + k, density="ones")
+        t0 = time.time()
+        P = Plan.from_workload(w, host_only=not gpu, timing=gpu)
+        plan_s = time.time() - t0
+        st = P.stats()
+        model = CM.paper_list_model(st, w.p_fmm, w.p_qbx)
+        row = {"k": k, "level": level, "n_sources": w.n_src, "n_boxes": st["n_boxes"],
+               "model": model, "model_per_source": model["total_lists"] / w.n_src,
+               "plan_seconds": round(plan_s, 2)}
+        if gpu:
+            d = torch.ones((1, w.n_src), dtype=torch.float64, device="cuda:0")
+            pot = torch.empty((1, w.n_tgt), dtype=torch.float64, device="cuda:0")
+            P.apply(d, pot)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                P.apply(d, pot)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            row["ms_per_apply"] = round(ms, 3)
+            row["ns_per_target"] = round(ms * 1e6 / w.n_tgt, 3)
+        P.close()
+        rows.append(row)
+        log(f"k={k} level={level}: N_S={w.n_src}, modeled {model['total_lists']:.3e} "
+            f"({row['model_per_source']:.3e}/source)" + (f", {row['ms_per_apply']} ms" if gpu else ""))
+    print(json.dumps({"study": "cost_scaling", "p_fmm": 15, "p_qbx": 5, "kernel": "S",
                       "rows": rows}), flush=True)
 
 
