@@ -53,7 +53,8 @@ import math
 
 import numpy as np
 
-from . import KERNELS, _f64, _i64, _p, lib, ncoef
+from . import KERNELS, _f64, _i64, _p, eval_local, eval_mpole, lib, ncoef
+from . import m2l as _m2l_one
 
 SQRT3 = math.sqrt(3.0)
 MAX_LEVEL = 30
@@ -571,10 +572,88 @@ class OracleFMM:
                              _p(_f64(w.ctr_xyz[cl])), _p(Lmat), _p(out), self.nthreads)
         return tids, out, qloc
 
+    def point_target_owner(self):
+        """Owning box of every target (targets sit in the boxes that own them after the
+        last subdivision, as sources do)."""
+        own = np.full(self.w.n_tgt, -1, dtype=np.int64)
+        for b, ts in enumerate(self.tree.own_tgt):
+            own[ts] = b
+        return own
+
+    def evaluate_points(self, density_index=0, targets=None, lists=LIST_NAMES):
+        """Conventional targets (no QBX center, tgt_center < 0): the stages of Algorithm 5
+        for targets owned by box b.  Direct sums over the sources of List 1, List 3 close
+        and List 4 close (Stages 3, 5a, 6a), multipole evaluation of each List 3 far box
+        (Stage 5b), and the box local of b evaluated at the target (Stage 9), where the box
+        local is the sum over b and its ancestors of their own List 2 (M2L) and List 4 far
+        (P2L) locals, each evaluated directly at the target (L2L is exact).
+
+        Returns (target ids, potential)."""
+        t, L, w = self.tree, self.lists, self.w
+        p = self.p
+        kern = KERNELS[self.kernel]
+        strength = _f64(w.strengths()[density_index])
+        conv = np.nonzero(w.tgt_center < 0)[0]
+        tids = conv if targets is None else np.intersect1d(conv, np.asarray(targets))
+        owner = self.point_target_owner()
+        self._mpole = {}
+        boxes = sorted(set(int(owner[i]) for i in tids))
+        chain = {b: [b] + t.ancestors(b) for b in boxes}
+        need_local = sorted(set(a for b in boxes for a in chain[b]))
+        mp = set()
+        for a in need_local:
+            if "V" in lists:
+                mp |= L.V(a)
+        for b in boxes:
+            if "Wfar" in lists:
+                mp |= L.Wfar(b)
+        self._multipoles(sorted(mp), strength)
+        np_ = ncoef(p)
+        own_local = {a: np.zeros(np_, dtype=np.complex128) for a in need_local}
+        for a in need_local:
+            if "V" in lists:
+                for d in L.V(a):
+                    own_local[a] += _m2l_one(p, p, self._mpole[(d, "M")], t.center[d],
+                                              t.center[a])
+            if "Xfar" in lists and L.Xfar(a):
+                idx = _i64(self._sources_of(L.Xfar(a)))
+                out = np.zeros(np_, dtype=np.complex128)
+                lib().oq_p2l_shared(kern, p, 1, _p(_f64(t.center[a])), len(idx), _p(idx),
+                                    _p(_f64(w.src_xyz)), _p(_f64(w.src_normal)), _p(strength),
+                                    _p(out), self.nthreads)
+                own_local[a] += out
+        pot = np.zeros(len(tids))
+        for i, tg in enumerate(tids):
+            b = int(owner[tg])
+            x = _f64(w.tgt_xyz[tg])
+            near = set()
+            for nm in ("U", "Wclose", "Xclose"):
+                if nm in lists:
+                    near |= L.get(nm, b)
+            if near:
+                # order-0 QBX coefficient at the target itself is the point sum
+                idx = _i64(self._sources_of(near))
+                c0 = np.zeros(1, dtype=np.complex128)
+                lib().oq_p2l_shared(kern, 0, 1, _p(x), len(idx), _p(idx), _p(_f64(w.src_xyz)),
+                                    _p(_f64(w.src_normal)), _p(strength), _p(c0), self.nthreads)
+                pot[i] += eval_local(0, c0, x, x)
+            if "Wfar" in lists:
+                for d in L.Wfar(b):
+                    pot[i] += eval_mpole(p, self._mpole[(d, "M")], t.center[d], x)
+            if ("V" in lists) or ("Xfar" in lists):
+                for a in chain[b]:
+                    pot[i] += eval_local(p, own_local[a], t.center[a], x)
+        return tids, pot
+
     # --- diagnostics -------------------------------------------------------------------
 
     def target_boxes(self):
-        return sorted(set(int(b) for b in self.tree.ctr_owner))
+        """Boxes owning a QBX center or a conventional target."""
+        s = set(int(b) for b in self.tree.ctr_owner)
+        conv = np.nonzero(self.w.tgt_center < 0)[0]
+        if len(conv):
+            s |= set(int(b) for b in self.point_target_owner()[conv])
+        return sorted(s)
 
     def list_owner_boxes(self):
         """Target boxes and target-ancestor boxes."""

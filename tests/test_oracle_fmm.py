@@ -204,3 +204,38 @@ def test_linf_prec_tcr_is_the_box_distance():
         for b in range(t.nboxes):
             dinf = np.max(np.abs(t.center[a] - t.center[b]))
             assert t.prec_tcr(a, b) == (dinf - t.h[b] * (1 + t.tcf) >= 3 * t.h[a])
+
+
+# --- conventional targets (Algorithm 5 Stages 3, 5(b) and 9 for point targets) -------------
+
+def _point_direct(w, tids, d=0):
+    x = w.tgt_xyz[tids]
+    pot, _ = O.direct_qbx(w.kernel, 0, w.src_xyz, w.strengths()[d], x, x,
+                          np.arange(len(tids)), nrm=w.src_normal)
+    return pot
+
+
+@pytest.mark.parametrize("kernel", ["S", "D"])
+def test_point_targets_single_box_and_accuracy(kernel):
+    from workloads import add_point_targets
+
+    w = add_point_targets(workload_tiny(level=1, order=2, kernel=kernel, p_qbx=3, p_fmm=8,
+                                        nmax=10 ** 9), n_out=40, n_in=20)
+    F = OracleFMM(w)
+    tids, pot = F.evaluate_points()
+    assert len(tids) == 60
+    ref = _point_direct(w, tids)
+    assert np.max(np.abs(pot - ref)) <= 1e-13 * np.max(np.abs(ref))  # one box: all direct
+    w = add_point_targets(workload_tiny(level=2, order=2, kernel=kernel, p_qbx=3, p_fmm=8,
+                                        nmax=24), n_out=120, n_in=60)
+    F = OracleFMM(w)
+    for b in F.list_owner_boxes():
+        missing, multi = F.partition_check(b)
+        assert not missing and not multi
+    tids, pot = F.evaluate_points()
+    ref = _point_direct(w, tids)
+    err = np.max(np.abs(pot - ref)) / np.max(np.abs(ref))
+    assert err <= 0.75 ** (w.p_fmm + 1)
+    # and the QBX targets are unaffected by the extra points being in the tree
+    t2, p2, _ = F.evaluate()
+    assert np.all(w.tgt_center[t2] >= 0)

@@ -7,6 +7,7 @@ arrays that both sides consume.
 
 from .geometry import (  # noqa: F401
     Workload,
+    add_point_targets,
     icosphere,
     make_workload,
     workload_c1,

@@ -357,6 +357,28 @@ def workload_c4(n_densities=1, seed=4, nmax=512):
                          n_densities=n_densities, density="lowpass")
 
 
+def add_point_targets(w: Workload, n_out=200, n_in=100, r_out=(1.4, 2.0), r_in=(0.2, 0.55),
+                      seed=11) -> Workload:
+    """A copy of w with conventional targets appended (tgt_center = -1): n_out points at
+    radii r_out (outside the surface) and n_in at radii r_in (inside), uniform in
+    direction."""
+    import dataclasses
+
+    rng = np.random.default_rng(seed)
+
+    def shell(n, lo, hi):
+        v = rng.standard_normal((n, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        return v * rng.uniform(lo, hi, n)[:, None]
+
+    pts = np.concatenate([shell(n_out, *r_out), shell(n_in, *r_in)])
+    return dataclasses.replace(
+        w, name=w.name + f"+{len(pts)}pt",
+        tgt_xyz=np.concatenate([w.tgt_xyz, pts]),
+        tgt_center=np.concatenate([w.tgt_center, np.full(len(pts), -1, dtype=np.int64)]),
+        meta=dict(w.meta, point_targets=len(pts)))
+
+
 def c3_surface_params(i: int):
     """Surface i (0..63) of the 64-surface batch: bump order k ~ U{2..10} with m = k // 2,
     amplitude ~ U(0.05, 0.25), icosphere level ~ U{3..6}; seeded by 3000 + i."""
