@@ -113,6 +113,7 @@ typedef struct {
   int64_t timed_applies;
   int32_t m2l_tile_cols;    /* M2L tile width in use (64 or 32) */
   int32_t m2l_xcd_order;    /* 1: XCD-aware M2L tile order, 0: plain */
+  int64_t n_point_targets;  /* conventional targets (tgt_center = -1) */
 } gq_stats_t;
 
 /*
@@ -123,9 +124,16 @@ typedef struct {
  *   src_normal[3*n_src]                     unit normals; required for GQ_KERNEL_D, may be
  *                                           NULL for GQ_KERNEL_S
  *   n_ctr, ctr_xyz[3*n_ctr], ctr_radius[n_ctr]  QBX centers c = x +- r n (Section 2.2)
- *   n_tgt, tgt_xyz[3*n_tgt], tgt_center[n_tgt]  targets and their associated center index
+ *   n_tgt, tgt_xyz[3*n_tgt], tgt_center[n_tgt]  targets and their associated center index;
+ *                                           tgt_center = -1 makes a conventional target:
+ *                                           the plain layer potential at the point,
+ *                                           evaluated by the FMM of Algorithm 5 (direct
+ *                                           sums over the near lists, List 3 far
+ *                                           multipoles, and the box local; no QBX), for
+ *                                           points off the surface (a target on a source
+ *                                           node gives inf)
  * Errors: GQ_EINVAL for negative counts, non-finite input, p_qbx > p_fmm, radius <= 0,
- * center index out of range, missing or non-unit normals (|1-|n|| > 1e-6) for D, t_f out
+ * center index out of range (below -1 or >= n_ctr), missing or non-unit normals (|1-|n|| > 1e-6) for D, t_f out
  * of range; GQ_EUNSUPPORTED for orders beyond the compiled limits.  *out is set only on
  * success; release with gq_plan_destroy.
  */

@@ -58,7 +58,8 @@ class gq_stats_t(ctypes.Structure):
                 ("list_entries", ctypes.c_int64 * 6), ("pairs", ctypes.c_int64 * 6),
                 ("m2l_classes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
                 ("stage_ms", ctypes.c_double * 12), ("timed_applies", ctypes.c_int64),
-                ("m2l_tile_cols", ctypes.c_int32), ("m2l_xcd_order", ctypes.c_int32)]
+                ("m2l_tile_cols", ctypes.c_int32), ("m2l_xcd_order", ctypes.c_int32),
+                ("n_point_targets", ctypes.c_int64)]
 
 
 class GQError(RuntimeError):
@@ -193,6 +194,7 @@ def gq_stats(plan):
         "stage_ms": dict(zip(STAGES, list(s.stage_ms))),
         "timed_applies": s.timed_applies,
         "m2l_tile_cols": s.m2l_tile_cols, "m2l_xcd_order": bool(s.m2l_xcd_order),
+        "n_point_targets": s.n_point_targets,
     }
 
 

@@ -82,6 +82,14 @@ struct gq_plan {
   std::vector<int> wf_box;
   std::vector<int> k5_c0, k5_nc, k5_w0, k5_w1;
   std::vector<int> k8_box, k8_c0, k8_nc;
+  // conventional targets (no QBX center), in tree order grouped by owning box
+  int64_t n_pt = 0, n_qt = 0;             // point targets, QBX targets
+  std::vector<int64_t> pt_count_box;      // per box: point targets owned
+  std::vector<int64_t> pt_first_box;      // per box: its first point target
+  std::vector<int64_t> h_pt_in;           // tree position -> input target index
+  std::vector<int> h_pt_box;              // tree position -> owning box
+  std::vector<int> pp_box, pp_t0, pp_nt;  // direct-sum items
+  std::vector<int> pm_t0, pm_nt, pm_w0, pm_w1;  // multipole-evaluation items
   std::vector<int> cls_keys;           // M2L class index -> offset key
   int m2l_cols = gq::kTileCols;        // M2L tile width (32 or 64)
   bool m2l_xcd = true;                 // XCD-aware M2L tile order
@@ -111,6 +119,11 @@ struct gq_plan {
   int* d_wf_box = nullptr;
   int *d_k5_c0 = nullptr, *d_k5_nc = nullptr, *d_k5_w0 = nullptr, *d_k5_w1 = nullptr;
   int *d_k8_box = nullptr, *d_k8_c0 = nullptr, *d_k8_nc = nullptr;
+  double *px = nullptr, *py = nullptr, *pz = nullptr, *phi = nullptr;
+  int* d_pt_box = nullptr;
+  int64_t* d_pt_out = nullptr;
+  int *d_pp_box = nullptr, *d_pp_t0 = nullptr, *d_pp_nt = nullptr;
+  int *d_pm_t0 = nullptr, *d_pm_nt = nullptr, *d_pm_w0 = nullptr, *d_pm_w1 = nullptr;
   double *T_m2m = nullptr, *T_l2l = nullptr, *T_m2l = nullptr;
   float *T32_m2m[2] = {nullptr, nullptr}, *T32_l2l[2] = {nullptr, nullptr},
         *T32_m2l[2] = {nullptr, nullptr};  // (hi, lo)
@@ -324,6 +337,13 @@ gq_status build_work(gq_plan* P) {
       for (auto& x : r)
         for (int64_t k = 0; k < x.second; ++k) P->near_idx.push_back((int)(x.first + k));
       if (!r.empty()) center_items(T, b, 64, P->k3_box, P->k3_c0, P->k3_nc);
+      const int64_t npt_b = P->pt_count_box.empty() ? 0 : P->pt_count_box[b];
+      if (npt_b > 0 && !r.empty())
+        for (int64_t o = 0; o < npt_b; o += 64) {
+          P->pp_box.push_back(b);
+          P->pp_t0.push_back((int)(P->pt_first_box[b] + o));
+          P->pp_nt.push_back((int)std::min<int64_t>(64, npt_b - o));
+        }
       if (on(GQ_LIST_WFAR)) {
         const auto& W = Ls.lst[gq::L_WFAR];
         const int w0 = (int)P->wf_box.size();
@@ -337,6 +357,13 @@ gq_status build_work(gq_plan* P) {
             P->k5_nc.push_back((int)std::min<int64_t>(64, T.ctr_count[b] - o));
             P->k5_w0.push_back(ws);
             P->k5_w1.push_back(std::min(w1, ws + kWfarChunk));
+          }
+        if (w1 > w0)
+          for (int64_t o = 0; o < npt_b; o += 64) {
+            P->pm_t0.push_back((int)(P->pt_first_box[b] + o));
+            P->pm_nt.push_back((int)std::min<int64_t>(64, npt_b - o));
+            P->pm_w0.push_back(w0);
+            P->pm_w1.push_back(w1);
           }
       }
       center_items(T, b, 64, P->k8_box, P->k8_c0, P->k8_nc);
@@ -462,6 +489,13 @@ gq_status upload_work(gq_plan* P) {
   GQ_TRY(upload(P, P->k8_box, &P->d_k8_box, s));
   GQ_TRY(upload(P, P->k8_c0, &P->d_k8_c0, s));
   GQ_TRY(upload(P, P->k8_nc, &P->d_k8_nc, s));
+  GQ_TRY(upload(P, P->pp_box, &P->d_pp_box, s));
+  GQ_TRY(upload(P, P->pp_t0, &P->d_pp_t0, s));
+  GQ_TRY(upload(P, P->pp_nt, &P->d_pp_nt, s));
+  GQ_TRY(upload(P, P->pm_t0, &P->d_pm_t0, s));
+  GQ_TRY(upload(P, P->pm_nt, &P->d_pm_nt, s));
+  GQ_TRY(upload(P, P->pm_w0, &P->d_pm_w0, s));
+  GQ_TRY(upload(P, P->pm_w1, &P->d_pm_w1, s));
   GQ_HIP(hipStreamSynchronize(s));  // the matrices above are host temporaries
   return GQ_OK;
 }
@@ -733,7 +767,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     if (!(ctr_radius[i] > 0.0) || !std::isfinite(ctr_radius[i]))
       return fail(GQ_EINVAL, "center radius must be positive and finite");
   for (int64_t i = 0; i < n_tgt; ++i)
-    if (tgt_center[i] < 0 || tgt_center[i] >= n_ctr) return fail(GQ_EINVAL, "tgt_center out of range");
+    if (tgt_center[i] < -1 || tgt_center[i] >= n_ctr) return fail(GQ_EINVAL, "tgt_center out of range");
   if (src_normal) {
     if (!finite3(src_normal, n_src)) return fail(GQ_EINVAL, "non-finite normal");
     for (int64_t i = 0; i < n_src; ++i) {
@@ -761,7 +795,30 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     delete P;
     return fail(GQ_EINVAL, msg);
   }
-  gq::build_lists(P->tree, prm->tcf, prm->wfar_direct_max, P->lists, tp.tcr_linf);
+  {
+    // conventional targets (tgt_center < 0), grouped by the box that owns them
+    const gq::Tree& T0 = P->tree;
+    P->pt_count_box.assign(T0.nboxes, 0);
+    P->pt_first_box.assign(T0.nboxes, 0);
+    for (int b : T0.preorder) {
+      P->pt_first_box[b] = (int64_t)P->h_pt_in.size();
+      for (int64_t k = T0.tgt_start[b]; k < T0.tgt_start[b] + T0.tgt_count[b]; ++k) {
+        const int64_t j = T0.tgt_order[k];
+        if (tgt_center[j] >= 0) continue;
+        P->h_pt_in.push_back(j);
+        P->h_pt_box.push_back(b);
+        P->pt_count_box[b] += 1;
+      }
+    }
+    P->n_pt = (int64_t)P->h_pt_in.size();
+    P->n_qt = n_tgt - P->n_pt;
+    if (P->n_pt > INT32_MAX) {
+      delete P;
+      return fail(GQ_EUNSUPPORTED, "more than 2^31 point targets");
+    }
+  }
+  gq::build_lists(P->tree, prm->tcf, prm->wfar_direct_max, P->lists, tp.tcr_linf,
+                  &P->pt_count_box);
   P->stats.n_sources = n_src;
   P->stats.n_centers = n_ctr;
   P->stats.n_targets = n_tgt;
@@ -811,14 +868,18 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
       GQ_TRY(upload(P, y, &P->cy, s));
       GQ_TRY(upload(P, z, &P->cz, s));
       // targets sorted by the tree position of their center
-      std::vector<int64_t> tord(n_tgt);
-      for (int64_t i = 0; i < n_tgt; ++i) tord[i] = i;
+      // QBX targets, sorted by the tree position of their center
+      std::vector<int64_t> tord;
+      tord.reserve(P->n_qt);
+      for (int64_t i = 0; i < n_tgt; ++i)
+        if (tgt_center[i] >= 0) tord.push_back(i);
       std::stable_sort(tord.begin(), tord.end(), [&](int64_t u, int64_t v) {
         return pos[tgt_center[u]] < pos[tgt_center[v]];
       });
-      std::vector<double> tx(n_tgt), ty(n_tgt), tz(n_tgt);
-      std::vector<int64_t> tc(n_tgt);
-      for (int64_t i = 0; i < n_tgt; ++i) {
+      const int64_t nq = (int64_t)tord.size();
+      std::vector<double> tx(nq), ty(nq), tz(nq);
+      std::vector<int64_t> tc(nq);
+      for (int64_t i = 0; i < nq; ++i) {
         int64_t j = tord[i];
         tx[i] = tgt_xyz[3 * j];
         ty[i] = tgt_xyz[3 * j + 1];
@@ -832,6 +893,22 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
       GQ_TRY(upload(P, tord, &P->tgt_out, s));
       P->h_tgt_ctr.swap(tc);
       P->h_tgt_out.swap(tord);
+      // conventional targets
+      if (P->n_pt > 0) {
+        std::vector<double> a(P->n_pt), b(P->n_pt), c(P->n_pt);
+        for (int64_t i = 0; i < P->n_pt; ++i) {
+          const int64_t j = P->h_pt_in[i];
+          a[i] = tgt_xyz[3 * j];
+          b[i] = tgt_xyz[3 * j + 1];
+          c[i] = tgt_xyz[3 * j + 2];
+        }
+        GQ_TRY(upload(P, a, &P->px, s));
+        GQ_TRY(upload(P, b, &P->py, s));
+        GQ_TRY(upload(P, c, &P->pz, s));
+        GQ_TRY(upload(P, P->h_pt_box, &P->d_pt_box, s));
+        GQ_TRY(upload(P, P->h_pt_in, &P->d_pt_out, s));
+        GQ_TRY(alloc(P, (size_t)P->n_pt, &P->phi));
+      }
       GQ_TRY(upload(P, T.center, &P->bctr, s));
       GQ_TRY(upload(P, T.h, &P->bh, s));
       GQ_TRY(upload(P, T.src_start, &P->src_start, s));
@@ -889,6 +966,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     gq::launch_fill(s, P->M, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->L, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->Lq, (int64_t)P->n_ctr * P->nq, 0.0);
+    if (P->n_pt > 0) gq::launch_fill(s, P->phi, P->n_pt, 0.0);
     GQ_TRY(mark(2));
     gq::launch_p2m(s, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_ptr,
                    P->d_p2m_idx, P->bctr, P->bh, src, P->q, P->M);
@@ -917,16 +995,22 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     gq::launch_p2qbxl(s, kern, qo, (int)P->k3_box.size(), P->d_k3_box, P->d_k3_c0, P->d_k3_nc,
                       P->d_near_ptr, P->d_near_idx, src, P->q, P->cx, P->cy,
                       P->cz, P->Lq, P->n_ctr);
+    gq::launch_p2p(s, kern, (int)P->pp_box.size(), P->d_pp_box, P->d_pp_t0, P->d_pp_nt,
+                   P->d_near_ptr, P->d_near_idx, src, P->q, P->px, P->py, P->pz, P->phi);
     GQ_TRY(mark(8));
     gq::launch_m2qbxl(s, p, qo, (int)P->k5_c0.size(), P->d_k5_c0, P->d_k5_nc, P->d_k5_w0,
                       P->d_k5_w1, P->d_wf_box, P->bctr, P->bh, P->M, P->cx, P->cy, P->cz,
                       P->Lq, P->n_ctr);
+    gq::launch_m2p(s, p, (int)P->pm_t0.size(), P->d_pm_t0, P->d_pm_nt, P->d_pm_w0, P->d_pm_w1,
+                   P->d_wf_box, P->bctr, P->bh, P->M, P->px, P->py, P->pz, P->phi);
     GQ_TRY(mark(9));
     gq::launch_l2qbxl(s, p, qo, (int)P->k8_box.size(), P->d_k8_box, P->d_k8_c0, P->d_k8_nc,
                       P->bctr, P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
     GQ_TRY(mark(10));
-    gq::launch_qbxl2p(s, qo, P->n_tgt, P->tgt_ctr, P->tx, P->ty, P->tz, P->cx, P->cy, P->cz,
+    gq::launch_qbxl2p(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->cx, P->cy, P->cz,
                       P->Lq, P->n_ctr, P->tgt_out, potential + (int64_t)d * P->n_tgt);
+    gq::launch_l2p(s, p, P->n_pt, P->d_pt_box, P->bctr, P->bh, P->L, P->px, P->py, P->pz,
+                   P->phi, P->d_pt_out, potential + (int64_t)d * P->n_tgt);
     GQ_TRY(mark(11));
     GQ_HIP(hipGetLastError());
   }
@@ -1001,6 +1085,7 @@ gq_status gq_stats(gq_plan* P, gq_stats_t* out) {
     P->ev_used = 0;
     P->timed_applies = 0;
   }
+  P->stats.n_point_targets = P->n_pt;
   P->stats.m2l_tile_cols = P->m2l_cols;
   P->stats.m2l_xcd_order = P->m2l_xcd ? 1 : 0;
   *out = P->stats;
@@ -1028,6 +1113,8 @@ gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, vo
                              "n_densities");
     for (int j = 0; j < k; ++j)
       if (plans[j] == P) return fail(GQ_EINVAL, "plan listed twice in batch");
+    if (P->n_pt > 0)
+      return fail(GQ_EUNSUPPORTED, "batches of plans with conventional targets are not supported");
   }
   gq_plan* B = new (std::nothrow) gq_plan();
   if (!B) return fail(GQ_ENOMEM, "host allocation failed");
@@ -1039,6 +1126,7 @@ gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, vo
     B->n_src += plans[k]->n_src;
     B->n_ctr += plans[k]->n_ctr;
     B->n_tgt += plans[k]->n_tgt;
+    B->n_qt += plans[k]->n_qt;
   }
   B->last_stream = (hipStream_t)hip_stream;
   gq_status st = merge_plans(B, plans, n_plans);

@@ -78,6 +78,24 @@ void launch_l2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
                    const double* L, const double* cx, const double* cy, const double* cz,
                    double* Lq, int64_t nctr);
 
+// Conventional targets (kernels_pt.hip), point targets in tree order, phi accumulates:
+// Stages 3, 5a, 6a: direct sums from the box's near sources.  Item i: box it_box[i],
+// point targets [it_t0[i], it_t0[i] + it_nt[i]) (at most 64).
+void launch_p2p(hipStream_t s, int kernel, int nitem, const int* it_box, const int* it_t0,
+                const int* it_nt, const int64_t* near_ptr, const int* near_idx, SrcSoA src,
+                const double* qs, const double* px, const double* py, const double* pz,
+                double* phi);
+// Stage 5b: multipoles of List 3 far boxes wf_box[it_w0[i] .. it_w1[i]) at the item's
+// targets.
+void launch_m2p(hipStream_t s, int p, int nitem, const int* it_t0, const int* it_nt,
+                const int* it_w0, const int* it_w1, const int* wf_box, const double* bctr,
+                const double* bh, const double* M, const double* px, const double* py,
+                const double* pz, double* phi);
+// Stage 9: the owning box's local at each point target; writes out[out_idx[t]].
+void launch_l2p(hipStream_t s, int p, int64_t npt, const int* pt_box, const double* bctr,
+                const double* bh, const double* L, const double* px, const double* py,
+                const double* pz, const double* phi, const int64_t* out_idx, double* out);
+
 // Stage 9: potential at targets (tree order t -> output index out_idx[t]).
 void launch_qbxl2p(hipStream_t s, int q, int64_t ntgt, const int64_t* tgt_ctr,
                    const double* tx, const double* ty, const double* tz, const double* cx,

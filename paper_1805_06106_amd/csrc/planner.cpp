@@ -201,7 +201,13 @@ std::string build_tree(const TreeParams& prm, int64_t n_src, const double* src,
   T.src_order.clear();
   T.ctr_order.clear();
   T.ctr_box.clear();
+  T.tgt_start.assign(nb, 0);
+  T.tgt_count.assign(nb, 0);
+  T.tgt_order.clear();
   for (int b : T.preorder) {
+    T.tgt_start[b] = (int64_t)T.tgt_order.size();
+    T.tgt_count[b] = (int64_t)own_t[b].size();
+    T.tgt_order.insert(T.tgt_order.end(), own_t[b].begin(), own_t[b].end());
     T.src_start[b] = (int64_t)T.src_order.size();
     T.src_count[b] = (int64_t)own_s[b].size();
     T.src_order.insert(T.src_order.end(), own_s[b].begin(), own_s[b].end());
@@ -392,13 +398,14 @@ void sort_unique(std::vector<int>& v) {
 
 }  // namespace
 
-void build_lists(const Tree& T, double tcf, int wfar_direct_max, Lists& out, bool tcr_linf) {
+void build_lists(const Tree& T, double tcf, int wfar_direct_max, Lists& out, bool tcr_linf,
+                 const std::vector<int64_t>* point_targets) {
   const int nb = T.nboxes;
   ListBuilder B(T, tcf, tcr_linf);
   out.is_target.assign(nb, 0);
   out.is_owner.assign(nb, 0);
   for (int b = 0; b < nb; ++b)
-    if (T.ctr_count[b] > 0) {
+    if (T.ctr_count[b] > 0 || (point_targets && (*point_targets)[b] > 0)) {
       out.is_target[b] = 1;
       for (int a = b; a >= 0 && !out.is_owner[a]; a = T.parent[a]) out.is_owner[a] = 1;
     }

@@ -36,10 +36,12 @@ struct Tree {
   // ownership after renumbering
   std::vector<int64_t> src_start, src_count;  // owned sources (leaves only)
   std::vector<int64_t> ctr_start, ctr_count;  // owned centers
+  std::vector<int64_t> tgt_start, tgt_count;  // owned targets (boxes they end up in)
   std::vector<int64_t> sub_src;               // sources in subtree
   std::vector<int64_t> src_order;  // tree position -> input source index
   std::vector<int64_t> ctr_order;  // tree position -> input center index
   std::vector<int64_t> ctr_box;    // tree position -> owning box
+  std::vector<int64_t> tgt_order;  // tree position -> input target index
   bool is_leaf(int b) const { return nchild[b] == 0; }
 };
 
@@ -68,9 +70,11 @@ std::string build_tree(const TreeParams& prm, int64_t n_src, const double* src_x
 // wfar_direct_max > 0: List 3 far boxes with at most that many sources are replaced by
 // their source leaves in List 3 close (Remark 4).
 // tcr_linf: box-shaped TCR of half-width |b|(1 + t_f) instead of the ball of radius
-// sqrt(3)|b|(1 + t_f) (List 3 close/far split).
+// sqrt(3)|b|(1 + t_f) (List 3 close/far split).  point_targets[b] (optional, per box): the
+// number of conventional targets (no QBX center) box b owns; such boxes are target boxes
+// too.
 void build_lists(const Tree& tree, double tcf, int wfar_direct_max, Lists& lists,
-                 bool tcr_linf = false);
+                 bool tcr_linf = false, const std::vector<int64_t>* point_targets = nullptr);
 
 // Dense real-packed translation matrices in scaled form (see translations.cpp).
 int ncoef(int p);

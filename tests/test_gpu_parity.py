@@ -197,3 +197,26 @@ def test_gpu_linf_tcr_vs_tier_b(dev, case):
     _, pot = run_gpu(w, dev, tcr_norm="linf")
     tids, ref, _ = OracleFMM(w, tcr_norm="linf").evaluate()
     assert rel(pot[0][tids], ref) < TOL
+
+
+@pytest.mark.parametrize("kernel", ["S", "D"])
+def test_gpu_point_targets_vs_tier_b(dev, kernel):
+    """Conventional targets (tgt_center = -1) beside the QBX targets: both against the
+    oracle, and the QBX results unchanged by the extra points' presence in the lists."""
+    from workloads import add_point_targets
+
+    w = add_point_targets(workload_tiny(level=2, order=2, kernel=kernel, p_qbx=3, p_fmm=8,
+                                        nmax=24), n_out=150, n_in=70)
+    print(f"[gpu] point targets {kernel} n_tgt={w.n_tgt}", flush=True)
+    _, pot = run_gpu(w, dev)
+    F = OracleFMM(w)
+    tids, ref = F.evaluate_points()
+    assert rel(pot[0][tids], ref) < TOL
+    qt, qref, _ = F.evaluate()
+    assert rel(pot[0][qt], qref) < TOL
+    # a single box: point targets are plain direct sums
+    w1 = add_point_targets(workload_tiny(level=1, order=2, kernel=kernel, p_qbx=3, p_fmm=8,
+                                         nmax=10 ** 9), n_out=30, n_in=10)
+    _, pot1 = run_gpu(w1, dev)
+    t1, r1 = OracleFMM(w1).evaluate_points()
+    assert rel(pot1[0][t1], r1) < 1e-12

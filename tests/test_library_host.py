@@ -67,6 +67,25 @@ def test_planner_matches_oracle_lists(gq, case):
             assert set(items[ptr[b]:ptr[b + 1]].tolist()) == F.lists.get(nm, b), (nm, b)
 
 
+@pytest.mark.parametrize("kernel", ["S", "D"])
+def test_planner_lists_with_point_targets(gq, kernel):
+    """Boxes that own conventional targets are target boxes: their lists equal the
+    oracle's, and the plan counts the targets."""
+    from workloads import add_point_targets
+
+    w = add_point_targets(workload_tiny(level=2, order=1, kernel=kernel, p_qbx=2, p_fmm=5,
+                                        nmax=24), n_out=80, n_in=40)
+    P = gq.Plan.from_workload(w, host_only=True)
+    F = OracleFMM(w)
+    assert P.stats()["n_point_targets"] == 120
+    owners = F.list_owner_boxes()
+    targets = F.target_boxes()
+    for nm in ("U", "V", "Wclose", "Wfar", "Xclose", "Xfar"):
+        ptr, items = P.list(nm)
+        for b in (targets if nm in ("U", "Wclose", "Wfar") else owners):
+            assert set(items[ptr[b]:ptr[b + 1]].tolist()) == F.lists.get(nm, b), (nm, b)
+
+
 def test_planner_c1_matches_oracle(gq):
     w = workload_c1()
     P = gq.Plan.from_workload(w, host_only=True)
