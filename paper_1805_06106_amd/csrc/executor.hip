@@ -538,7 +538,7 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
   B->p2m_ptr.push_back(0);
   B->p2l_ptr.push_back(0);
   B->near_ptr.push_back(0);
-  int64_t boff = 0, soff = 0, coff = 0, toff = 0;
+  int64_t boff = 0, soff = 0, coff = 0, toff = 0, poff = 0;
   int woff = 0;
   gq_stats_t& S = B->stats;
   for (int k = 0; k < n; ++k) {
@@ -586,6 +586,16 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
     append_shifted(B->k8_box, P->k8_box, bo);
     append_shifted(B->k8_c0, P->k8_c0, co);
     B->k8_nc.insert(B->k8_nc.end(), P->k8_nc.begin(), P->k8_nc.end());
+    // conventional targets
+    append_shifted(B->h_pt_in, P->h_pt_in, toff);  // output index in the batch
+    append_shifted(B->h_pt_box, P->h_pt_box, bo);
+    append_shifted(B->pp_box, P->pp_box, bo);
+    append_shifted(B->pp_t0, P->pp_t0, (int)poff);
+    B->pp_nt.insert(B->pp_nt.end(), P->pp_nt.begin(), P->pp_nt.end());
+    append_shifted(B->pm_t0, P->pm_t0, (int)poff);
+    B->pm_nt.insert(B->pm_nt.end(), P->pm_nt.begin(), P->pm_nt.end());
+    append_shifted(B->pm_w0, P->pm_w0, woff);
+    append_shifted(B->pm_w1, P->pm_w1, woff);
     // statistics
     const gq_stats_t& Q = P->stats;
     S.n_sources += Q.n_sources;
@@ -602,11 +612,13 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
     soff += P->n_src;
     coff += P->n_ctr;
     toff += P->n_tgt;
+    poff += P->n_pt;
     woff += (int)P->wf_box.size();
   }
   if (boff > INT32_MAX || soff > INT32_MAX || coff > INT32_MAX)
     return fail(GQ_EUNSUPPORTED, "batch exceeds 2^31 boxes, sources or centers");
   TB.nboxes = (int)boff;
+  B->n_pt = poff;
   S.n_levels = nlev;
   S.m2l_classes = (int64_t)B->cls_keys.size();
   B->m2m_levels.assign(nlev, TileSet());
@@ -632,12 +644,13 @@ gq_status merge_geometry(gq_plan* B, gq_plan* const* plans, int n, hipStream_t s
                           {&gq_plan::cz, 1}, {&gq_plan::tx, 2}, {&gq_plan::ty, 2},
                           {&gq_plan::tz, 2}};
   for (const Field& f : fields) {
-    const int64_t total = f.which == 0 ? B->n_src : f.which == 1 ? B->n_ctr : B->n_tgt;
+    // targets: the QBX targets only (point targets are copied below)
+    const int64_t total = f.which == 0 ? B->n_src : f.which == 1 ? B->n_ctr : B->n_qt;
     GQ_TRY(alloc(B, (size_t)total, &(B->*f.arr)));
     int64_t off = 0;
     for (int k = 0; k < n; ++k) {
       const gq_plan* P = plans[k];
-      const int64_t m = f.which == 0 ? P->n_src : f.which == 1 ? P->n_ctr : P->n_tgt;
+      const int64_t m = f.which == 0 ? P->n_src : f.which == 1 ? P->n_ctr : P->n_qt;
       if (m > 0)
         GQ_HIP(hipMemcpyAsync(B->*f.arr + off, P->*f.arr, (size_t)m * sizeof(double),
                               hipMemcpyDeviceToDevice, s));
@@ -645,6 +658,22 @@ gq_status merge_geometry(gq_plan* B, gq_plan* const* plans, int n, hipStream_t s
     }
   }
   const gq::Tree& T = B->tree;
+  if (B->n_pt > 0) {
+    double* gq_plan::*pf[3] = {&gq_plan::px, &gq_plan::py, &gq_plan::pz};
+    for (auto f : pf) {
+      GQ_TRY(alloc(B, (size_t)B->n_pt, &(B->*f)));
+      int64_t off = 0;
+      for (int k = 0; k < n; ++k) {
+        if (plans[k]->n_pt > 0)
+          GQ_HIP(hipMemcpyAsync(B->*f + off, plans[k]->*f, (size_t)plans[k]->n_pt * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+        off += plans[k]->n_pt;
+      }
+    }
+    GQ_TRY(upload(B, B->h_pt_box, &B->d_pt_box, s));
+    GQ_TRY(upload(B, B->h_pt_in, &B->d_pt_out, s));
+    GQ_TRY(alloc(B, (size_t)B->n_pt, &B->phi));
+  }
   GQ_TRY(upload(B, T.src_order, &B->src_order, s));
   GQ_TRY(upload(B, B->h_tgt_ctr, &B->tgt_ctr, s));
   GQ_TRY(upload(B, B->h_tgt_out, &B->tgt_out, s));
@@ -1113,8 +1142,6 @@ gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, vo
                              "n_densities");
     for (int j = 0; j < k; ++j)
       if (plans[j] == P) return fail(GQ_EINVAL, "plan listed twice in batch");
-    if (P->n_pt > 0)
-      return fail(GQ_EUNSUPPORTED, "batches of plans with conventional targets are not supported");
   }
   gq_plan* B = new (std::nothrow) gq_plan();
   if (!B) return fail(GQ_ENOMEM, "host allocation failed");

@@ -138,3 +138,26 @@ def test_autotuned_plan_matches_default(members):
         assert st["m2l_tile_cols"] in (32, 64)
         got = P.apply(d).cpu().numpy()
         assert rel(got, ref) < (1e-13 if prec == "fp64" else 1e-6)
+
+
+def test_batch_with_point_targets(members):
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from workloads import add_point_targets
+
+    dev = torch.device("cuda:0")
+    ws = [add_point_targets(members[0], n_out=50, n_in=20, seed=1), members[1],
+          add_point_targets(members[2], n_out=30, n_in=10, seed=2)]
+    plans = [Plan.from_workload(w, n_densities=2) for w in ws]
+    singles = [p.apply(torch.tensor(w.density, device=dev)).cpu().numpy()
+               for p, w in zip(plans, ws)]
+    print("[gpu] batch with point targets", flush=True)
+    B = Plan.batch(plans, graph=True)
+    dens = torch.tensor(np.concatenate([w.density for w in ws], axis=1), device=dev)
+    pot = B.apply(dens).cpu().numpy()
+    off = 0
+    for w, ref in zip(ws, singles):
+        assert rel(pot[:, off:off + w.n_tgt], ref) < 1e-12
+        off += w.n_tgt
+    assert B.stats()["n_point_targets"] == 110
