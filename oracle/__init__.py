@@ -189,6 +189,37 @@ def direct_qbx(kernel, p_qbx, src, strength, ctr, tgt, tgt_center, nrm=None, nth
     return out, used
 
 
+def qbx_locals(kernel, p_qbx, src, strength, ctr, nrm=None, nthreads=0):
+    """Tier A QBX coefficients (paper form, order p_qbx) at each center from every source."""
+    src, strength, ctr = _f64(src), _f64(strength), _f64(ctr).reshape(-1, 3)
+    nrm = _f64(src * 0.0 if nrm is None else nrm)
+    idx = _i64(np.arange(src.shape[0]))
+    out = np.zeros((ctr.shape[0], ncoef(p_qbx)), dtype=np.complex128)
+    lib().oq_p2l_shared(KERNELS[kernel], p_qbx, ctr.shape[0], _p(ctr), len(idx), _p(idx),
+                        _p(src), _p(nrm), _p(strength), _p(out), int(nthreads))
+    return out
+
+
+def local_normal_derivative(p, L, c, t, n):
+    """d/dn of the local expansion L (order p, about c) at the point t, along the unit vector
+    n.  The expansion is re-centred at t (L2L is exact for it); its degree-1 part about t is
+    the linear term, so the derivative is that part evaluated at t + n."""
+    L1 = l2l(p, 1, L, c, t)
+    t, n = _f64(t), _f64(n)
+    return eval_local(1, L1, t, t + n) - eval_local(0, L1[:1], t, t)
+
+
+def direct_qbx_sprime(p_qbx, src, strength, ctr, tgt, tgt_center, tgt_normal, nthreads=0):
+    """Tier A for the adjoint double layer S' (the normal derivative of the single layer at
+    the target): the single-layer QBX coefficients of each target's center, differentiated
+    along the target's unit normal (local_normal_derivative)."""
+    tgt_center = _i64(tgt_center)
+    Ls = qbx_locals("S", p_qbx, src, strength, ctr, nthreads=nthreads)
+    ctr, tgt, tn = _f64(ctr).reshape(-1, 3), _f64(tgt).reshape(-1, 3), _f64(tgt_normal)
+    return np.array([local_normal_derivative(p_qbx, Ls[tgt_center[i]], ctr[tgt_center[i]],
+                                             tgt[i], tn[i]) for i in range(tgt.shape[0])])
+
+
 def direct_qbx_sampled(w, center_ids, density_index=0, nthreads=0):
     """Tier A on a subset of centers of a workload: returns (target ids, potentials)."""
     center_ids = np.asarray(center_ids, dtype=np.int64)

@@ -121,3 +121,48 @@ def test_direct_qbx_is_linear_and_matches_explicit_sum():
         for j in range(30):
             L += O.p2l(kern, 4, src[j], [qs[j]], c[0], nrm=nrm[j])
         assert abs(pot[0] - O.eval_local(4, L, c[0], t[0])) < 1e-14 * np.abs(L).max()
+
+
+# --- adjoint double layer S' = d/dn_t S (the Neumann operator) -----------------------------
+
+def _sphere_sprime(q, l, m, n_sample=64, seed=4):
+    fine = make_workload("fine", level=4, order=6, spec=SurfaceSpec(curved=True), kernel="S",
+                         p_qbx=q, p_fmm=q, density="ones")
+    coarse = make_workload("coarse", level=2, order=4, spec=SurfaceSpec(curved=True),
+                           kernel="S", p_qbx=q, p_fmm=q, density="ones")
+    idx = l * l + l + m
+    dens = real_sh_basis(l, fine.src_xyz)[idx]
+    rng = np.random.default_rng(seed)
+    cids = np.sort(rng.choice(coarse.n_ctr, n_sample, replace=False))
+    tgt = coarse.tgt_xyz[cids]
+    tn = coarse.src_normal[cids // 2]  # outward normal at each target's base node
+    d = O.direct_qbx_sprime(q, fine.src_xyz, fine.src_w * dens, coarse.ctr_xyz[cids], tgt,
+                            np.arange(len(cids)), tn)
+    return d, real_sh_basis(l, tgt)[idx], (cids % 2) == 0
+
+
+@pytest.mark.parametrize("l,m", [(1, 0), (2, 1), (3, -2)])
+def test_sprime_sphere_eigenrelation(l, m):
+    """S[Y_l] is r^l Y/(2l+1) inside and r^-(l+1) Y/(2l+1) outside the unit sphere, so its
+    radial derivative on the surface is l/(2l+1) Y from inside and -(l+1)/(2l+1) Y from
+    outside."""
+    d, y, ext = _sphere_sprime(5, l, m)
+    scale = np.abs(y).max()
+    assert np.abs(d[~ext] - l / (2 * l + 1) * y[~ext]).max() / scale < 1e-6
+    assert np.abs(d[ext] + (l + 1) / (2 * l + 1) * y[ext]).max() / scale < 5e-3
+
+
+def test_local_normal_derivative_matches_finite_differences():
+    rng = np.random.default_rng(8)
+    p = 6
+    src = rng.uniform(-1, 1, (20, 3)) * 0.3 + np.array([2.0, 0.5, -1.0])
+    c = np.array([0.1, -0.2, 0.05])
+    L = O.p2l("S", p, src, rng.standard_normal(20), c)
+    for _ in range(5):
+        t = c + rng.uniform(-0.3, 0.3, 3)
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        h = 1e-3
+        f = [O.eval_local(p, L, c, t + k * h * n) for k in (-2, -1, 1, 2)]
+        fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+        assert abs(O.local_normal_derivative(p, L, c, t, n) - fd) <= 1e-9 * max(1.0, abs(fd))
