@@ -43,7 +43,12 @@ typedef enum {
   GQ_EUNSUPPORTED = 4  /* valid but outside what this build supports (e.g. p_fmm > 20) */
 } gq_status;
 
-typedef enum { GQ_KERNEL_S = 0, GQ_KERNEL_D = 1 } gq_kernel;
+/* GQ_KERNEL_S: single layer S; GQ_KERNEL_D: double layer D (kernel dG/dn_y);
+   GQ_KERNEL_SP: adjoint double layer S' = dS/dn_t, the derivative of the single layer
+   along the target's unit normal (the Neumann operator): the QBX coefficients are S's and
+   Stage 9 differentiates the local expansion (targets with a QBX center only; the target
+   normals are given by gq_set_target_normals). */
+typedef enum { GQ_KERNEL_S = 0, GQ_KERNEL_D = 1, GQ_KERNEL_SP = 2 } gq_kernel;
 /* Arithmetic of the dense translations (M2M, M2L, L2L; Stages 2, 4, 7).  Every other
    stage, the expansions in memory and the final potential are FP64 in all modes.
    GQ_FP64        FP64 matrix cores.
@@ -155,6 +160,14 @@ gq_status gq_apply(gq_plan* plan, const double* density, double* potential, void
 /* Copy plan statistics.  With GQ_FLAG_TIMING this waits for the timed applies, sums
    their stage times into out->stage_ms and starts a new timing window. */
 gq_status gq_stats(gq_plan* plan, gq_stats_t* out);
+
+/*
+ * Target normals for GQ_KERNEL_SP: tgt_normal[3*n_tgt] unit vectors (host, input target
+ * order; copied).  Required before the first gq_apply of an S' plan; may be called again
+ * to change them.  Errors: GQ_EINVAL for a host-only or batch plan (a batch takes its
+ * members' normals), non-finite or non-unit normals.
+ */
+gq_status gq_set_target_normals(gq_plan* plan, const double* tgt_normal);
 
 /*
  * Merge plans into one batch plan (the many-surface form of Algorithm 5): each stage then

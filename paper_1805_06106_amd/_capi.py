@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgigaqbx.so")
 
 GQ_OK, GQ_EINVAL, GQ_ENOMEM, GQ_EDEVICE, GQ_EUNSUPPORTED = 0, 1, 2, 3, 4
-GQ_KERNEL_S, GQ_KERNEL_D = 0, 1
+GQ_KERNEL_S, GQ_KERNEL_D, GQ_KERNEL_SP = 0, 1, 2
 GQ_FP64 = 0
 GQ_FP32_SPLIT = 1
 GQ_FP32 = 2
@@ -40,7 +40,7 @@ STAGES = ("strength", "p2m", "m2m", "m2l", "p2l", "l2l", "p2qbxl", "m2qbxl", "l2
 
 EXPORTED = ("gq_plan_create", "gq_apply", "gq_stats", "gq_plan_destroy", "gq_last_error",
             "gq_tree_export", "gq_list_export", "gq_qbx_locals", "gq_translation_matrix",
-            "gq_batch_create")
+            "gq_batch_create", "gq_set_target_normals")
 
 
 class gq_params(ctypes.Structure):
@@ -97,6 +97,8 @@ def lib():
         L.gq_list_export.argtypes = [P, i32, P, P, ctypes.POINTER(ctypes.c_int64)]
         L.gq_qbx_locals.restype = i32
         L.gq_qbx_locals.argtypes = [P, P]
+        L.gq_set_target_normals.restype = i32
+        L.gq_set_target_normals.argtypes = [P, P]
         L.gq_batch_create.restype = i32
         L.gq_batch_create.argtypes = [i32, P, ctypes.c_uint, P, ctypes.POINTER(ctypes.c_void_p)]
         L.gq_translation_matrix.restype = i32
@@ -140,7 +142,7 @@ def gq_last_error():
 
 def make_params(p_qbx, p_fmm, nmax=512, tcf=0.9, kernel="S", n_densities=1, flags=0,
                 lists=None, wfar_direct_max=0, precision="fp64", tcr_norm="l2"):
-    k = {"S": GQ_KERNEL_S, "D": GQ_KERNEL_D}.get(kernel, kernel)
+    k = {"S": GQ_KERNEL_S, "D": GQ_KERNEL_D, "SP": GQ_KERNEL_SP}.get(kernel, kernel)
     prec = PRECISIONS.get(precision, precision)
     if lists is not None:
         for nm in lists:
@@ -164,6 +166,12 @@ def gq_plan_create(params, src_xyz, src_w, src_normal, ctr_xyz, ctr_radius, tgt_
                               _ptr(tgt_center), _stream(stream), ctypes.byref(out))
     _check(st)
     return out.value
+
+
+def gq_set_target_normals(plan, normals):
+    """normals: host (n_tgt, 3) float64 unit vectors in input target order."""
+    normals = np.ascontiguousarray(normals, dtype=np.float64)
+    _check(lib().gq_set_target_normals(ctypes.c_void_p(plan), _ptr(normals)))
 
 
 def gq_batch_create(plans, flags=0, stream=None):

@@ -120,6 +120,7 @@ struct gq_plan {
   int *d_k5_c0 = nullptr, *d_k5_nc = nullptr, *d_k5_w0 = nullptr, *d_k5_w1 = nullptr;
   int *d_k8_box = nullptr, *d_k8_c0 = nullptr, *d_k8_nc = nullptr;
   double *px = nullptr, *py = nullptr, *pz = nullptr, *phi = nullptr;
+  double *tnx = nullptr, *tny = nullptr, *tnz = nullptr;  // S': QBX target normals
   int* d_pt_box = nullptr;
   int64_t* d_pt_out = nullptr;
   int *d_pp_box = nullptr, *d_pp_t0 = nullptr, *d_pp_nt = nullptr;
@@ -658,6 +659,21 @@ gq_status merge_geometry(gq_plan* B, gq_plan* const* plans, int n, hipStream_t s
     }
   }
   const gq::Tree& T = B->tree;
+  if (B->prm.kernel == GQ_KERNEL_SP && B->n_qt > 0) {
+    double* gq_plan::*nf[3] = {&gq_plan::tnx, &gq_plan::tny, &gq_plan::tnz};
+    for (auto f : nf) {
+      GQ_TRY(alloc(B, (size_t)B->n_qt, &(B->*f)));
+      int64_t off = 0;
+      for (int k = 0; k < n; ++k) {
+        if (plans[k]->n_qt > 0 && !(plans[k]->*f))
+          return fail(GQ_EINVAL, "S' batch member without target normals");
+        if (plans[k]->n_qt > 0)
+          GQ_HIP(hipMemcpyAsync(B->*f + off, plans[k]->*f, (size_t)plans[k]->n_qt * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+        off += plans[k]->n_qt;
+      }
+    }
+  }
   if (B->n_pt > 0) {
     double* gq_plan::*pf[3] = {&gq_plan::px, &gq_plan::py, &gq_plan::pz};
     for (auto f : pf) {
@@ -778,7 +794,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
   if (prm->nmax < 1) return fail(GQ_EINVAL, "nmax must be >= 1");
   if (!(prm->tcf >= 0.0 && prm->tcf < 2.0 * std::sqrt(3.0) - 2.0))
     return fail(GQ_EINVAL, "target confinement factor outside [0, 2 sqrt(3) - 2)");
-  if (prm->kernel != GQ_KERNEL_S && prm->kernel != GQ_KERNEL_D)
+  if (prm->kernel != GQ_KERNEL_S && prm->kernel != GQ_KERNEL_D && prm->kernel != GQ_KERNEL_SP)
     return fail(GQ_EINVAL, "unknown kernel");
   if (prm->precision != GQ_FP64 && prm->precision != GQ_FP32_SPLIT && prm->precision != GQ_FP32)
     return fail(GQ_EINVAL, "unknown precision");
@@ -841,6 +857,10 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     }
     P->n_pt = (int64_t)P->h_pt_in.size();
     P->n_qt = n_tgt - P->n_pt;
+    if (P->n_pt > 0 && prm->kernel == GQ_KERNEL_SP) {
+      delete P;
+      return fail(GQ_EUNSUPPORTED, "S' is evaluated at QBX targets only (tgt_center >= 0)");
+    }
     if (P->n_pt > INT32_MAX) {
       delete P;
       return fail(GQ_EUNSUPPORTED, "more than 2^31 point targets");
@@ -972,7 +992,8 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
                        bool timing) {
   const gq::Tree& T = P->tree;
   const int p = P->prm.p_fmm, qo = P->prm.p_qbx, np = P->np;
-  const int kern = P->prm.kernel;
+  const int kern = P->prm.kernel == GQ_KERNEL_D ? 1 : 0;  // source side: S' uses S's
+  const bool sprime = P->prm.kernel == GQ_KERNEL_SP;
   const int prec = P->prm.precision;
   gq::SrcSoA src{P->sx, P->sy, P->sz, P->snx, P->sny, P->snz};
   hipEvent_t* ev = nullptr;
@@ -1036,8 +1057,13 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     gq::launch_l2qbxl(s, p, qo, (int)P->k8_box.size(), P->d_k8_box, P->d_k8_c0, P->d_k8_nc,
                       P->bctr, P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
     GQ_TRY(mark(10));
-    gq::launch_qbxl2p(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->cx, P->cy, P->cz,
-                      P->Lq, P->n_ctr, P->tgt_out, potential + (int64_t)d * P->n_tgt);
+    if (sprime)
+      gq::launch_qbxl2p_grad(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->tnx, P->tny,
+                             P->tnz, P->cx, P->cy, P->cz, P->Lq, P->n_ctr, P->tgt_out,
+                             potential + (int64_t)d * P->n_tgt);
+    else
+      gq::launch_qbxl2p(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->cx, P->cy, P->cz,
+                        P->Lq, P->n_ctr, P->tgt_out, potential + (int64_t)d * P->n_tgt);
     gq::launch_l2p(s, p, P->n_pt, P->d_pt_box, P->bctr, P->bh, P->L, P->px, P->py, P->pz,
                    P->phi, P->d_pt_out, potential + (int64_t)d * P->n_tgt);
     GQ_TRY(mark(11));
@@ -1055,6 +1081,8 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
   if (!P) return fail(GQ_EINVAL, "NULL plan");
   if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
   if (!density || !potential) return fail(GQ_EINVAL, "NULL device buffer");
+  if (P->prm.kernel == GQ_KERNEL_SP && P->n_qt > 0 && !P->tnx)
+    return fail(GQ_EINVAL, "S' needs the target normals (gq_set_target_normals)");
   hipStream_t s = (hipStream_t)hip_stream;
   P->last_stream = s;
   const bool timing = (P->prm.flags & GQ_FLAG_TIMING) != 0;
@@ -1118,6 +1146,34 @@ gq_status gq_stats(gq_plan* P, gq_stats_t* out) {
   P->stats.m2l_tile_cols = P->m2l_cols;
   P->stats.m2l_xcd_order = P->m2l_xcd ? 1 : 0;
   *out = P->stats;
+  return GQ_OK;
+}
+
+gq_status gq_set_target_normals(gq_plan* P, const double* tgt_normal) {
+  g_err.clear();
+  if (!P || !tgt_normal) return fail(GQ_EINVAL, "NULL argument");
+  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
+  if (P->h_tgt_out.size() != (size_t)P->n_qt)
+    return fail(GQ_EINVAL, "a batch plan takes its members' target normals");
+  if (!finite3(tgt_normal, P->n_tgt)) return fail(GQ_EINVAL, "non-finite normal");
+  std::vector<double> a(P->n_qt), b(P->n_qt), c(P->n_qt);
+  for (int64_t i = 0; i < P->n_qt; ++i) {
+    const double* nn = tgt_normal + 3 * P->h_tgt_out[i];
+    const double l = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    if (std::fabs(l - 1.0) > 1e-6) return fail(GQ_EINVAL, "target normals must have unit length");
+    a[i] = nn[0];
+    b[i] = nn[1];
+    c[i] = nn[2];
+  }
+  hipStream_t s = P->last_stream;
+  double** dst[3] = {&P->tnx, &P->tny, &P->tnz};
+  const std::vector<double>* src[3] = {&a, &b, &c};
+  for (int k = 0; k < 3; ++k) {
+    if (!*dst[k]) GQ_TRY(alloc(P, (size_t)P->n_qt, dst[k]));
+    GQ_HIP(hipMemcpyAsync(*dst[k], src[k]->data(), (size_t)P->n_qt * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+  }
+  GQ_HIP(hipStreamSynchronize(s));
   return GQ_OK;
 }
 

@@ -858,6 +858,92 @@ __global__ __launch_bounds__(256) void k_qbxl2p(int64_t ntgt, const int64_t* __r
   out[out_idx[t]] = phi * kInv4Pi;
 }
 
+// Stage 9 for the adjoint double layer S': the derivative of the QBX local along the
+// target's unit normal nu,
+//   phi'(t) = (1/4pi) Re sum_{n >= 1} sum_{|m| <= n} l_n^m (nu . grad) R_n^m (t - c),
+//   (nu . grad) R_n^m = nu_z R_{n-1}^m + (nu_x - i nu_y)/2 R_{n-1}^{m+1}
+//                       - (nu_x + i nu_y)/2 R_{n-1}^{m-1}   (zero where |order| > degree),
+// with l^-m = (-1)^m conj(l^m) and R^-m = (-1)^m conj(R^m).
+template <int Q>
+__global__ __launch_bounds__(256) void k_qbxl2p_grad(
+    int64_t ntgt, const int64_t* __restrict__ tgt_ctr, const double* __restrict__ tx,
+    const double* __restrict__ ty, const double* __restrict__ tz, const double* __restrict__ tnx,
+    const double* __restrict__ tny, const double* __restrict__ tnz, const double* __restrict__ cx,
+    const double* __restrict__ cy, const double* __restrict__ cz, const double* __restrict__ Lq,
+    int64_t nctr, const int64_t* __restrict__ out_idx, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntgt) return;
+  const int64_t c = tgt_ctr[t];
+  const double ux = tx[t] - cx[c], uy = ty[t] - cy[c], uz = tz[t] - cz[c];
+  const double r2 = ux * ux + uy * uy + uz * uz;
+  constexpr int K = Q > 0 ? Q : 1;  // degrees 0..Q-1 of R are needed
+  double Rr[K * (K + 1) / 2], Ri[K * (K + 1) / 2];
+  double dr = 1.0, di = 0.0;
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    if (m > 0) {  // R_m^m = -(x + i y)/(2m) R_{m-1}^{m-1}
+      const double f = -0.5 / m;
+      const double nr = f * (dr * ux - di * uy), ni = f * (dr * uy + di * ux);
+      dr = nr;
+      di = ni;
+    }
+    double p1r = dr, p1i = di, p2r = 0.0, p2i = 0.0;
+    Rr[m * (m + 1) / 2 + m] = dr;
+    Ri[m * (m + 1) / 2 + m] = di;
+#pragma unroll
+    for (int n = m + 1; n < K; ++n) {
+      const double inv = 1.0 / (double)(n * n - m * m);
+      const double c1 = (2.0 * n - 1.0) * uz;
+      const double rr = (c1 * p1r - r2 * p2r) * inv, ri = (c1 * p1i - r2 * p2i) * inv;
+      Rr[n * (n + 1) / 2 + m] = rr;
+      Ri[n * (n + 1) / 2 + m] = ri;
+      p2r = p1r;
+      p2i = p1i;
+      p1r = rr;
+      p1i = ri;
+    }
+  }
+  auto R = [&](int k, int j, double& re, double& im) {
+    const int aj = j < 0 ? -j : j;
+    if (aj > k) {
+      re = im = 0.0;
+      return;
+    }
+    re = Rr[k * (k + 1) / 2 + aj];
+    im = Ri[k * (k + 1) / 2 + aj];
+    if (j < 0) {  // R^-j = (-1)^j conj(R^j)
+      const double sg = (aj & 1) ? -1.0 : 1.0;
+      re *= sg;
+      im *= -sg;
+    }
+  };
+  const double ax = 0.5 * tnx[t], ay = 0.5 * tny[t], nz = tnz[t];
+  double sum = 0.0;
+#pragma unroll
+  for (int n = 1; n <= Q; ++n) {
+#pragma unroll
+    for (int m = -n; m <= n; ++m) {
+      const int am = m < 0 ? -m : m;
+      double lr = Lq[(int64_t)cpk_re(n, am) * nctr + c];
+      double li = am ? Lq[(int64_t)cpk_im(n, am) * nctr + c] : 0.0;
+      if (m < 0) {  // l^-m = (-1)^m conj(l^m)
+        const double sg = (am & 1) ? -1.0 : 1.0;
+        lr *= sg;
+        li *= -sg;
+      }
+      double r0r, r0i, rpr, rpi, rmr, rmi;
+      R(n - 1, m, r0r, r0i);
+      R(n - 1, m + 1, rpr, rpi);
+      R(n - 1, m - 1, rmr, rmi);
+      // D = nu_z R^m + (ax - i ay) R^(m+1) - (ax + i ay) R^(m-1)
+      const double Dr = nz * r0r + (ax * rpr + ay * rpi) - (ax * rmr - ay * rmi);
+      const double Di = nz * r0i + (ax * rpi - ay * rpr) - (ax * rmi + ay * rmr);
+      sum += lr * Dr - li * Di;
+    }
+  }
+  out[out_idx[t]] = sum * kInv4Pi;
+}
+
 // ------------------------------------------------------------------------------------
 // dispatch helpers over the compile-time QBX order
 // ------------------------------------------------------------------------------------
@@ -920,6 +1006,17 @@ struct L2qbxlGo {
                  int64_t nctr) {
     k_l2qbxl<Q><<<nitem, 64, 0, s>>>(p, it_box, it_c0, it_nc, bctr, bh, L, cx, cy, cz, Lq,
                                      nctr);
+  }
+};
+
+template <int Q>
+struct Qbxl2pGradGo {
+  static void go(hipStream_t s, int64_t ntgt, const int64_t* tgt_ctr, const double* tx,
+                 const double* ty, const double* tz, const double* tnx, const double* tny,
+                 const double* tnz, const double* cx, const double* cy, const double* cz,
+                 const double* Lq, int64_t nctr, const int64_t* out_idx, double* out) {
+    k_qbxl2p_grad<Q><<<grid1d(ntgt, 256), 256, 0, s>>>(ntgt, tgt_ctr, tx, ty, tz, tnx, tny, tnz,
+                                                       cx, cy, cz, Lq, nctr, out_idx, out);
   }
 };
 
@@ -1023,6 +1120,16 @@ void launch_qbxl2p(hipStream_t s, int q, int64_t ntgt, const int64_t* tgt_ctr,
   if (ntgt <= 0) return;
   QDispatch<Qbxl2pGo>::run(q, s, ntgt, tgt_ctr, tx, ty, tz, cx, cy, cz, Lq, nctr, out_idx,
                            out);
+}
+
+void launch_qbxl2p_grad(hipStream_t s, int q, int64_t ntgt, const int64_t* tgt_ctr,
+                        const double* tx, const double* ty, const double* tz, const double* tnx,
+                        const double* tny, const double* tnz, const double* cx, const double* cy,
+                        const double* cz, const double* Lq, int64_t nctr, const int64_t* out_idx,
+                        double* out) {
+  if (ntgt <= 0) return;
+  QDispatch<Qbxl2pGradGo>::run(q, s, ntgt, tgt_ctr, tx, ty, tz, tnx, tny, tnz, cx, cy, cz, Lq,
+                               nctr, out_idx, out);
 }
 
 }  // namespace gq

@@ -96,6 +96,14 @@ void launch_l2p(hipStream_t s, int p, int64_t npt, const int* pt_box, const doub
                 const double* bh, const double* L, const double* px, const double* py,
                 const double* pz, const double* phi, const int64_t* out_idx, double* out);
 
+// Stage 9 for the adjoint double layer: derivative of the QBX local along the target
+// normal (tnx, tny, tnz in target tree order).
+void launch_qbxl2p_grad(hipStream_t s, int q, int64_t ntgt, const int64_t* tgt_ctr,
+                        const double* tx, const double* ty, const double* tz, const double* tnx,
+                        const double* tny, const double* tnz, const double* cx, const double* cy,
+                        const double* cz, const double* Lq, int64_t nctr, const int64_t* out_idx,
+                        double* out);
+
 // Stage 9: potential at targets (tree order t -> output index out_idx[t]).
 void launch_qbxl2p(hipStream_t s, int q, int64_t ntgt, const int64_t* tgt_ctr,
                    const double* tx, const double* ty, const double* tz, const double* cx,

@@ -68,6 +68,10 @@ class Plan:
         C.gq_apply(self.handle, density, potential, stream=stream)
         return potential
 
+    def set_target_normals(self, normals):
+        """Target normals (n_tgt, 3) for the adjoint double layer (kernel "SP")."""
+        C.gq_set_target_normals(self.handle, normals)
+
     def stats(self):
         return C.gq_stats(self.handle)
 

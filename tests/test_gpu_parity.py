@@ -220,3 +220,31 @@ def test_gpu_point_targets_vs_tier_b(dev, kernel):
     _, pot1 = run_gpu(w1, dev)
     t1, r1 = OracleFMM(w1).evaluate_points()
     assert rel(pot1[0][t1], r1) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["S-l1-n32", "S-l2-tf05", "S-l2-q8p20"])
+def test_gpu_sprime_vs_tier_b(dev, case):
+    """Adjoint double layer: the single-layer QBX locals of the oracle differentiated along
+    each target's normal (the base node's normal)."""
+    import torch
+
+    from paper_1805_06106_amd import Plan
+
+    w = workload_tiny(**CASES[case])
+    print(f"[gpu] S' case={case}", flush=True)
+    tn = w.src_normal[np.arange(w.n_tgt) // 2]
+    P = Plan.from_workload(w, kernel="SP")
+    P.set_target_normals(tn)
+    pot = P.apply(torch.tensor(w.density, device=dev)).cpu().numpy()[0]
+    F = OracleFMM(w)
+    tids, _, qloc = F.evaluate()
+    ref = np.array([O.local_normal_derivative(w.p_qbx, qloc[int(w.tgt_center[t])],
+                                              w.ctr_xyz[w.tgt_center[t]], w.tgt_xyz[t], tn[t])
+                    for t in tids])
+    assert rel(pot[tids], ref) < TOL
+    # without normals the apply is refused
+    from paper_1805_06106_amd import GQError
+
+    Q = Plan.from_workload(w, kernel="SP")
+    with pytest.raises(GQError):
+        Q.apply(torch.tensor(w.density, device=dev))

@@ -241,3 +241,17 @@ def test_batch_and_graph_validation(gq):
     with pytest.raises(G.GQError) as e:
         G.Plan(**_args(w, timing=True, graph=True))
     assert "exclusive" in str(e.value)
+
+
+def test_sprime_validation(gq):
+    w = workload_tiny(level=1, order=2, kernel="S", p_qbx=2, p_fmm=4, nmax=16)
+    G = gq
+    P = G.Plan(**_args(w, kernel="SP"))  # host-only S' plan is valid
+    with pytest.raises(G.GQError):
+        P.set_target_normals(np.repeat(w.src_normal, 2, axis=0))  # host-only: no device
+    from workloads import add_point_targets
+
+    wp = add_point_targets(w, n_out=5, n_in=0)
+    with pytest.raises(G.GQError) as e:
+        G.Plan(**_args(wp, kernel="SP", host_only=False))
+    assert e.value.status == 4
