@@ -151,7 +151,8 @@ gq_status gq_plan_create(const gq_params* params, int64_t n_src, const double* s
 /*
  * Evaluate the layer potential (Algorithm 5 Stages 2-9) for params.n_densities densities.
  *   density   device, [n_densities][n_src] (row d is density d at the input source order)
- *   potential device, [n_densities][n_tgt], OVERWRITTEN (input target order)
+ *   potential device, [n_densities][n_tgt], OVERWRITTEN (input target order); may be
+ *             NULL when n_tgt = 0
  * The plan owns its workspace; concurrent applies of one plan must be serialized by the
  * caller (they share it).  Non-finite densities propagate to the output.
  */

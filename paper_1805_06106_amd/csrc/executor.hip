@@ -1080,7 +1080,7 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
   g_err.clear();
   if (!P) return fail(GQ_EINVAL, "NULL plan");
   if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
-  if (!density || !potential) return fail(GQ_EINVAL, "NULL device buffer");
+  if (!density || (!potential && P->n_tgt > 0)) return fail(GQ_EINVAL, "NULL device buffer");
   if (P->prm.kernel == GQ_KERNEL_SP && P->n_qt > 0 && !P->tnx)
     return fail(GQ_EINVAL, "S' needs the target normals (gq_set_target_normals)");
   hipStream_t s = (hipStream_t)hip_stream;
