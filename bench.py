@@ -28,21 +28,26 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # HBM bytes per launch (read + write) of the main kernels on the default workload, from two
 # rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy measured in the
 # same process (profiles/hbm_traffic_urchin20480_D_q5p15.md).  Valid only for the kernel
-# source they were measured on: reported while its sha256 matches, else null.
+# sources they were measured on (sha256 over csrc/kernels*.hip in name order): reported
+# while it matches, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "271d667719848b5f8c916b784a0943793e2e7fe80085e0ea2515116fcaac49e1",
+    "kernels_sha256": "d5c26154cfa095d05a03979dbe640350b80fad0ca8b510676ee2371afd08fc28",
     "workload": "urchin8-20480", "wfar_direct_max": 128, "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 5975.39e6, "m2l": 13430.74e6, "m2qbxl": 263.47e6,
-                         "l2qbxl": 938.65e6},
+    "bytes_per_launch": {"p2qbxl": 5.97828e+09, "m2l": 1.34249e+10, "m2qbxl": 2.6333e+08,
+                         "l2qbxl": 9.3864e+08},
 }
 
 
 def counter_traffic(kernel, workload, wfar_direct_max):
     import hashlib
 
-    src = os.path.join(ROOT, "paper_1805_06106_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()
+    csrc = os.path.join(ROOT, "paper_1805_06106_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.startswith("kernels") and name.endswith(".hip"):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    h = h.hexdigest()
     c = COUNTER_TRAFFIC
     if (h != c["kernels_sha256"] or workload != c["workload"]
             or wfar_direct_max != c["wfar_direct_max"]):
@@ -75,7 +80,7 @@ def main():
                          "timing run")
     ap.add_argument("--surfaces", type=int, default=8,
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
-    ap.add_argument("--cpu-sample", type=int, default=128,
+    ap.add_argument("--cpu-sample", type=int, default=768,
                     help="centers evaluated by the CPU oracle (direct QBX) for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true",
