@@ -68,16 +68,23 @@ def make_workload(name):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 10; 200 for --workload c5)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "c3"],
-                    help="c2: the urchin (default); c3: the many-urchin batch (see --surfaces)")
-    ap.add_argument("--study", choices=["greens", "tcr", "scaling"], default=None,
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "c3", "c5"],
+                    help="c2: the urchin (default); c3: the many-urchin batch (see --surfaces); "
+                         "c5: the urchin with its plan cached, one fresh density per step, "
+                         "split-precision translations")
+    ap.add_argument("--study", choices=["greens", "tcr", "scaling", "solve"], default=None,
                     help="greens: Green's-formula accuracy sweep over p_fmm x p_qbx on the "
                          "urchin; tcr: modeled cost and time of the ball-shaped vs the "
                          "box-shaped target confinement region; scaling: modeled cost (and "
-                         "time, with a GPU) over urchins of growing size; instead of the "
-                         "timing run")
+                         "time, with a GPU) over urchins of growing size; solve: the interior "
+                         "Dirichlet problem on an oversampled urchin by GMRES with "
+                         "split-precision applies and FP64 refinement; instead of the timing "
+                         "run")
+    ap.add_argument("--level", type=int, default=4,
+                    help="--study solve: icosphere level of the urchin's elements")
     ap.add_argument("--surfaces", type=int, default=8,
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
     ap.add_argument("--cpu-sample", type=int, default=768,
@@ -93,6 +100,8 @@ def main():
                     help="Remark 4: List 3 far boxes with at most this many sources are "
                          "evaluated directly (0 disables); 128 is the measured optimum here")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 200 if args.workload == "c5" else 10
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures a single GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -112,8 +121,12 @@ def main():
         return study_greens(args, dev)
     if args.study == "tcr":
         return study_tcr(args, dev)
+    if args.study == "solve":
+        return study_solve(args, dev)
     if args.workload == "c3":
         return bench_batch(args, dev)
+    if args.workload == "c5":
+        return bench_fresh_densities(args, dev)
     if args.calibrate_copy:
         n = 1 << 27
         x = torch.ones(n, dtype=torch.float64, device=dev)
@@ -387,6 +400,136 @@ def study_tcr(args, dev):
     out["rel_diff_potentials"] = float(np.max(np.abs(pots["l2"] - pots["linf"]))
                                        / np.max(np.abs(pots["l2"])))
     print(json.dumps(out), flush=True)
+
+
+def bench_fresh_densities(args, dev):
+    """The urchin with its plan cached and a fresh density for every apply (split-precision
+    translations, translation matrices resident in HBM): all densities are uploaded before
+    the timed region, and step i applies density i."""
+    import numpy as np
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from workloads import fresh_densities, workload_c2
+
+    t0 = time.time()
+    w = workload_c2()
+    n = args.warmup + args.steps
+    dens = torch.tensor(fresh_densities(w, n), device=dev)
+    log(f"workload {w.name}: {w.n_src} sources, {w.n_tgt} targets, {n} fresh densities "
+        f"({time.time() - t0:.1f}s)")
+    t0 = time.time()
+    plan = Plan.from_workload(w, wfar_direct_max=args.wfar_direct_max, precision="fp32_split")
+    plan_s = time.time() - t0
+    out = torch.empty((n, w.n_tgt), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for i in range(args.warmup):
+        plan.apply(dens[i:i + 1], out[i:i + 1], stream=stream)
+    torch.cuda.synchronize()
+    log(f"plan {plan_s:.2f}s; warmup {args.warmup} done; timing {args.steps} steps")
+    t = time.perf_counter()
+    for i in range(args.warmup, n):
+        plan.apply(dens[i:i + 1], out[i:i + 1], stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    plan.close()
+    # accuracy: the last density through the FP64 path, and through direct QBX on a sample
+    ref64 = Plan.from_workload(w, wfar_direct_max=args.wfar_direct_max)
+    last = ref64.apply(dens[n - 1:n])[0]
+    err64 = float((out[n - 1] - last).abs().max() / last.abs().max())
+    ref64.close()
+    err_direct = None
+    if not args.no_cpu_baseline:
+        import dataclasses
+
+        import oracle as O
+
+        rng = np.random.default_rng(12345)
+        cids = np.sort(rng.choice(w.n_ctr, 128, replace=False))
+        wl = dataclasses.replace(w, density=dens[n - 1:n].cpu().numpy())
+        tids, ref, _ = O.direct_qbx_sampled(wl, cids, density_index=0)
+        got = out[n - 1].cpu().numpy()[tids]
+        err_direct = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    log(f"{ms:.2f} ms per apply, {w.n_tgt / (ms * 1e-3):.4g} target evals/s; rel err vs FP64 "
+        f"path {err64:.3e}, vs direct QBX {err_direct}")
+    print(json.dumps({
+        "metric": "QBX-FMM target evals/sec at stated rel. error; M2L MFMA util (FP32 vs FP64)",
+        "value": round(w.n_tgt / (ms * 1e-3), 1), "unit": "target evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}, plan cached, fresh density per apply",
+                   "kernel": w.kernel, "p_qbx": w.p_qbx, "p_fmm": w.p_fmm,
+                   "n_sources": w.n_src, "n_targets": w.n_tgt, "precision": "fp32_split",
+                   "densities": n, "wfar_direct_max": args.wfar_direct_max},
+        "rel_err_vs_fp64_path": err64, "rel_err_vs_direct_qbx": err_direct,
+        "plan_seconds": round(plan_s, 3)}), flush=True)
+
+
+def study_solve(args, dev):
+    """The interior Dirichlet problem on an oversampled urchin (rho = 1 + 0.2 Re Y_8^4):
+    boundary values of u = 1 / (4 pi |x - x0|), x0 = (3, 1, 2); u = D[mu] with the interior
+    limit taken through the interior QBX centers; GMRES on split-precision applies, residuals
+    refined with the FP64 path, to a relative residual of 1e-10 within 200 applies.  D[mu] is
+    then compared with u at points inside."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from paper_1805_06106_amd.solve import gmres_ir, plan_operator
+    from workloads import oversampled_workload
+    from workloads.geometry import SurfaceSpec
+
+    t0 = time.time()
+    spec = SurfaceSpec(curved=True, bump_k=8, bump_m=4, bump_a=0.2)
+    w = oversampled_workload(f"urchin8-{20 * 4 ** args.level}-oversampled", level=args.level,
+                             spec=spec, kernel="D", p_qbx=5, p_fmm=15, node_order=4,
+                             quad_order=4, sub=4, sides="interior")
+    log(f"{w.name}: {w.n_tgt} density nodes, {w.n_src} quadrature sources "
+        f"({time.time() - t0:.1f}s)")
+    x0 = np.array([3.0, 1.0, 2.0])
+    g_np = 1.0 / (4 * np.pi * np.linalg.norm(w.node_xyz - x0, axis=1))
+    g = torch.tensor(g_np, device=dev)
+    t0 = time.time()
+    hi = Plan.from_workload(w, wfar_direct_max=args.wfar_direct_max)
+    lo = Plan.from_workload(w, wfar_direct_max=args.wfar_direct_max, precision="fp32_split")
+    plan_s = time.time() - t0
+    A_hi, A_lo = plan_operator(hi), plan_operator(lo)
+    for A in (A_hi, A_lo):  # warm
+        A(g)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    mu, info = gmres_ir(A_lo, A_hi, g, tol=1e-10, inner_tol=1e-6, max_applies=200)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t
+    ms = {}
+    for name, A in (("fp64", A_hi), ("fp32_split", A_lo)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            A(g)
+        torch.cuda.synchronize()
+        ms[name] = round((time.perf_counter() - t) * 200, 3)
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal((256, 3))
+    pts = v / np.linalg.norm(v, axis=1)[:, None] * rng.uniform(0.1, 0.6, 256)[:, None]
+    wp = dataclasses.replace(w, tgt_xyz=pts, tgt_center=np.full(len(pts), -1, dtype=np.int64))
+    u = Plan.from_workload(wp).apply(mu.reshape(1, -1)).cpu().numpy()[0]
+    exact = 1.0 / (4 * np.pi * np.linalg.norm(pts - x0, axis=1))
+    err = float(np.max(np.abs(u - exact)) / np.max(np.abs(exact)))
+    log(f"solve {solve_s:.2f}s, residuals {info['outer_residuals']}, inner "
+        f"{info['inner_iterations']}; interior error {err:.3e}")
+    print(json.dumps({"study": "interior_dirichlet_gmres_ir", "workload": w.name,
+                      "n_nodes": w.n_tgt, "n_sources": w.n_src, "p_qbx": 5, "p_fmm": 15,
+                      "oversampling": "15-node interior lattice -> 16 x 15-node rule",
+                      "charge": x0.tolist(), "tol": 1e-10, "converged": info["converged"],
+                      "outer_residuals": info["outer_residuals"],
+                      "inner_iterations": info["inner_iterations"],
+                      "applies_fp32_split": info["applies_lo"], "applies_fp64": info["applies_hi"],
+                      "ms_per_apply": ms, "solve_seconds": round(solve_s, 3),
+                      "plan_seconds": round(plan_s, 3), "interior_rel_err": err}), flush=True)
 
 
 def bench_batch(args, dev):

@@ -171,6 +171,24 @@ gq_status gq_stats(gq_plan* plan, gq_stats_t* out);
 gq_status gq_set_target_normals(gq_plan* plan, const double* tgt_normal);
 
 /*
+ * Oversampled source quadrature (Section 3, the stage-2 quadrature discretization: the
+ * density lives on the nodes of a unisolvent discretization and the layer potential is
+ * computed with a finer quadrature on the same elements).  After this call the densities
+ * given to gq_apply are node values, [n_densities][n_elem * n_node] (element-major), and
+ * the apply's first step computes the quadrature strengths of each source from its
+ * element's node values:
+ *   q_{e*n_quad + j} = w_{e*n_quad + j} * sum_k interp[j*n_node + k] * density[e*n_node + k]
+ * The plan's sources must be the quadrature nodes in element-major order, so
+ * n_src = n_elem * n_quad.  interp: host, [n_quad][n_node] row-major (copied);
+ * 1 <= n_node <= 64, 1 <= n_quad, n_quad * n_node <= 65536.  May be called again to change
+ * the matrix; a captured graph of the plan is recaptured at the next apply.
+ * Errors: GQ_EINVAL for a host-only plan, sizes that do not match the plan's sources or
+ * exceed the limits, or non-finite entries; GQ_EUNSUPPORTED for a batch plan.
+ */
+gq_status gq_set_source_interp(gq_plan* plan, int64_t n_elem, int n_node, int n_quad,
+                               const double* interp);
+
+/*
  * Merge plans into one batch plan (the many-surface form of Algorithm 5): each stage then
  * runs as one launch over every member's work, and the members' M2L pairs share the
  * offset-class matrices, so tiles fill across surfaces.

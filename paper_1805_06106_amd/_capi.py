@@ -40,7 +40,7 @@ STAGES = ("strength", "p2m", "m2m", "m2l", "p2l", "l2l", "p2qbxl", "m2qbxl", "l2
 
 EXPORTED = ("gq_plan_create", "gq_apply", "gq_stats", "gq_plan_destroy", "gq_last_error",
             "gq_tree_export", "gq_list_export", "gq_qbx_locals", "gq_translation_matrix",
-            "gq_batch_create", "gq_set_target_normals")
+            "gq_batch_create", "gq_set_target_normals", "gq_set_source_interp")
 
 
 class gq_params(ctypes.Structure):
@@ -99,6 +99,8 @@ def lib():
         L.gq_qbx_locals.argtypes = [P, P]
         L.gq_set_target_normals.restype = i32
         L.gq_set_target_normals.argtypes = [P, P]
+        L.gq_set_source_interp.restype = i32
+        L.gq_set_source_interp.argtypes = [P, ctypes.c_int64, i32, i32, P]
         L.gq_batch_create.restype = i32
         L.gq_batch_create.argtypes = [i32, P, ctypes.c_uint, P, ctypes.POINTER(ctypes.c_void_p)]
         L.gq_translation_matrix.restype = i32
@@ -172,6 +174,15 @@ def gq_set_target_normals(plan, normals):
     """normals: host (n_tgt, 3) float64 unit vectors in input target order."""
     normals = np.ascontiguousarray(normals, dtype=np.float64)
     _check(lib().gq_set_target_normals(ctypes.c_void_p(plan), _ptr(normals)))
+
+
+def gq_set_source_interp(plan, n_elem, interp):
+    """interp: host (n_quad, n_node) float64 matrix from an element's node values to its
+    quadrature nodes; the plan's sources are the n_elem * n_quad quadrature nodes."""
+    interp = np.ascontiguousarray(interp, dtype=np.float64)
+    n_quad, n_node = interp.shape
+    _check(lib().gq_set_source_interp(ctypes.c_void_p(plan), int(n_elem), int(n_node),
+                                      int(n_quad), _ptr(interp)))
 
 
 def gq_batch_create(plans, flags=0, stream=None):

@@ -33,16 +33,16 @@ def build(verbose: bool = False) -> str:
     for f in ("planner.cpp", "translations.cpp"):
         jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, f),
                      "-o", os.path.join(BUILD, f + ".o")])
-    for f in ("kernels.hip", "kernels_p2x.hip", "kernels_pt.hip", "executor.hip"):
+    hip_sources = ("kernels.hip", "kernels_p2x.hip", "kernels_pt.hip", "oversample.hip",
+                   "executor.hip")
+    for f in hip_sources:
         jobs.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, f),
                      "-o", os.path.join(BUILD, f + ".o")])
     with ThreadPoolExecutor(max_workers=6) as ex:
         for out in ex.map(_run, jobs):
             if verbose and out:
                 print(out)
-    objs = [os.path.join(BUILD, f + ".o") for f in
-            ("planner.cpp", "translations.cpp", "kernels.hip", "kernels_p2x.hip",
-             "kernels_pt.hip", "executor.hip")]
+    objs = [os.path.join(BUILD, f + ".o") for f in ("planner.cpp", "translations.cpp", *hip_sources)]
     tmp = LIB + ".tmp%d" % os.getpid()
     _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -94,6 +94,10 @@ struct gq_plan {
   int m2l_cols = gq::kTileCols;        // M2L tile width (32 or 64)
   bool m2l_xcd = true;                 // XCD-aware M2L tile order
   std::vector<int64_t> h_tgt_ctr, h_tgt_out;  // host copies of tgt_ctr / tgt_out
+  bool is_batch = false;               // made by gq_batch_create
+  // oversampled source quadrature: densities are node values of n_elem elements
+  int64_t n_elem = 0;
+  int n_node = 0, n_quad = 0;
 
   // device memory
   std::vector<void*> allocs;
@@ -130,6 +134,7 @@ struct gq_plan {
         *T32_m2l[2] = {nullptr, nullptr};  // (hi, lo)
   gq::TransMats tm_m2m{}, tm_l2l{}, tm_m2l{};
   double *q = nullptr, *M = nullptr, *L = nullptr, *Lq = nullptr;
+  double* interp = nullptr;  // [n_quad][n_node], set by gq_set_source_interp
   // GQ_FLAG_GRAPH: the passes of one apply captured once per (density, potential) pair
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -1011,7 +1016,12 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
       ev = P->ev_sets[P->ev_used++].data();
     }
     GQ_TRY(mark(0));
-    gq::launch_strength(s, P->n_src, P->src_order, P->sw, density + (int64_t)d * P->n_src, P->q);
+    if (P->interp)
+      gq::launch_strength_interp(s, P->n_src, P->src_order, P->sw, P->n_node, P->n_quad,
+                                 P->interp, density + (int64_t)d * P->n_elem * P->n_node, P->q);
+    else
+      gq::launch_strength(s, P->n_src, P->src_order, P->sw, density + (int64_t)d * P->n_src,
+                          P->q);
     GQ_TRY(mark(1));
     gq::launch_fill(s, P->M, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->L, (int64_t)T.nboxes * np, 0.0);
@@ -1153,8 +1163,7 @@ gq_status gq_set_target_normals(gq_plan* P, const double* tgt_normal) {
   g_err.clear();
   if (!P || !tgt_normal) return fail(GQ_EINVAL, "NULL argument");
   if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
-  if (P->h_tgt_out.size() != (size_t)P->n_qt)
-    return fail(GQ_EINVAL, "a batch plan takes its members' target normals");
+  if (P->is_batch) return fail(GQ_EINVAL, "a batch plan takes its members' target normals");
   if (!finite3(tgt_normal, P->n_tgt)) return fail(GQ_EINVAL, "non-finite normal");
   std::vector<double> a(P->n_qt), b(P->n_qt), c(P->n_qt);
   for (int64_t i = 0; i < P->n_qt; ++i) {
@@ -1174,6 +1183,39 @@ gq_status gq_set_target_normals(gq_plan* P, const double* tgt_normal) {
                           hipMemcpyHostToDevice, s));
   }
   GQ_HIP(hipStreamSynchronize(s));
+  return GQ_OK;
+}
+
+gq_status gq_set_source_interp(gq_plan* P, int64_t n_elem, int n_node, int n_quad,
+                               const double* interp) {
+  g_err.clear();
+  if (!P || !interp) return fail(GQ_EINVAL, "NULL argument");
+  if (P->is_batch) return fail(GQ_EUNSUPPORTED, "a batch plan cannot take a source interpolation");
+  if (n_node < 1 || n_node > 64 || n_quad < 1 || (int64_t)n_quad * n_node > 65536)
+    return fail(GQ_EINVAL, "interpolation size out of range (1 <= n_node <= 64, "
+                           "n_quad * n_node <= 65536)");
+  if (n_elem < 1 || n_elem * n_quad != P->n_src)
+    return fail(GQ_EINVAL, "n_elem * n_quad must equal the plan's source count");
+  const int64_t nm = (int64_t)n_quad * n_node;
+  for (int64_t i = 0; i < nm; ++i)
+    if (!std::isfinite(interp[i])) return fail(GQ_EINVAL, "non-finite interpolation entry");
+  if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
+  hipStream_t s = P->last_stream;
+  if (P->graph_exec) {  // the captured apply reads the old layout: capture anew
+    GQ_HIP(hipStreamSynchronize(s));
+    GQ_HIP(hipGraphExecDestroy(P->graph_exec));
+    P->graph_exec = nullptr;
+  }
+  if (P->interp && (int64_t)P->n_quad * P->n_node < nm) {
+    GQ_HIP(hipStreamSynchronize(s));
+    P->interp = nullptr;  // the old buffer stays in P->allocs until the plan is destroyed
+  }
+  if (!P->interp) GQ_TRY(alloc(P, (size_t)nm, &P->interp));
+  GQ_HIP(hipMemcpyAsync(P->interp, interp, (size_t)nm * sizeof(double), hipMemcpyHostToDevice, s));
+  GQ_HIP(hipStreamSynchronize(s));
+  P->n_elem = n_elem;
+  P->n_node = n_node;
+  P->n_quad = n_quad;
   return GQ_OK;
 }
 
@@ -1199,8 +1241,12 @@ gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, vo
     for (int j = 0; j < k; ++j)
       if (plans[j] == P) return fail(GQ_EINVAL, "plan listed twice in batch");
   }
+  for (int k = 0; k < n_plans; ++k)
+    if (plans[k]->interp)
+      return fail(GQ_EUNSUPPORTED, "batch members with an oversampled source quadrature");
   gq_plan* B = new (std::nothrow) gq_plan();
   if (!B) return fail(GQ_ENOMEM, "host allocation failed");
+  B->is_batch = true;
   B->prm = P0->prm;
   B->prm.flags = (P0->prm.flags & ~(GQ_FLAG_TIMING | GQ_FLAG_GRAPH | GQ_FLAG_AUTOTUNE)) | flags;
   B->np = P0->np;

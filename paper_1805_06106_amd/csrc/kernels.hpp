@@ -24,6 +24,11 @@ struct SrcSoA {
 // q[i] = w[i] * density[order[i]]
 void launch_strength(hipStream_t s, int64_t n, const int64_t* order, const double* w,
                      const double* density, double* q);
+// Oversampled quadrature: q[i] = w[i] * sum_k interp[f * n_node + k] * density[e * n_node + k]
+// with (e, f) = divmod(order[i], n_quad) (source i in tree order; oversample.hip).
+void launch_strength_interp(hipStream_t s, int64_t n, const int64_t* order, const double* w,
+                            int n_node, int n_quad, const double* interp, const double* density,
+                            double* q);
 void launch_fill(hipStream_t s, double* p, int64_t n, double v);
 
 // Stage 2a: multipoles (scaled) of leaf boxes from their own sources.  Item i: box

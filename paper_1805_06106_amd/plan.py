@@ -27,6 +27,7 @@ class Plan:
         self.n_tgt = int(tgt_xyz.shape[0])
         self.p_qbx = int(p_qbx)
         self.n_densities = int(n_densities)
+        self.n_density_cols = self.n_src  # node values per density row
         self.handle = None
         self.handle = C.gq_plan_create(self.params, src_xyz, src_w, src_normal, ctr_xyz,
                                        ctr_radius, tgt_xyz, tgt_center, stream=stream)
@@ -35,8 +36,11 @@ class Plan:
     def from_workload(cls, w, **kw):
         args = dict(p_qbx=w.p_qbx, p_fmm=w.p_fmm, kernel=w.kernel, nmax=w.nmax, tcf=w.tcf)
         args.update(kw)
-        return cls(src_xyz=w.src_xyz, src_w=w.src_w, src_normal=w.src_normal, ctr_xyz=w.ctr_xyz,
+        plan = cls(src_xyz=w.src_xyz, src_w=w.src_w, src_normal=w.src_normal, ctr_xyz=w.ctr_xyz,
                    ctr_radius=w.ctr_radius, tgt_xyz=w.tgt_xyz, tgt_center=w.tgt_center, **args)
+        if getattr(w, "interp", None) is not None and not args.get("host_only", False):
+            plan.set_source_interp(w.n_elem, w.interp)
+        return plan
 
     @classmethod
     def batch(cls, plans, *, timing=False, graph=False, autotune=False, stream=None):
@@ -53,6 +57,7 @@ class Plan:
         self.n_tgt = sum(p.n_tgt for p in plans)
         self.p_qbx = plans[0].p_qbx
         self.n_densities = plans[0].n_densities
+        self.n_density_cols = self.n_src
         return self
 
     def apply(self, density, potential=None, stream=None):
@@ -63,14 +68,22 @@ class Plan:
                                     device=density.device)
         if density.dtype != torch.float64 or not density.is_contiguous():
             raise ValueError("density must be a contiguous float64 device tensor")
-        if tuple(density.shape) != (self.n_densities, self.n_src):
-            raise ValueError(f"density shape {tuple(density.shape)} != {(self.n_densities, self.n_src)}")
+        want = (self.n_densities, self.n_density_cols)
+        if tuple(density.shape) != want:
+            raise ValueError(f"density shape {tuple(density.shape)} != {want}")
         C.gq_apply(self.handle, density, potential, stream=stream)
         return potential
 
     def set_target_normals(self, normals):
         """Target normals (n_tgt, 3) for the adjoint double layer (kernel "SP")."""
         C.gq_set_target_normals(self.handle, normals)
+
+    def set_source_interp(self, n_elem, interp):
+        """Oversampled quadrature: the sources are n_elem elements' quadrature nodes
+        (element-major) and densities become node values, (n_densities, n_elem * n_node);
+        interp (n_quad, n_node) maps one element's node values to its quadrature nodes."""
+        C.gq_set_source_interp(self.handle, n_elem, interp)
+        self.n_density_cols = int(n_elem) * int(interp.shape[1])
 
     def stats(self):
         return C.gq_stats(self.handle)

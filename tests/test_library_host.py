@@ -255,3 +255,31 @@ def test_sprime_validation(gq):
     with pytest.raises(G.GQError) as e:
         G.Plan(**_args(wp, kernel="SP", host_only=False))
     assert e.value.status == 4
+
+
+def test_source_interp_validation(gq):
+    """gq_set_source_interp checks its sizes against the plan's sources before anything
+    touches the device; a host-only plan is then refused."""
+    from workloads import oversampled_workload
+    from workloads.geometry import SurfaceSpec
+
+    w = oversampled_workload("os", level=0, spec=SurfaceSpec(curved=True), kernel="S",
+                             p_qbx=2, p_fmm=4, node_order=2, quad_order=2, sub=2, nmax=32)
+    G = gq
+    P = G.Plan.from_workload(w, host_only=True)
+    nq, nn = w.interp.shape
+    assert w.n_src == w.n_elem * nq
+    bad = [(w.n_elem + 1, w.interp, "n_elem"), (w.n_elem, np.zeros((nq, 65)), "size"),
+           (w.n_elem, np.zeros((nq + 1, nn)), "n_elem"), (0, w.interp, "n_elem")]
+    for ne, m, what in bad:
+        with pytest.raises(G.GQError) as e:
+            P.set_source_interp(ne, m)
+        assert e.value.status == 1 and what in str(e.value), (ne, m.shape, str(e.value))
+    nan = w.interp.copy()
+    nan[0, 0] = np.nan
+    with pytest.raises(G.GQError) as e:
+        P.set_source_interp(w.n_elem, nan)
+    assert "non-finite" in str(e.value)
+    with pytest.raises(G.GQError) as e:
+        P.set_source_interp(w.n_elem, w.interp)
+    assert "host-only" in str(e.value)

@@ -8,8 +8,10 @@ arrays that both sides consume.
 from .geometry import (  # noqa: F401
     Workload,
     add_point_targets,
+    fresh_densities,
     icosphere,
     make_workload,
+    oversampled_workload,
     workload_c1,
     workload_c2,
     workload_c3,

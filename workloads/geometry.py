@@ -224,8 +224,16 @@ class Workload:
     ctr_radius: np.ndarray       # (N_C,)
     tgt_xyz: np.ndarray          # (N_T, 3)
     tgt_center: np.ndarray       # (N_T,) int64
-    density: np.ndarray          # (n_densities, N_S)
+    density: np.ndarray          # (n_densities, N_S), or node values with `interp`
     meta: dict = field(default_factory=dict)
+    # Oversampled quadrature (optional): the sources are the quadrature nodes of n_elem
+    # elements, element-major, and `density` holds values at each element's n_node
+    # interpolation nodes; interp (n_quad, n_node) maps one element's node values to its
+    # quadrature nodes.
+    interp: np.ndarray | None = None
+    n_elem: int = 0
+    node_xyz: np.ndarray | None = None     # (n_elem * n_node, 3)
+    node_normal: np.ndarray | None = None  # (n_elem * n_node, 3)
 
     @property
     def n_src(self):
@@ -239,9 +247,18 @@ class Workload:
     def n_tgt(self):
         return self.tgt_xyz.shape[0]
 
+    def source_density(self):
+        """Density at the sources, shape (n_densities, N_S): `density` itself, or with an
+        oversampled quadrature each element's node values mapped by `interp`."""
+        if self.interp is None:
+            return self.density
+        nd = self.density.shape[0]
+        nodes = self.density.reshape(nd, self.n_elem, self.interp.shape[1])
+        return np.einsum("dek,jk->dej", nodes, self.interp).reshape(nd, -1)
+
     def strengths(self):
-        """q = w * mu, shape (n_densities, N_S)."""
-        return self.density * self.src_w[None, :]
+        """q = w * mu at the sources, shape (n_densities, N_S)."""
+        return self.source_density() * self.src_w[None, :]
 
 
 def _nodes(level: int, order: int, spec: SurfaceSpec):
@@ -333,6 +350,111 @@ def make_workload(name, *, level, order, spec: SurfaceSpec, kernel, p_qbx, p_fmm
     )
 
 
+def interior_lattice(order: int):
+    """Reference coordinates (x, y) on {0 <= y <= x <= 1} of the interior points of the
+    degree-(order+3) barycentric lattice: a scaled principal lattice of degree `order`,
+    (order+1)(order+2)/2 points, unisolvent for polynomials of total degree <= order, none
+    on an edge (so no node is shared between elements)."""
+    n = order + 3
+    lam = np.array([(a, b, n - a - b) for a in range(1, n) for b in range(1, n - a)
+                    if n - a - b >= 1], dtype=np.float64) / n
+    # vertices (0,0), (1,0), (1,1) carry barycentric weights lam[:, 0], lam[:, 1], lam[:, 2]
+    return lam[:, 1] + lam[:, 2], lam[:, 2]
+
+
+def subdivided_rule(order: int, sub: int):
+    """The collapsed Gauss-Legendre rule of `order` on each of the sub^2 congruent
+    sub-triangles of the reference triangle: (x, y, w), weights summing to 1/2."""
+    xr, yr, wr = duffy_rule(order)
+    pts, wts = [], []
+    for i in range(sub):
+        for j in range(i + 1):
+            v0 = np.array([i, j]) / sub
+            tris = [(v0, np.array([i + 1, j]) / sub, np.array([i + 1, j + 1]) / sub)]
+            if j < i:
+                tris.append((v0, np.array([i + 1, j + 1]) / sub, np.array([i, j + 1]) / sub))
+            for a, b, c in tris:
+                pts.append(a[None] + xr[:, None] * (b - a)[None] + yr[:, None] * (c - b)[None])
+                wts.append(wr / sub ** 2)
+    p = np.concatenate(pts)
+    return p[:, 0], p[:, 1], np.concatenate(wts)
+
+
+def lattice_interpolation(order: int, xq, yq):
+    """Matrix (len(xq), n_node) taking values at interior_lattice(order) to the values of
+    their degree-`order` interpolating polynomial at the points (xq, yq)."""
+    xn, yn = interior_lattice(order)
+    mono = [(i, j) for i in range(order + 1) for j in range(order + 1 - i)]
+    vn = np.stack([xn ** i * yn ** j for i, j in mono], axis=1)
+    vq = np.stack([xq ** i * yq ** j for i, j in mono], axis=1)
+    return np.linalg.solve(vn.T, vq.T).T
+
+
+def oversampled_workload(name, *, level, spec: SurfaceSpec, kernel, p_qbx, p_fmm,
+                         node_order=4, quad_order=4, sub=4, sides="both", nmax=512, tcf=0.9,
+                         seed=0, n_densities=1):
+    """A surface discretized as the paper's stage-2 pair (Section 3): the density lives on a
+    unisolvent node set per element (interior_lattice(node_order)) and the layer potential
+    uses an oversampled quadrature on the same elements (subdivided_rule(quad_order, sub)).
+
+    Sources are the quadrature nodes (element-major); each density node gets its QBX
+    center(s) at distance r_k (half the largest chord of its element) along the normal:
+    sides "both" gives centers 2i (exterior) and 2i+1 (interior) with targets at the node,
+    "interior" or "exterior" one center per node and target i at node i (a square
+    operator).  Densities: random combinations of real Y_l^m, l <= 4, at the nodes' sphere
+    directions (seed `seed`)."""
+    verts, faces = icosphere(level)
+    A, B, C = verts[faces[:, 0]], verts[faces[:, 1]], verts[faces[:, 2]]
+    ne = faces.shape[0]
+    xn, yn = interior_lattice(node_order)
+    xq, yq, wq = subdivided_rule(quad_order, sub)
+    interp = lattice_interpolation(node_order, xq, yq)
+    _, Fn, Fnx, Fny = _map_and_jacobian(spec, A, B, C, xn, yn)
+    crn = np.cross(Fnx, Fny)
+    node = Fn.reshape(-1, 3)
+    node_nrm = (crn / np.linalg.norm(crn, axis=2)[..., None]).reshape(-1, 3)
+    _, Fq, Fqx, Fqy = _map_and_jacobian(spec, A, B, C, xq, yq)
+    crq = np.cross(Fqx, Fqy)
+    arq = np.linalg.norm(crq, axis=2)
+    src = Fq.reshape(-1, 3)
+    src_nrm = (crq / arq[..., None]).reshape(-1, 3)
+    src_w = (wq[None, :] * arq).ravel()
+    _, Fu, _, _ = _map_and_jacobian(SurfaceSpec(curved=True), A, B, C, xq, yq)
+    _, Fun, _, _ = _map_and_jacobian(SurfaceSpec(curved=True), A, B, C, xn, yn)
+    tri = np.stack([A, B, C], axis=1)
+    mv = _surface_map(spec, tri.astype(np.complex128)).real
+    chords = np.stack([np.linalg.norm(mv[:, 0] - mv[:, 1], axis=1),
+                       np.linalg.norm(mv[:, 1] - mv[:, 2], axis=1),
+                       np.linalg.norm(mv[:, 2] - mv[:, 0], axis=1)], axis=1)
+    rk = np.repeat(0.5 * chords.max(axis=1), xn.shape[0])
+    nn = node.shape[0]
+    if sides == "both":
+        ctr = np.empty((2 * nn, 3))
+        ctr[0::2] = node + rk[:, None] * node_nrm
+        ctr[1::2] = node - rk[:, None] * node_nrm
+        crad = np.repeat(rk, 2)
+        tgt = np.repeat(node, 2, axis=0)
+    elif sides in ("interior", "exterior"):
+        sgn = -1.0 if sides == "interior" else 1.0
+        ctr = node + sgn * rk[:, None] * node_nrm
+        crad = rk.copy()
+        tgt = node.copy()
+    else:
+        raise ValueError(sides)
+    rng = np.random.default_rng(seed)
+    dens = _density_random_sh(rng, n_densities, Fun.reshape(-1, 3))
+    return Workload(
+        name=name, kernel=kernel, p_qbx=p_qbx, p_fmm=p_fmm, nmax=nmax, tcf=tcf,
+        src_xyz=src, src_w=src_w, src_normal=src_nrm, src_dir=Fu.reshape(-1, 3),
+        ctr_xyz=ctr, ctr_radius=crad, tgt_xyz=tgt,
+        tgt_center=np.arange(ctr.shape[0], dtype=np.int64),
+        density=np.ascontiguousarray(dens),
+        meta=dict(level=level, node_order=node_order, quad_order=quad_order, sub=sub,
+                  n_triangles=ne, seed=seed, sides=sides, curved=spec.curved,
+                  bump=(spec.bump_k, spec.bump_m, spec.bump_a), scale=spec.scale),
+        interp=interp, n_elem=ne, node_xyz=node, node_normal=node_nrm)
+
+
 def workload_c1(nmax=512, n_densities=1, p_fmm=10, p_qbx=3, kernel="S"):
     """Unit sphere as 320 flat triangles, 15-node rule, S, p_qbx=3, p_fmm=10, seed 1."""
     return make_workload("sphere320-flat", level=2, order=4, spec=SurfaceSpec(curved=False),
@@ -402,6 +524,14 @@ def workload_c3(i: int, n_densities=8, nmax=512):
     w.density = np.ascontiguousarray(_lowpass_project(raw, w.src_dir, _unit_weights(level, 6)))
     w.meta["density"] = "lowpass"
     return w
+
+
+def fresh_densities(w: Workload, count: int, seed0: int = 5000):
+    """`count` new densities on w's nodes by the urchin recipe (uniform(-1, 1) node values
+    smoothed by projection onto real Y_l^m, l <= 16); density i is seeded by seed0 + i."""
+    raw = [np.random.default_rng(seed0 + i).uniform(-1.0, 1.0, w.n_src) for i in range(count)]
+    uw = _unit_weights(w.meta["level"], w.meta["order"])
+    return np.ascontiguousarray(_lowpass_project(raw, w.src_dir, uw))
 
 
 def _unit_weights(level, order):
