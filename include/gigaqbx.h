@@ -188,6 +188,40 @@ gq_status gq_set_target_normals(gq_plan* plan, const double* tgt_normal);
 gq_status gq_set_source_interp(gq_plan* plan, int64_t n_elem, int n_node, int n_quad,
                                const double* interp);
 
+/* Target association results (gq_associate_targets) besides a center index. */
+#define GQ_TARGET_FAR (-1)        /* no source endangers it: a conventional target */
+#define GQ_TARGET_UNMATCHED (-2)  /* endangered, but no admissible center is close enough */
+
+/*
+ * Associate targets with QBX centers (Algorithm 3, with the side preference of Section 3).
+ * A target t is endangered if some source s has |t - s| <= danger[s] (the danger zone of
+ * a source is half its element's size).  An endangered target is associated with the
+ * closest center c with |t - c| <= ctr_radius[c] * (1 + tol) whose side matches: when
+ * tgt_side[t] != 0, only centers with ctr_side[c] == tgt_side[t] qualify.  Equal
+ * distances go to the lower center index.  Distances are compared squared, in FP64,
+ * without fused multiply-adds: ((dx*dx + dy*dy) + dz*dz) <= (r*r).
+ *   src_xyz[3*n_src], src_danger[n_src]        host, danger radii >= 0
+ *   ctr_xyz[3*n_ctr], ctr_radius[n_ctr]        host, radii > 0
+ *   ctr_side[n_ctr]   host, +1 / -1 per center (which side of the surface it lies on);
+ *                     may be NULL when tgt_side is NULL
+ *   tgt_xyz[3*n_tgt]  host
+ *   tgt_side[n_tgt]   host, +1 / -1 / 0 (no preference); NULL means all 0
+ *   tol               >= 0
+ *   tgt_center[n_tgt] host output: a center index, GQ_TARGET_FAR or GQ_TARGET_UNMATCHED;
+ *                     it can be passed to gq_plan_create once no entry is
+ *                     GQ_TARGET_UNMATCHED (GQ_TARGET_FAR is its conventional-target mark)
+ * The queries run on the device (one thread per target over a uniform cell grid built on
+ * the host); the call allocates and frees its own device memory and returns when the
+ * result is on the host.  Errors: GQ_EINVAL for NULL arrays with nonzero counts,
+ * non-finite coordinates or radii, negative radii or tolerance, side values outside
+ * {-1, 0, +1} (ctr_side: {-1, +1}), or tgt_side without ctr_side.
+ */
+gq_status gq_associate_targets(int64_t n_src, const double* src_xyz, const double* src_danger,
+                               int64_t n_ctr, const double* ctr_xyz, const double* ctr_radius,
+                               const int8_t* ctr_side, int64_t n_tgt, const double* tgt_xyz,
+                               const int8_t* tgt_side, double tol, int64_t* tgt_center,
+                               void* hip_stream);
+
 /*
  * Merge plans into one batch plan (the many-surface form of Algorithm 5): each stage then
  * runs as one launch over every member's work, and the members' M2L pairs share the

@@ -8,7 +8,10 @@ raises.
 from ._capi import (  # noqa: F401
     GQ_FLAG_HOST_ONLY,
     GQ_FLAG_TIMING,
+    GQ_TARGET_FAR,
+    GQ_TARGET_UNMATCHED,
     GQError,
+    gq_associate_targets as associate_targets,
     gq_apply,
     gq_last_error,
     gq_list_export,

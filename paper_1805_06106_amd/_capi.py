@@ -40,7 +40,10 @@ STAGES = ("strength", "p2m", "m2m", "m2l", "p2l", "l2l", "p2qbxl", "m2qbxl", "l2
 
 EXPORTED = ("gq_plan_create", "gq_apply", "gq_stats", "gq_plan_destroy", "gq_last_error",
             "gq_tree_export", "gq_list_export", "gq_qbx_locals", "gq_translation_matrix",
-            "gq_batch_create", "gq_set_target_normals", "gq_set_source_interp")
+            "gq_batch_create", "gq_set_target_normals", "gq_set_source_interp",
+            "gq_associate_targets")
+GQ_TARGET_FAR = -1
+GQ_TARGET_UNMATCHED = -2
 
 
 class gq_params(ctypes.Structure):
@@ -78,6 +81,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1805_06106_amd.build` (hipcc, gfx950)")
+        # torch carries its own HIP runtime; loading it first makes this library bind to
+        # that same runtime instead of initializing a second one in the process (torch then
+        # finds no device if the library's runtime claimed it first)
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
         L.gq_plan_create.restype = i32
@@ -100,6 +108,9 @@ def lib():
         L.gq_set_target_normals.restype = i32
         L.gq_set_target_normals.argtypes = [P, P]
         L.gq_set_source_interp.restype = i32
+        L.gq_associate_targets.restype = i32
+        L.gq_associate_targets.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, P, P,
+                                           ctypes.c_int64, P, P, ctypes.c_double, P, P]
         L.gq_set_source_interp.argtypes = [P, ctypes.c_int64, i32, i32, P]
         L.gq_batch_create.restype = i32
         L.gq_batch_create.argtypes = [i32, P, ctypes.c_uint, P, ctypes.POINTER(ctypes.c_void_p)]
@@ -183,6 +194,31 @@ def gq_set_source_interp(plan, n_elem, interp):
     n_quad, n_node = interp.shape
     _check(lib().gq_set_source_interp(ctypes.c_void_p(plan), int(n_elem), int(n_node),
                                       int(n_quad), _ptr(interp)))
+
+
+def gq_associate_targets(src_xyz, src_danger, ctr_xyz, ctr_radius, tgt_xyz, tol=0.0,
+                         ctr_side=None, tgt_side=None, stream=None):
+    """Algorithm 3 on the device; host arrays in, host int64 array out (a center index per
+    target, GQ_TARGET_FAR or GQ_TARGET_UNMATCHED)."""
+    f64 = lambda a, shape: np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))  # noqa: E731
+    src_xyz = f64(src_xyz, (-1, 3))
+    ctr_xyz = f64(ctr_xyz, (-1, 3))
+    tgt_xyz = f64(tgt_xyz, (-1, 3))
+    src_danger = f64(src_danger, (-1,))
+    ctr_radius = f64(ctr_radius, (-1,))
+    i8 = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.int8))  # noqa: E731
+    ctr_side, tgt_side = i8(ctr_side), i8(tgt_side)
+    if src_danger.shape[0] != src_xyz.shape[0] or ctr_radius.shape[0] != ctr_xyz.shape[0]:
+        raise ValueError("radius arrays must match their point arrays")
+    for side, n in ((ctr_side, ctr_xyz.shape[0]), (tgt_side, tgt_xyz.shape[0])):
+        if side is not None and side.shape != (n,):
+            raise ValueError("side arrays must have one entry per point")
+    out = np.empty(tgt_xyz.shape[0], dtype=np.int64)
+    _check(lib().gq_associate_targets(
+        src_xyz.shape[0], _ptr(src_xyz), _ptr(src_danger), ctr_xyz.shape[0], _ptr(ctr_xyz),
+        _ptr(ctr_radius), _ptr(ctr_side), tgt_xyz.shape[0], _ptr(tgt_xyz), _ptr(tgt_side),
+        float(tol), _ptr(out), _stream(stream)))
+    return out
 
 
 def gq_batch_create(plans, flags=0, stream=None):

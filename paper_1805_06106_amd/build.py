@@ -34,7 +34,7 @@ def build(verbose: bool = False) -> str:
         jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, f),
                      "-o", os.path.join(BUILD, f + ".o")])
     hip_sources = ("kernels.hip", "kernels_p2x.hip", "kernels_pt.hip", "oversample.hip",
-                   "executor.hip")
+                   "associate.hip", "executor.hip")
     for f in hip_sources:
         jobs.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, f),
                      "-o", os.path.join(BUILD, f + ".o")])

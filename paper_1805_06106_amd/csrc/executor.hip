@@ -1186,6 +1186,172 @@ gq_status gq_set_target_normals(gq_plan* P, const double* tgt_normal) {
   return GQ_OK;
 }
 
+gq_status gq_associate_targets(int64_t n_src, const double* src_xyz, const double* src_danger,
+                               int64_t n_ctr, const double* ctr_xyz, const double* ctr_radius,
+                               const int8_t* ctr_side, int64_t n_tgt, const double* tgt_xyz,
+                               const int8_t* tgt_side, double tol, int64_t* tgt_center,
+                               void* hip_stream) {
+  g_err.clear();
+  if (n_src < 0 || n_ctr < 0 || n_tgt < 0) return fail(GQ_EINVAL, "negative count");
+  if ((n_src && (!src_xyz || !src_danger)) || (n_ctr && (!ctr_xyz || !ctr_radius)) ||
+      (n_tgt && (!tgt_xyz || !tgt_center)))
+    return fail(GQ_EINVAL, "NULL array with a nonzero count");
+  if (tgt_side && !ctr_side) return fail(GQ_EINVAL, "target sides need center sides");
+  if (!std::isfinite(tol) || tol < 0) return fail(GQ_EINVAL, "tolerance must be finite and >= 0");
+  if (!finite3(src_xyz, n_src) || !finite3(ctr_xyz, n_ctr) || !finite3(tgt_xyz, n_tgt))
+    return fail(GQ_EINVAL, "non-finite coordinate");
+  for (int64_t i = 0; i < n_src; ++i)
+    if (!std::isfinite(src_danger[i]) || src_danger[i] < 0)
+      return fail(GQ_EINVAL, "danger radii must be finite and >= 0");
+  for (int64_t i = 0; i < n_ctr; ++i)
+    if (!std::isfinite(ctr_radius[i]) || ctr_radius[i] <= 0)
+      return fail(GQ_EINVAL, "center radii must be finite and > 0");
+  if (ctr_side)
+    for (int64_t i = 0; i < n_ctr; ++i)
+      if (ctr_side[i] != 1 && ctr_side[i] != -1) return fail(GQ_EINVAL, "center side must be +-1");
+  if (tgt_side)
+    for (int64_t i = 0; i < n_tgt; ++i)
+      if (tgt_side[i] < -1 || tgt_side[i] > 1) return fail(GQ_EINVAL, "target side must be -1, 0 or 1");
+  if (n_src + n_ctr + n_tgt >= ((int64_t)1 << 31))
+    return fail(GQ_EUNSUPPORTED, "more than 2^31 points");
+  if (n_tgt == 0) return GQ_OK;
+  if (n_src == 0) {  // nothing endangers any target
+    for (int64_t i = 0; i < n_tgt; ++i) tgt_center[i] = GQ_TARGET_FAR;
+    return GQ_OK;
+  }
+  // grid: cells at least as wide as every query radius, so a 27-cell neighbourhood holds
+  // every source or center a target can reach
+  std::vector<double> cr(n_ctr);
+  for (int64_t i = 0; i < n_ctr; ++i) cr[i] = ctr_radius[i] * (1.0 + tol);
+  double lo[3], hi[3], rmax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = tgt_xyz[a];
+    hi[a] = tgt_xyz[a];
+  }
+  auto grow = [&](const double* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], p[3 * i + a]);
+        hi[a] = std::max(hi[a], p[3 * i + a]);
+      }
+  };
+  grow(src_xyz, n_src);
+  grow(ctr_xyz, n_ctr);
+  grow(tgt_xyz, n_tgt);
+  for (int64_t i = 0; i < n_src; ++i) rmax = std::max(rmax, src_danger[i]);
+  for (int64_t i = 0; i < n_ctr; ++i) rmax = std::max(rmax, cr[i]);
+  const double extent = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+  gq::AssocGrid g{};
+  g.h = rmax * (1.0 + 1e-9) + extent * 1e-12;
+  if (!(g.h > 0)) g.h = 1.0;
+  for (;;) {
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+      g.lo[a] = lo[a];
+      g.n[a] = (int)std::min<double>(std::floor((hi[a] - lo[a]) / g.h) + 1.0, 1 << 24);
+      cells *= g.n[a];
+    }
+    if (cells <= ((int64_t)1 << 24)) break;
+    g.h *= 1.25;  // wider cells only add candidates; reach is unchanged
+  }
+  const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  auto cell_of = [&](const double* p) {
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) {
+      int64_t i = (int64_t)std::floor((p[a] - g.lo[a]) / g.h);
+      c[a] = i < 0 ? 0 : (i >= g.n[a] ? g.n[a] - 1 : i);
+    }
+    return (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
+  };
+  // counting sort of sources and centers by cell
+  struct Sorted {
+    std::vector<int64_t> start, id;
+    std::vector<double> x, y, z, r;
+    std::vector<int8_t> side;
+  };
+  auto sort_cells = [&](int64_t n, const double* p, const double* r, const int8_t* sd, Sorted& o) {
+    std::vector<int64_t> cell(n);
+    o.start.assign(ncell + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      cell[i] = cell_of(p + 3 * i);
+      o.start[cell[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncell; ++c) o.start[c + 1] += o.start[c];
+    std::vector<int64_t> fill(o.start.begin(), o.start.end() - 1);
+    o.id.resize(n);
+    o.x.resize(n);
+    o.y.resize(n);
+    o.z.resize(n);
+    o.r.resize(n);
+    if (sd) o.side.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t k = fill[cell[i]]++;
+      o.id[k] = i;
+      o.x[k] = p[3 * i];
+      o.y[k] = p[3 * i + 1];
+      o.z[k] = p[3 * i + 2];
+      o.r[k] = r[i];
+      if (sd) o.side[k] = sd[i];
+    }
+  };
+  Sorted S, Cs;
+  sort_cells(n_src, src_xyz, src_danger, nullptr, S);
+  sort_cells(n_ctr, ctr_xyz, cr.data(), ctr_side, Cs);
+  std::vector<double> tx(n_tgt), ty(n_tgt), tz(n_tgt);
+  for (int64_t i = 0; i < n_tgt; ++i) {
+    tx[i] = tgt_xyz[3 * i];
+    ty[i] = tgt_xyz[3 * i + 1];
+    tz[i] = tgt_xyz[3 * i + 2];
+  }
+  // device copies, freed on every exit
+  struct DevBufs {
+    std::vector<void*> p;
+    ~DevBufs() {
+      for (void* q : p) (void)hipFree(q);
+    }
+  } bufs;
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto up = [&](const void* h, size_t bytes, void** d) -> gq_status {
+    *d = nullptr;
+    if (bytes == 0) return GQ_OK;
+    GQ_HIP(hipMalloc(d, bytes));
+    bufs.p.push_back(*d);
+    if (h) GQ_HIP(hipMemcpyAsync(*d, h, bytes, hipMemcpyHostToDevice, s));
+    return GQ_OK;
+  };
+  void *dtx, *dty, *dtz, *dts, *dout;
+  GQ_TRY(up(tx.data(), n_tgt * sizeof(double), &dtx));
+  GQ_TRY(up(ty.data(), n_tgt * sizeof(double), &dty));
+  GQ_TRY(up(tz.data(), n_tgt * sizeof(double), &dtz));
+  GQ_TRY(up(tgt_side, tgt_side ? n_tgt : 0, &dts));
+  GQ_TRY(up(nullptr, n_tgt * sizeof(int64_t), &dout));
+  gq::AssocCells dc[2]{};
+  Sorted* hs[2] = {&S, &Cs};
+  for (int w = 0; w < 2; ++w) {
+    Sorted& o = *hs[w];
+    const size_t n = o.x.size();
+    void *st, *x, *y, *z, *r, *sd = nullptr, *id = nullptr;
+    GQ_TRY(up(o.start.data(), o.start.size() * sizeof(int64_t), &st));
+    GQ_TRY(up(o.x.data(), n * sizeof(double), &x));
+    GQ_TRY(up(o.y.data(), n * sizeof(double), &y));
+    GQ_TRY(up(o.z.data(), n * sizeof(double), &z));
+    GQ_TRY(up(o.r.data(), n * sizeof(double), &r));
+    if (w == 1) {
+      GQ_TRY(up(o.side.empty() ? nullptr : o.side.data(), o.side.size(), &sd));
+      GQ_TRY(up(o.id.data(), n * sizeof(int64_t), &id));
+    }
+    dc[w] = gq::AssocCells{(const int64_t*)st, (const double*)x, (const double*)y,
+                           (const double*)z, (const double*)r, (const int8_t*)sd,
+                           (const int64_t*)id};
+  }
+  gq::launch_associate(s, n_tgt, (const double*)dtx, (const double*)dty, (const double*)dtz,
+                       (const int8_t*)dts, g, dc[0], dc[1], (int64_t*)dout);
+  GQ_HIP(hipGetLastError());
+  GQ_HIP(hipMemcpyAsync(tgt_center, dout, n_tgt * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  GQ_HIP(hipStreamSynchronize(s));
+  return GQ_OK;
+}
+
 gq_status gq_set_source_interp(gq_plan* P, int64_t n_elem, int n_node, int n_quad,
                                const double* interp) {
   g_err.clear();

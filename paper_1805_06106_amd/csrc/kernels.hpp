@@ -31,6 +31,25 @@ void launch_strength_interp(hipStream_t s, int64_t n, const int64_t* order, cons
                             double* q);
 void launch_fill(hipStream_t s, double* p, int64_t n, double v);
 
+// Target association (associate.hip).  A uniform grid of n[0] x n[1] x n[2] cells of width
+// h from lo; cell (i, j, k) has linear index (k * n[1] + j) * n[0] + i.
+struct AssocGrid {
+  double lo[3];
+  double h;
+  int n[3];
+};
+// Points sorted by cell: cell c holds [start[c], start[c + 1]); r is the query radius of
+// each point (danger radius, or center radius times 1 + tol); side and id for centers only.
+struct AssocCells {
+  const int64_t* start;
+  const double *x, *y, *z, *r;
+  const int8_t* side;
+  const int64_t* id;
+};
+void launch_associate(hipStream_t s, int64_t nt, const double* tx, const double* ty,
+                      const double* tz, const int8_t* tside, const AssocGrid& g,
+                      const AssocCells& src, const AssocCells& ctr, int64_t* out);
+
 // Stage 2a: multipoles (scaled) of leaf boxes from their own sources.  Item i: box
 // boxes[i], sources idx[ptr[i] .. ptr[i+1]) (tree positions).  Overwrites.  (kernels_p2x.hip)
 void launch_p2m(hipStream_t s, int kernel, int p, int nitem, const int* boxes,

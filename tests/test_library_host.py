@@ -283,3 +283,23 @@ def test_source_interp_validation(gq):
     with pytest.raises(G.GQError) as e:
         P.set_source_interp(w.n_elem, w.interp)
     assert "host-only" in str(e.value)
+
+
+def test_associate_targets_validation(gq):
+    """Argument errors of gq_associate_targets are found on the host, before any device
+    work."""
+    G = gq
+    s3, c3, t3 = np.zeros((2, 3)), np.ones((1, 3)), np.zeros((3, 3))
+    bad = [dict(src_danger=[1.0, -1.0]), dict(src_danger=[1.0, np.nan]), dict(ctr_radius=[0.0]),
+           dict(tol=-0.1), dict(tol=np.inf), dict(tgt_side=[0, 1, 0]),
+           dict(ctr_side=[2], tgt_side=[0, 0, 0]), dict(ctr_side=[1], tgt_side=[0, 3, 0]),
+           dict(tgt_xyz=np.array([[0, 0, np.nan]]))]
+    for over in bad:
+        a = dict(src_xyz=s3, src_danger=[1.0, 1.0], ctr_xyz=c3, ctr_radius=[1.0], tgt_xyz=t3)
+        a.update(over)
+        with pytest.raises(G.GQError) as e:
+            G.associate_targets(**a)
+        assert e.value.status == 1, over
+    assert G.associate_targets(s3, [1.0, 1.0], c3, [1.0], np.zeros((0, 3))).shape == (0,)
+    got = G.associate_targets(np.zeros((0, 3)), [], c3, [1.0], t3)  # no sources: no danger
+    assert got.tolist() == [G.GQ_TARGET_FAR] * 3

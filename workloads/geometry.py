@@ -234,6 +234,10 @@ class Workload:
     n_elem: int = 0
     node_xyz: np.ndarray | None = None     # (n_elem * n_node, 3)
     node_normal: np.ndarray | None = None  # (n_elem * n_node, 3)
+    # Element size data for target association: each source's danger radius (half its
+    # element's size) and each center's side (+1 exterior, -1 interior).
+    src_radius: np.ndarray | None = None
+    ctr_side: np.ndarray | None = None
 
     @property
     def n_src(self):
@@ -347,6 +351,7 @@ def make_workload(name, *, level, order, spec: SurfaceSpec, kernel, p_qbx, p_fmm
         meta=dict(level=level, order=order, n_triangles=ntri, seed=seed,
                   curved=spec.curved, bump=(spec.bump_k, spec.bump_m, spec.bump_a),
                   scale=spec.scale, density=density),
+        src_radius=rk.copy(), ctr_side=np.tile(np.array([1, -1], dtype=np.int8), n),
     )
 
 
@@ -434,11 +439,13 @@ def oversampled_workload(name, *, level, spec: SurfaceSpec, kernel, p_qbx, p_fmm
         ctr[1::2] = node - rk[:, None] * node_nrm
         crad = np.repeat(rk, 2)
         tgt = np.repeat(node, 2, axis=0)
+        side = np.tile(np.array([1, -1], dtype=np.int8), nn)
     elif sides in ("interior", "exterior"):
         sgn = -1.0 if sides == "interior" else 1.0
         ctr = node + sgn * rk[:, None] * node_nrm
         crad = rk.copy()
         tgt = node.copy()
+        side = np.full(nn, int(sgn), dtype=np.int8)
     else:
         raise ValueError(sides)
     rng = np.random.default_rng(seed)
@@ -452,7 +459,8 @@ def oversampled_workload(name, *, level, spec: SurfaceSpec, kernel, p_qbx, p_fmm
         meta=dict(level=level, node_order=node_order, quad_order=quad_order, sub=sub,
                   n_triangles=ne, seed=seed, sides=sides, curved=spec.curved,
                   bump=(spec.bump_k, spec.bump_m, spec.bump_a), scale=spec.scale),
-        interp=interp, n_elem=ne, node_xyz=node, node_normal=node_nrm)
+        interp=interp, n_elem=ne, node_xyz=node, node_normal=node_nrm,
+        src_radius=np.repeat(rk[::xn.shape[0]], xq.shape[0]), ctr_side=side)
 
 
 def workload_c1(nmax=512, n_densities=1, p_fmm=10, p_qbx=3, kernel="S"):
