@@ -3,7 +3,8 @@
 
 Workload (default): the 'urchin' surface rho = 1 + 0.2 Re Y_8^4 on 20,480 curved triangles,
 28 nodes per triangle (573,440 sources), two QBX centers per node (1,146,880 centers, one
-target each), double-layer potential, p_qbx = 5, p_fmm = 15, nmax = 512, t_f = 0.9, FP64.
+target each), double-layer potential, p_qbx = 5, p_fmm = 15, nmax = 512, t_f = 0.9, FP64;
+level-restricted tree, Remark 4 at 64 sources (both paper options, measured fastest here).
 One step = one full evaluation (Algorithm 5 Stages 2-9) of one density with the plan cached
 and all inputs resident in HBM.
 
@@ -38,7 +39,13 @@ COUNTER_TRAFFIC = {
 }
 
 
-def counter_traffic(kernel, workload, wfar_direct_max):
+def tree_opts(args):
+    """Plan options that shape the tree and lists: Remark 4's threshold and level
+    restriction."""
+    return {"wfar_direct_max": args.wfar_direct_max, "level_restrict": bool(args.level_restrict)}
+
+
+def counter_traffic(kernel, workload, wfar_direct_max, level_restrict):
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_1805_06106_amd", "csrc")
@@ -50,7 +57,8 @@ def counter_traffic(kernel, workload, wfar_direct_max):
     h = h.hexdigest()
     c = COUNTER_TRAFFIC
     if (h != c["kernels_sha256"] or workload != c["workload"]
-            or wfar_direct_max != c["wfar_direct_max"]):
+            or wfar_direct_max != c["wfar_direct_max"]
+            or level_restrict != c.get("level_restrict", False)):
         return None
     return c["bytes_per_launch"].get(kernel)
 
@@ -78,7 +86,8 @@ def main():
     ap.add_argument("--study", choices=["greens", "tcr", "scaling", "solve"], default=None,
                     help="greens: Green's-formula accuracy sweep over p_fmm x p_qbx on the "
                          "urchin; tcr: modeled cost and time of the ball-shaped vs the "
-                         "box-shaped target confinement region; scaling: modeled cost (and "
+                         "box-shaped target confinement region, and of a level-restricted "
+                         "tree; scaling: modeled cost (and "
                          "time, with a GPU) over urchins of growing size; solve: the interior "
                          "Dirichlet problem on an oversampled urchin by GMRES with "
                          "split-precision applies and FP64 refinement; instead of the timing "
@@ -96,9 +105,14 @@ def main():
                     help="first run one plain elementwise copy (y = -x) over 1 GiB, so that a "
                          "hardware-counter pass can scale its byte counters by a kernel of "
                          "known traffic")
-    ap.add_argument("--wfar-direct-max", type=int, default=128,
+    ap.add_argument("--wfar-direct-max", type=int, default=64,
                     help="Remark 4: List 3 far boxes with at most this many sources are "
-                         "evaluated directly (0 disables); 128 is the measured optimum here")
+                         "evaluated directly (0 disables); 64 with the level-restricted tree "
+                         "(128 without it) is the measured optimum here")
+    ap.add_argument("--level-restrict", type=int, choices=[0, 1], default=1,
+                    help="1 (default): level-restricted tree, adjacent leaves differ by at most "
+                         "one level (the remark on List 3 complexity); 0: the adaptive tree as "
+                         "built")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 200 if args.workload == "c5" else 10
@@ -145,8 +159,8 @@ def main():
 
     def run(precision):
         t0 = time.time()
-        plan = Plan.from_workload(w, timing=True, wfar_direct_max=args.wfar_direct_max,
-                                  precision=precision)
+        plan = Plan.from_workload(w, timing=True, precision=precision,
+                                  **tree_opts(args))
         plan_wall = time.time() - t0
         st = plan.stats()
         log(f"[{precision}] plan: {st['n_boxes']} boxes, {st['n_levels']} levels, pairs "
@@ -183,7 +197,8 @@ def main():
     roofline = {"kernel": dominant, "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
-                "traffic": counter_traffic(dominant, w.name, args.wfar_direct_max),
+                "traffic": counter_traffic(dominant, w.name, args.wfar_direct_max,
+                                           bool(args.level_restrict)),
                 "flops_per_launch": flops[dominant], "ms_per_launch": round(dom_ms, 4)}
     per_stage = {}
     for s, f in flops.items():
@@ -251,7 +266,8 @@ def main():
         "config": {"workload": w.name, "kernel": w.kernel, "p_qbx": w.p_qbx, "p_fmm": w.p_fmm,
                    "n_sources": w.n_src, "n_centers": w.n_ctr, "n_targets": w.n_tgt,
                    "nmax": w.nmax, "tcf": w.tcf, "n_densities": 1, "precision": "fp64",
-                   "wfar_direct_max": args.wfar_direct_max},
+                   "wfar_direct_max": args.wfar_direct_max,
+                   "level_restrict": bool(args.level_restrict)},
         "rel_err_vs_direct_qbx": err_direct,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -296,7 +312,7 @@ def study_greens(args, dev):
             pots = {}
             for kern, dens in (("S", dudn), ("D", u)):
                 P = Plan.from_workload(w, kernel=kern, p_fmm=p_fmm, p_qbx=p_qbx,
-                                       wfar_direct_max=args.wfar_direct_max)
+                                       **tree_opts(args))
                 pots[kern] = P.apply(torch.tensor(dens[None, :], device=dev))[0].cpu().numpy()
                 P.close()
             E = pots["S"][interior] - pots["D"][interior] - utgt
@@ -306,7 +322,7 @@ def study_greens(args, dev):
             log(f"p_fmm={p_fmm:2d} p_qbx={p_qbx}: {err:.3e}  ({time.time() - t0:.1f}s)")
     print(json.dumps({"study": "greens_formula", "workload": w.name, "charge": x0.tolist(),
                       "nmax": w.nmax, "tcf": w.tcf, "wfar_direct_max": args.wfar_direct_max,
-                      "rows": rows}), flush=True)
+                      "level_restrict": bool(args.level_restrict), "rows": rows}), flush=True)
 
 
 def study_scaling(args):
@@ -357,8 +373,9 @@ def study_scaling(args):
 def study_tcr(args, dev):
     """The cost comparison of Section 6 (Table 8) on the urchin: modeled operation counts
     per interaction list (Table 7 model) and measured apply time, for the ball-shaped TCR
-    of this method and the box-shaped TCR of the earlier algorithm.  Remark 4 is off for
-    both, so the lists are the plain ones."""
+    of this method and the box-shaped TCR of the earlier algorithm, and for the ball with a
+    level-restricted tree (the remark on List 3 complexity).  Remark 4 is off for all, so
+    the lists are the plain ones."""
     import numpy as np
     import torch
 
@@ -371,8 +388,10 @@ def study_tcr(args, dev):
     out = {"study": "tcr_shape", "workload": w.name, "p_fmm": w.p_fmm, "p_qbx": w.p_qbx,
            "nmax": w.nmax, "tcf": w.tcf, "rows": {}}
     pots = {}
-    for tcr in ("linf", "l2"):
-        P = Plan.from_workload(w, tcr_norm=tcr, timing=True)
+    variants = {"linf": dict(tcr_norm="linf"), "l2": dict(tcr_norm="l2"),
+                "l2_level_restricted": dict(tcr_norm="l2", level_restrict=True)}
+    for tcr, kw in variants.items():
+        P = Plan.from_workload(w, timing=True, **kw)
         st = P.stats()
         model = CM.paper_list_model(st, w.p_fmm, w.p_qbx)
         pot = torch.empty((1, w.n_tgt), dtype=torch.float64, device=dev)
@@ -399,6 +418,8 @@ def study_tcr(args, dev):
                                       / out["rows"]["linf"]["ms_per_apply"])
     out["rel_diff_potentials"] = float(np.max(np.abs(pots["l2"] - pots["linf"]))
                                        / np.max(np.abs(pots["l2"])))
+    out["rel_diff_level_restricted"] = float(np.max(np.abs(pots["l2"] - pots["l2_level_restricted"]))
+                                             / np.max(np.abs(pots["l2"])))
     print(json.dumps(out), flush=True)
 
 
@@ -419,7 +440,7 @@ def bench_fresh_densities(args, dev):
     log(f"workload {w.name}: {w.n_src} sources, {w.n_tgt} targets, {n} fresh densities "
         f"({time.time() - t0:.1f}s)")
     t0 = time.time()
-    plan = Plan.from_workload(w, wfar_direct_max=args.wfar_direct_max, precision="fp32_split")
+    plan = Plan.from_workload(w, **tree_opts(args), precision="fp32_split")
     plan_s = time.time() - t0
     out = torch.empty((n, w.n_tgt), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -434,7 +455,7 @@ def bench_fresh_densities(args, dev):
     ms = (time.perf_counter() - t) * 1e3 / args.steps
     plan.close()
     # accuracy: the last density through the FP64 path, and through direct QBX on a sample
-    ref64 = Plan.from_workload(w, wfar_direct_max=args.wfar_direct_max)
+    ref64 = Plan.from_workload(w, **tree_opts(args))
     last = ref64.apply(dens[n - 1:n])[0]
     err64 = float((out[n - 1] - last).abs().max() / last.abs().max())
     ref64.close()
@@ -461,7 +482,8 @@ def bench_fresh_densities(args, dev):
         "config": {"workload": f"{w.name}, plan cached, fresh density per apply",
                    "kernel": w.kernel, "p_qbx": w.p_qbx, "p_fmm": w.p_fmm,
                    "n_sources": w.n_src, "n_targets": w.n_tgt, "precision": "fp32_split",
-                   "densities": n, "wfar_direct_max": args.wfar_direct_max},
+                   "densities": n, "wfar_direct_max": args.wfar_direct_max,
+                   "level_restrict": bool(args.level_restrict)},
         "rel_err_vs_fp64_path": err64, "rel_err_vs_direct_qbx": err_direct,
         "plan_seconds": round(plan_s, 3)}), flush=True)
 
@@ -493,8 +515,8 @@ def study_solve(args, dev):
     g_np = 1.0 / (4 * np.pi * np.linalg.norm(w.node_xyz - x0, axis=1))
     g = torch.tensor(g_np, device=dev)
     t0 = time.time()
-    hi = Plan.from_workload(w, wfar_direct_max=args.wfar_direct_max)
-    lo = Plan.from_workload(w, wfar_direct_max=args.wfar_direct_max, precision="fp32_split")
+    hi = Plan.from_workload(w, **tree_opts(args))
+    lo = Plan.from_workload(w, **tree_opts(args), precision="fp32_split")
     plan_s = time.time() - t0
     A_hi, A_lo = plan_operator(hi), plan_operator(lo)
     for A in (A_hi, A_lo):  # warm
@@ -563,7 +585,7 @@ def bench_batch(args, dev):
 
     # plain FP64: one plan per surface
     t0 = time.time()
-    plans = [Plan.from_workload(w, n_densities=nd, wfar_direct_max=args.wfar_direct_max)
+    plans = [Plan.from_workload(w, n_densities=nd, **tree_opts(args))
              for w in ws]
     plan64_s = time.time() - t0
     outs = [torch.empty((nd, w.n_tgt), dtype=torch.float64, device=dev) for w in ws]
@@ -580,7 +602,7 @@ def bench_batch(args, dev):
     for prec in ("fp64", "fp32_split"):
         t0 = time.time()
         members = plans if prec == "fp64" else [
-            Plan.from_workload(w, n_densities=nd, wfar_direct_max=args.wfar_direct_max,
+            Plan.from_workload(w, n_densities=nd, **tree_opts(args),
                                precision=prec) for w in ws]
         B = Plan.batch(members, graph=True, autotune=True)
         if prec != "fp64":
@@ -610,7 +632,8 @@ def bench_batch(args, dev):
                    "p_fmm": 15, "n_surfaces": len(ws), "n_densities": nd,
                    "n_sources": n_src, "n_targets": n_tgt,
                    "levels": [w.meta["level"] for w in ws],
-                   "wfar_direct_max": args.wfar_direct_max},
+                   "wfar_direct_max": args.wfar_direct_max,
+                   "level_restrict": bool(args.level_restrict)},
         "plain_fp64": {"value": round(nd * n_tgt / (ms_plain * 1e-3), 1),
                        "ms_per_apply": round(ms_plain, 3), "plan_seconds": round(plan64_s, 2)},
         "batched_fp64_graph": res["fp64"],

@@ -96,6 +96,11 @@ typedef struct {
      earlier two-dimensional algorithm, kept for the cost comparison of Section 6 (Theorem 1
      is stated for the ball). */
   int tcr_norm;
+  /* Level restriction (the remark on List 3 complexity in Section 5): 1 refines the tree
+     after Stage 1 until leaves that touch differ by at most one level, splitting the
+     coarser leaf of each offending pair by the usual rule (a leaf where nothing can move
+     stays); 0 (default) keeps the adaptive tree as built. */
+  int level_restrict;
 } gq_params;
 
 typedef struct gq_plan gq_plan; /* opaque */

@@ -82,7 +82,7 @@ def _dyadic_root(lo, hi):
 class OracleTree:
     """Stage 1: octree with target-confinement-restricted centers."""
 
-    def __init__(self, src, ctr, crad, tgt, nmax, tcf, tcr_norm="l2"):
+    def __init__(self, src, ctr, crad, tgt, nmax, tcf, tcr_norm="l2", level_restrict=False):
         src, ctr, crad, tgt = _f64(src), _f64(ctr), _f64(crad), _f64(tgt)
         self.tcf = float(tcf)
         if tcr_norm not in ("l2", "linf"):
@@ -96,6 +96,59 @@ class OracleTree:
         own_s = [np.arange(src.shape[0])]
         own_c = [np.arange(ctr.shape[0])]
         own_t = [np.arange(tgt.shape[0])]
+        def split(b):
+            """Subdivide box b by the Stage 1 rule; returns the new children (none if
+            nothing would move)."""
+            xb, hb = centers[b], halfw[b]
+            hc = hb * 0.5
+
+            def octant(P):
+                return ((P[:, 0] >= xb[0]).astype(np.int64)
+                        + 2 * (P[:, 1] >= xb[1]).astype(np.int64)
+                        + 4 * (P[:, 2] >= xb[2]).astype(np.int64))
+
+            def child_center(o):
+                return xb + hc * np.array([1.0 if o & 1 else -1.0,
+                                           1.0 if o & 2 else -1.0,
+                                           1.0 if o & 4 else -1.0])
+
+            os_ = octant(src[own_s[b]])
+            ot_ = octant(tgt[own_t[b]])
+            oc_ = octant(ctr[own_c[b]])
+            cc = np.array([child_center(o) for o in range(8)])
+            cpos = ctr[own_c[b]]
+            d = cpos - cc[oc_]
+            if self.linf:
+                dist = np.max(np.abs(d), axis=1)
+                fits = dist + crad[own_c[b]] <= hc * (1.0 + self.tcf)
+            else:
+                dist = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
+                fits = dist + crad[own_c[b]] <= (SQRT3 * hc) * (1.0 + self.tcf)
+            if len(own_s[b]) + len(own_t[b]) + int(fits.sum()) == 0:
+                return []  # subdividing would only produce empty children
+            made = []
+            for o in range(8):
+                s_o = own_s[b][os_ == o]
+                t_o = own_t[b][ot_ == o]
+                c_o = own_c[b][(oc_ == o) & fits]
+                if len(s_o) + len(t_o) + len(c_o) == 0:
+                    continue
+                cid = len(centers)
+                centers.append(cc[o])
+                halfw.append(hc)
+                level.append(level[b] + 1)
+                parent.append(b)
+                children.append([])
+                children[b].append(cid)
+                own_s.append(s_o)
+                own_t.append(t_o)
+                own_c.append(c_o)
+                made.append(cid)
+            own_s[b] = own_s[b][:0]
+            own_t[b] = own_t[b][:0]
+            own_c[b] = own_c[b][~fits]
+            return made
+
         frontier = [0]
         while frontier:
             nxt = []
@@ -103,54 +156,40 @@ class OracleTree:
                 n_own = len(own_s[b]) + len(own_c[b]) + len(own_t[b])
                 if n_own <= self.nmax or level[b] >= MAX_LEVEL:
                     continue
-                xb, hb = centers[b], halfw[b]
-                hc = hb * 0.5
-
-                def octant(P):
-                    return ((P[:, 0] >= xb[0]).astype(np.int64)
-                            + 2 * (P[:, 1] >= xb[1]).astype(np.int64)
-                            + 4 * (P[:, 2] >= xb[2]).astype(np.int64))
-
-                def child_center(o):
-                    return xb + hc * np.array([1.0 if o & 1 else -1.0,
-                                               1.0 if o & 2 else -1.0,
-                                               1.0 if o & 4 else -1.0])
-
-                os_ = octant(src[own_s[b]])
-                ot_ = octant(tgt[own_t[b]])
-                oc_ = octant(ctr[own_c[b]])
-                cc = np.array([child_center(o) for o in range(8)])
-                cpos = ctr[own_c[b]]
-                d = cpos - cc[oc_]
-                if self.linf:
-                    dist = np.max(np.abs(d), axis=1)
-                    fits = dist + crad[own_c[b]] <= hc * (1.0 + self.tcf)
-                else:
-                    dist = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
-                    fits = dist + crad[own_c[b]] <= (SQRT3 * hc) * (1.0 + self.tcf)
-                if len(own_s[b]) + len(own_t[b]) + int(fits.sum()) == 0:
-                    continue  # subdividing would only produce empty children
-                for o in range(8):
-                    s_o = own_s[b][os_ == o]
-                    t_o = own_t[b][ot_ == o]
-                    c_o = own_c[b][(oc_ == o) & fits]
-                    if len(s_o) + len(t_o) + len(c_o) == 0:
-                        continue
-                    cid = len(centers)
-                    centers.append(cc[o])
-                    halfw.append(hc)
-                    level.append(level[b] + 1)
-                    parent.append(b)
-                    children.append([])
-                    children[b].append(cid)
-                    own_s.append(s_o)
-                    own_t.append(t_o)
-                    own_c.append(c_o)
-                    nxt.append(cid)
-                own_s[b] = own_s[b][:0]
-                own_t[b] = own_t[b][:0]
-                own_c[b] = own_c[b][~fits]
+                nxt += split(b)
             frontier = nxt
+        if level_restrict:
+            # Level restriction (the remark on List 3 complexity): adjacent leaves may differ
+            # by at most one level.  Every pass looks at all pairs of leaves; a leaf that
+            # touches (closed cubes meet) a leaf at least two levels finer is split.
+            while True:
+                leaves = [b for b in range(len(centers)) if not children[b]]
+                C = np.array([centers[b] for b in leaves])
+                H = np.array([halfw[b] for b in leaves])
+                lev = np.array([level[b] for b in leaves])
+                todo = []
+                for i, b in enumerate(leaves):
+                    if level[b] >= MAX_LEVEL:
+                        continue
+                    touch = np.all(np.abs(C - C[i]) <= (H + H[i])[:, None], axis=1)
+                    if np.any(touch & (lev >= lev[i] + 2)):
+                        todo.append(b)
+                made = [c for b in todo for c in split(b)]
+                if not made:
+                    break
+            # breadth-first renumbering, children in octant order (the plain build's order)
+            order = [0]
+            for b in order:  # the list grows while it is walked
+                order += children[b]  # created in octant order
+            new = {b: i for i, b in enumerate(order)}
+            centers = [centers[b] for b in order]
+            halfw = [halfw[b] for b in order]
+            level = [level[b] for b in order]
+            parent = [-1 if parent[b] < 0 else new[parent[b]] for b in order]
+            children = [[new[c] for c in children[b]] for b in order]
+            own_s = [own_s[b] for b in order]
+            own_c = [own_c[b] for b in order]
+            own_t = [own_t[b] for b in order]
         self.center = np.array(centers)
         self.h = np.array(halfw)
         self.level = np.array(level, dtype=np.int64)
@@ -425,7 +464,7 @@ class OracleFMM:
     """Tier B: GIGAQBX evaluation of the S or D layer potential."""
 
     def __init__(self, w, nmax=None, tcf=None, p_fmm=None, p_qbx=None, nthreads=0,
-                 wfar_direct_max=0, tcr_norm="l2"):
+                 wfar_direct_max=0, tcr_norm="l2", level_restrict=False):
         self.w = w
         self.kernel = w.kernel
         self.p = int(w.p_fmm if p_fmm is None else p_fmm)
@@ -433,7 +472,7 @@ class OracleFMM:
         self.nthreads = nthreads
         self.tree = OracleTree(w.src_xyz, w.ctr_xyz, w.ctr_radius, w.tgt_xyz,
                                w.nmax if nmax is None else nmax,
-                               w.tcf if tcf is None else tcf, tcr_norm)
+                               w.tcf if tcf is None else tcf, tcr_norm, level_restrict)
         self.lists = OracleLists(self.tree, wfar_direct_max)
         self._mpole = {}
 

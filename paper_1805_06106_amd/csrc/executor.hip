@@ -806,6 +806,8 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
   if (prm->n_densities < 1) return fail(GQ_EINVAL, "n_densities must be >= 1");
   if (prm->wfar_direct_max < 0) return fail(GQ_EINVAL, "wfar_direct_max must be >= 0");
   if (prm->tcr_norm != 0 && prm->tcr_norm != 1) return fail(GQ_EINVAL, "tcr_norm must be 0 or 1");
+  if (prm->level_restrict != 0 && prm->level_restrict != 1)
+    return fail(GQ_EINVAL, "level_restrict must be 0 or 1");
   if ((prm->flags & GQ_FLAG_TIMING) && (prm->flags & GQ_FLAG_GRAPH))
     return fail(GQ_EINVAL, "GQ_FLAG_TIMING and GQ_FLAG_GRAPH are exclusive");
   if (prm->kernel == GQ_KERNEL_D && !src_normal) return fail(GQ_EINVAL, "double layer needs normals");
@@ -839,6 +841,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
   tp.nmax = prm->nmax;
   tp.tcf = prm->tcf;
   tp.tcr_linf = prm->tcr_norm == 1;
+  tp.level_restrict = prm->level_restrict == 1;
   std::string msg = gq::build_tree(tp, n_src, src_xyz, n_ctr, ctr_xyz, ctr_radius, n_tgt,
                                    tgt_xyz, P->tree);
   if (!msg.empty()) {

@@ -13,6 +13,8 @@
 //  * k-colleagues exclude the box itself; List 3's descendants are strict;
 //  * adjacent: closed cubes touch and neither box contains the other;
 //  * list entries are restricted to boxes whose subtree holds a source.
+//  * level restriction (optional): afterwards, a leaf touching a leaf two or more levels
+//    finer is split by the same rule, until no such pair is left (or nothing can move);
 //  * box-shaped TCR variant (tcr_linf): TCR(b) is the closed box of half-width |b|(1+t_f);
 //    a center descends iff |c - x_child|_inf + r_c <= |child|(1 + t_f), and
 //    a < TCR(b) iff |x_a - x_b|_inf - |b|(1+t_f) >= 3|a|.
@@ -111,61 +113,146 @@ std::string build_tree(const TreeParams& prm, int64_t n_src, const double* src,
     return (p[0] >= xb[0] ? 1 : 0) | (p[1] >= xb[1] ? 2 : 0) | (p[2] >= xb[2] ? 4 : 0);
   };
 
+  // Split box b: its sources and targets go to the octants that hold them, and each center
+  // descends to its octant's child iff its ball fits that child's confinement region (else
+  // it stays, suspended).  Only non-empty children are created.  False if nothing would
+  // move (the box stays a leaf).
+  auto split = [&](int b, std::vector<int>* created) -> bool {
+    const double xb[3] = {T.center[3 * b], T.center[3 * b + 1], T.center[3 * b + 2]};
+    const double hc = T.h[b] * 0.5;
+    double cc[8][3];
+    for (int o = 0; o < 8; ++o) {
+      cc[o][0] = xb[0] + ((o & 1) ? hc : -hc);
+      cc[o][1] = xb[1] + ((o & 2) ? hc : -hc);
+      cc[o][2] = xb[2] + ((o & 4) ? hc : -hc);
+    }
+    const double conf = prm.tcr_linf ? hc * (1.0 + prm.tcf) : (kSqrt3 * hc) * (1.0 + prm.tcf);
+    std::vector<int64_t> cs[8], ct[8], cc_[8], stay;
+    for (int64_t i : own_s[b]) cs[octant(src + 3 * i, xb)].push_back(i);
+    for (int64_t i : own_t[b]) ct[octant(tgt + 3 * i, xb)].push_back(i);
+    int64_t moved_c = 0;
+    for (int64_t i : own_c[b]) {
+      const double* p = ctr + 3 * i;
+      int o = octant(p, xb);
+      double dx = p[0] - cc[o][0], dy = p[1] - cc[o][1], dz = p[2] - cc[o][2];
+      double dist = prm.tcr_linf
+                        ? std::max(std::fabs(dx), std::max(std::fabs(dy), std::fabs(dz)))
+                        : std::sqrt((dx * dx + dy * dy) + dz * dz);
+      if (dist + crad[i] <= conf) {
+        cc_[o].push_back(i);
+        ++moved_c;
+      } else {
+        stay.push_back(i);
+      }
+    }
+    if ((int64_t)own_s[b].size() + (int64_t)own_t[b].size() + moved_c == 0) return false;
+    for (int o = 0; o < 8; ++o) {
+      if (cs[o].empty() && ct[o].empty() && cc_[o].empty()) continue;
+      int id = (int)T.h.size();
+      T.center.insert(T.center.end(), {cc[o][0], cc[o][1], cc[o][2]});
+      T.h.push_back(hc);
+      T.level.push_back(T.level[b] + 1);
+      T.parent.push_back(b);
+      T.child.push_back(none);
+      T.nchild.push_back(0);
+      T.child[b][o] = id;
+      T.nchild[b] += 1;
+      own_s.push_back(std::move(cs[o]));
+      own_t.push_back(std::move(ct[o]));
+      own_c.push_back(std::move(cc_[o]));
+      if (created) created->push_back(id);
+    }
+    own_s[b].clear();
+    own_t[b].clear();
+    own_c[b] = std::move(stay);
+    return true;
+  };
+
   std::vector<int> frontier = {0};
   while (!frontier.empty()) {
     std::vector<int> next;
     for (int b : frontier) {
       int64_t n_own = (int64_t)own_s[b].size() + own_c[b].size() + own_t[b].size();
       if (n_own <= prm.nmax || T.level[b] >= prm.max_level) continue;
-      const double xb[3] = {T.center[3 * b], T.center[3 * b + 1], T.center[3 * b + 2]};
-      const double hc = T.h[b] * 0.5;
-      double cc[8][3];
-      for (int o = 0; o < 8; ++o) {
-        cc[o][0] = xb[0] + ((o & 1) ? hc : -hc);
-        cc[o][1] = xb[1] + ((o & 2) ? hc : -hc);
-        cc[o][2] = xb[2] + ((o & 4) ? hc : -hc);
-      }
-      const double conf = prm.tcr_linf ? hc * (1.0 + prm.tcf) : (kSqrt3 * hc) * (1.0 + prm.tcf);
-      std::vector<int64_t> cs[8], ct[8], cc_[8], stay;
-      for (int64_t i : own_s[b]) cs[octant(src + 3 * i, xb)].push_back(i);
-      for (int64_t i : own_t[b]) ct[octant(tgt + 3 * i, xb)].push_back(i);
-      int64_t moved_c = 0;
-      for (int64_t i : own_c[b]) {
-        const double* p = ctr + 3 * i;
-        int o = octant(p, xb);
-        double dx = p[0] - cc[o][0], dy = p[1] - cc[o][1], dz = p[2] - cc[o][2];
-        double dist = prm.tcr_linf
-                          ? std::max(std::fabs(dx), std::max(std::fabs(dy), std::fabs(dz)))
-                          : std::sqrt((dx * dx + dy * dy) + dz * dz);
-        if (dist + crad[i] <= conf) {
-          cc_[o].push_back(i);
-          ++moved_c;
-        } else {
-          stay.push_back(i);
-        }
-      }
-      if ((int64_t)own_s[b].size() + (int64_t)own_t[b].size() + moved_c == 0) continue;
-      for (int o = 0; o < 8; ++o) {
-        if (cs[o].empty() && ct[o].empty() && cc_[o].empty()) continue;
-        int id = (int)T.h.size();
-        T.center.insert(T.center.end(), {cc[o][0], cc[o][1], cc[o][2]});
-        T.h.push_back(hc);
-        T.level.push_back(T.level[b] + 1);
-        T.parent.push_back(b);
-        T.child.push_back(none);
-        T.nchild.push_back(0);
-        T.child[b][o] = id;
-        T.nchild[b] += 1;
-        own_s.push_back(std::move(cs[o]));
-        own_t.push_back(std::move(ct[o]));
-        own_c.push_back(std::move(cc_[o]));
-        next.push_back(id);
-      }
-      own_s[b].clear();
-      own_t[b].clear();
-      own_c[b] = std::move(stay);
+      split(b, &next);
     }
     frontier = std::move(next);
+  }
+
+  if (prm.level_restrict) {
+    // Level restriction (the remark on List 3 complexity): while a leaf touches a leaf two
+    // or more levels finer, split the coarser one.  Splitting only refines, so the result
+    // does not depend on the order; leaves that cannot split (nothing would move) or sit
+    // at the level cap are left as they are.
+    for (;;) {
+      const int nb0 = (int)T.h.size();
+      auto icoord = [&](int b, int a) {
+        return (int64_t)std::floor((T.center[3 * b + a] - (x0[a] - h0)) / (2.0 * T.h[b]));
+      };
+      std::unordered_map<CellKey, int, CellHash> cells;
+      cells.reserve(2 * nb0);
+      for (int b = 0; b < nb0; ++b) cells[{T.level[b], icoord(b, 0), icoord(b, 1), icoord(b, 2)}] = b;
+      auto touches = [&](int x, int y) {
+        for (int a = 0; a < 3; ++a)
+          if (std::fabs(T.center[3 * x + a] - T.center[3 * y + a]) > T.h[x] + T.h[y]) return false;
+        return true;
+      };
+      // does the subtree of x hold a leaf of level >= lmin touching box a?
+      std::function<bool(int, int, int)> finer = [&](int x, int a, int lmin) -> bool {
+        if (!touches(x, a)) return false;
+        if (T.nchild[x] == 0) return T.level[x] >= lmin;
+        for (int o = 0; o < 8; ++o)
+          if (T.child[x][o] >= 0 && finer(T.child[x][o], a, lmin)) return true;
+        return false;
+      };
+      std::vector<int> todo;
+      for (int a = 0; a < nb0; ++a) {
+        if (T.nchild[a] != 0 || T.level[a] >= prm.max_level) continue;
+        const int64_t ix = icoord(a, 0), iy = icoord(a, 1), iz = icoord(a, 2);
+        bool bad = false;
+        for (int dz = -1; dz <= 1 && !bad; ++dz)
+          for (int dy = -1; dy <= 1 && !bad; ++dy)
+            for (int dx = -1; dx <= 1 && !bad; ++dx) {
+              if (!dx && !dy && !dz) continue;
+              auto it = cells.find({T.level[a], ix + dx, iy + dy, iz + dz});
+              if (it != cells.end() && finer(it->second, a, T.level[a] + 2)) bad = true;
+            }
+        if (bad) todo.push_back(a);
+      }
+      bool any = false;
+      for (int a : todo) any = split(a, nullptr) || any;
+      if (!any) break;
+    }
+    // canonical breadth-first numbering (children in octant order), as the plain build has
+    const int nbt = (int)T.h.size();
+    std::vector<int> order = {0}, newid(nbt, -1);
+    newid[0] = 0;
+    for (size_t i = 0; i < order.size(); ++i)
+      for (int o = 0; o < 8; ++o) {
+        const int c = T.child[order[i]][o];
+        if (c >= 0) {
+          newid[c] = (int)order.size();
+          order.push_back(c);
+        }
+      }
+    Tree R = T;
+    std::vector<std::vector<int64_t>> os(nbt), oc(nbt), ot(nbt);
+    for (int i = 0; i < nbt; ++i) {
+      const int b = order[i];
+      for (int a = 0; a < 3; ++a) R.center[3 * i + a] = T.center[3 * b + a];
+      R.h[i] = T.h[b];
+      R.level[i] = T.level[b];
+      R.parent[i] = T.parent[b] < 0 ? -1 : newid[T.parent[b]];
+      R.nchild[i] = T.nchild[b];
+      for (int o = 0; o < 8; ++o) R.child[i][o] = T.child[b][o] < 0 ? -1 : newid[T.child[b][o]];
+      os[i] = std::move(own_s[b]);
+      oc[i] = std::move(own_c[b]);
+      ot[i] = std::move(own_t[b]);
+    }
+    T = std::move(R);
+    own_s = std::move(os);
+    own_c = std::move(oc);
+    own_t = std::move(ot);
   }
   const int nb = (int)T.h.size();
   T.nboxes = nb;

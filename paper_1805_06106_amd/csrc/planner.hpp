@@ -15,6 +15,7 @@ struct TreeParams {
   double tcf = 0.9;
   int max_level = 30;
   bool tcr_linf = false;  // box-shaped target confinement region (cost comparison only)
+  bool level_restrict = false;  // adjacent leaves differ by at most one level
 };
 
 // Octree.  Boxes are numbered breadth-first, children in octant order (bit 0: x upper,

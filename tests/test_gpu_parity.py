@@ -199,6 +199,17 @@ def test_gpu_linf_tcr_vs_tier_b(dev, case):
     assert rel(pot[0][tids], ref) < TOL
 
 
+@pytest.mark.parametrize("case", ["S-l1-n32", "D-l2-flat", "S-l2-tf05"])
+def test_gpu_level_restricted_vs_tier_b(dev, case):
+    """A level-restricted tree (the remark on List 3 complexity): same kernels, a refined
+    tree, and the oracle's own level-restricted tree and lists."""
+    w = workload_tiny(**CASES[case])
+    print(f"[gpu] case={case} level-restricted", flush=True)
+    _, pot = run_gpu(w, dev, level_restrict=True)
+    tids, ref, _ = OracleFMM(w, level_restrict=True).evaluate()
+    assert rel(pot[0][tids], ref) < TOL
+
+
 @pytest.mark.parametrize("kernel", ["S", "D"])
 def test_gpu_point_targets_vs_tier_b(dev, kernel):
     """Conventional targets (tgt_center = -1) beside the QBX targets: both against the

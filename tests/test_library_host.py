@@ -48,13 +48,17 @@ CASES = {
 
 
 @pytest.mark.parametrize("case", sorted(CASES) + ["D-l1-n32-r4", "S-l1-n32-linf",
-                                                   "S-l2-tf05-linf", "D-l2-flat-linf"])
+                                                   "S-l2-tf05-linf", "D-l2-flat-linf",
+                                                   "S-l1-n32-lr", "D-l2-flat-lr",
+                                                   "S-l2-tf05-lr"])
 def test_planner_matches_oracle_lists(gq, case):
     thr = 24 if case.endswith("-r4") else 0
     tcr = "linf" if case.endswith("-linf") else "l2"
-    w = workload_tiny(**CASES[case.replace("-r4", "").replace("-linf", "")])
-    P = gq.Plan.from_workload(w, host_only=True, wfar_direct_max=thr, tcr_norm=tcr)
-    F = OracleFMM(w, wfar_direct_max=thr, tcr_norm=tcr)
+    lr = case.endswith("-lr")
+    w = workload_tiny(**CASES[case.replace("-r4", "").replace("-linf", "").replace("-lr", "")])
+    P = gq.Plan.from_workload(w, host_only=True, wfar_direct_max=thr, tcr_norm=tcr,
+                              level_restrict=lr)
+    F = OracleFMM(w, wfar_direct_max=thr, tcr_norm=tcr, level_restrict=lr)
     c, h, lev, par, own = P.tree()
     t = F.tree
     assert len(h) == t.nboxes

@@ -239,3 +239,34 @@ def test_point_targets_single_box_and_accuracy(kernel):
     # and the QBX targets are unaffected by the extra points being in the tree
     t2, p2, _ = F.evaluate()
     assert np.all(w.tgt_center[t2] >= 0)
+
+
+@pytest.mark.parametrize("case", ["S-l1", "D-l2-flat", "S-l2-tf05"])
+def test_level_restriction_balance_refinement_and_accuracy(case):
+    """The level-restricted tree (the remark on List 3 complexity): no two touching leaves
+    differ by two or more levels unless the coarser one cannot split; it refines the plain
+    tree (every plain box is still there, with the same particles below it); the lists
+    still reach every source leaf exactly once; and the result stays within the
+    acceleration bound.  The check of "touching" is a separate brute force over exact
+    dyadic box geometry."""
+    w = workload_tiny(**CASES[case])
+    plain = OracleFMM(w).tree
+    F = OracleFMM(w, level_restrict=True)
+    t = F.tree
+    assert t.nboxes > plain.nboxes  # these trees are not balanced to begin with
+    keys = {t.key(b) for b in range(t.nboxes)}
+    assert all(plain.key(b) in keys for b in range(plain.nboxes))
+    leaves = np.nonzero(t.is_leaf)[0]
+    for i in leaves:
+        for j in leaves:
+            if t.level[j] < t.level[i] + 2:
+                continue
+            gap = np.abs(t.center[i] - t.center[j]) - (t.h[i] + t.h[j])
+            if np.all(gap <= 0):  # closed cubes meet: i must be unable to split
+                assert len(t.own_src[i]) == 0 and len(t.own_tgt[i]) == 0, (i, j)
+    for b in F.list_owner_boxes():
+        missing, multi = F.partition_check(b)
+        assert not missing and not multi, (b, missing, multi)
+    ref = _tier_a(w)
+    tids, pot, _ = F.evaluate()
+    assert np.max(np.abs(pot - ref[tids])) / np.max(np.abs(ref)) <= 0.75 ** (w.p_fmm + 1)
