@@ -33,9 +33,10 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # while it matches, else null.
 COUNTER_TRAFFIC = {
     "kernels_sha256": "d5c26154cfa095d05a03979dbe640350b80fad0ca8b510676ee2371afd08fc28",
-    "workload": "urchin8-20480", "wfar_direct_max": 128, "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 5.97828e+09, "m2l": 1.34249e+10, "m2qbxl": 2.6333e+08,
-                         "l2qbxl": 9.3864e+08},
+    "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
+    "precision": "fp64",
+    "bytes_per_launch": {"p2qbxl": 5.26972e+09, "m2l": 1.404085e+10, "m2qbxl": 8.948e+07,
+                         "l2qbxl": 9.4045e+08},
 }
 
 

@@ -160,19 +160,28 @@ class OracleTree:
             frontier = nxt
         if level_restrict:
             # Level restriction (the remark on List 3 complexity): adjacent leaves may differ
-            # by at most one level.  Every pass looks at all pairs of leaves; a leaf that
-            # touches (closed cubes meet) a leaf at least two levels finer is split.
+            # by at most one level.  Every pass checks each leaf against the leaves at least
+            # two levels finer; one that touches (closed cubes meet) such a leaf is split.
+            # A k-d tree in the max norm only narrows the candidates: its radius h_i + h_max
+            # (slightly widened) covers every leaf that can touch leaf i, and the exact
+            # test below decides.
+            from scipy.spatial import cKDTree
+
             while True:
                 leaves = [b for b in range(len(centers)) if not children[b]]
                 C = np.array([centers[b] for b in leaves])
                 H = np.array([halfw[b] for b in leaves])
                 lev = np.array([level[b] for b in leaves])
+                kd = cKDTree(C)
+                near = kd.query_ball_point(C, (H + H.max()) * (1.0 + 1e-9), p=np.inf)
                 todo = []
                 for i, b in enumerate(leaves):
                     if level[b] >= MAX_LEVEL:
                         continue
-                    touch = np.all(np.abs(C - C[i]) <= (H + H[i])[:, None], axis=1)
-                    if np.any(touch & (lev >= lev[i] + 2)):
+                    j = np.asarray(near[i], dtype=np.int64)
+                    j = j[lev[j] >= lev[i] + 2]
+                    touch = np.all(np.abs(C[j] - C[i]) <= (H[j] + H[i])[:, None], axis=1)
+                    if np.any(touch):
                         todo.append(b)
                 made = [c for b in todo for c in split(b)]
                 if not made:
