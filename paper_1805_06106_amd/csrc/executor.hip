@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -211,7 +212,53 @@ void center_items(const gq::Tree& T, int b, int chunk, std::vector<int>& box,
   }
 }
 
-// Near-field items, most expensive first, so that the longest workgroups start early.
+// Near-field items.  An item of r <= 64 centers runs one wave with S = 64 / r source slices,
+// so r * S of its 64 lanes work and the wave makes n / S passes over the box's n near
+// sources.  Cutting a box's centers into plain 64-chunks leaves the last chunk with up to
+// half its lanes idle (r = 33 gives S = 1); instead the remainder is split into chunks that
+// fill the lanes (37 = 32 + 5: S = 2 and 12), chosen by a small dynamic program that
+// minimizes the passes sum(1 / S) plus a per-item charge of 1/64 for staging the sources
+// once more.
+const std::array<std::vector<int>, 64>& near_chunk_table() {
+  static const std::array<std::vector<int>, 64> table = [] {
+    std::array<double, 64> best{};
+    std::array<int, 64> first{};
+    for (int r = 1; r < 64; ++r) {
+      best[r] = 1e30;
+      for (int k = 1; k <= r; ++k) {
+        const double c = 1.0 / (64 / k) + 1.0 / 64 + best[r - k];
+        if (c < best[r] - 1e-12) {
+          best[r] = c;
+          first[r] = k;
+        }
+      }
+    }
+    std::array<std::vector<int>, 64> t;
+    for (int r = 1; r < 64; ++r)
+      for (int q = r; q > 0; q -= first[q]) t[r].push_back(first[q]);
+    return t;
+  }();
+  return table;
+}
+
+void near_center_items(const gq::Tree& T, int b, std::vector<int>& box, std::vector<int>& c0,
+                       std::vector<int>& nc) {
+  int64_t s = T.ctr_start[b], n = T.ctr_count[b];
+  auto push = [&](int64_t o, int k) {
+    box.push_back(b);
+    c0.push_back((int)(s + o));
+    nc.push_back(k);
+  };
+  int64_t o = 0;
+  for (; o + 64 <= n; o += 64) push(o, 64);
+  for (int k : near_chunk_table()[n - o]) {
+    push(o, k);
+    o += k;
+  }
+}
+
+// Near-field items, most expensive first (passes over the near sources times slice length),
+// so that the longest workgroups start early.
 void sort_near_items(gq_plan* P) {
   const size_t n = P->k3_box.size();
   std::vector<size_t> ord(n);
@@ -219,7 +266,8 @@ void sort_near_items(gq_plan* P) {
   for (size_t i = 0; i < n; ++i) {
     ord[i] = i;
     const int b = P->k3_box[i];
-    cost[i] = (P->near_ptr[b + 1] - P->near_ptr[b]) * (int64_t)P->k3_nc[i];
+    const int64_t slices = 64 / P->k3_nc[i];
+    cost[i] = (P->near_ptr[b + 1] - P->near_ptr[b] + slices - 1) / slices;
   }
   std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
   std::vector<int> bx(n), c0(n), nc(n);
@@ -342,7 +390,7 @@ gq_status build_work(gq_plan* P) {
       merge_ranges(r);
       for (auto& x : r)
         for (int64_t k = 0; k < x.second; ++k) P->near_idx.push_back((int)(x.first + k));
-      if (!r.empty()) center_items(T, b, 64, P->k3_box, P->k3_c0, P->k3_nc);
+      if (!r.empty()) near_center_items(T, b, P->k3_box, P->k3_c0, P->k3_nc);
       const int64_t npt_b = P->pt_count_box.empty() ? 0 : P->pt_count_box[b];
       if (npt_b > 0 && !r.empty())
         for (int64_t o = 0; o < npt_b; o += 64) {
