@@ -29,14 +29,14 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # HBM bytes per launch (read + write) of the main kernels on the default workload, from two
 # rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy measured in the
 # same process (profiles/hbm_traffic_urchin20480_D_q5p15.md).  Valid only for the kernel
-# sources they were measured on (sha256 over csrc/kernels*.hip in name order): reported
-# while it matches, else null.
+# sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
+# on: reported while they match, else null.
 COUNTER_TRAFFIC = {
     "kernels_sha256": "d5c26154cfa095d05a03979dbe640350b80fad0ca8b510676ee2371afd08fc28",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 5.26972e+09, "m2l": 1.404085e+10, "m2qbxl": 8.948e+07,
-                         "l2qbxl": 9.4045e+08},
+    "bytes_per_launch": {"p2qbxl": 8.10145e+09, "m2l": 1.40497e+10, "m2qbxl": 8.94795e+07,
+                         "l2qbxl": 9.40441e+08},
 }
 
 
