@@ -114,6 +114,9 @@ def main():
                     help="1 (default): level-restricted tree, adjacent leaves differ by at most "
                          "one level (the remark on List 3 complexity); 0: the adaptive tree as "
                          "built")
+    ap.add_argument("--m2l-rotation", type=int, choices=[0, 1], default=0,
+                    help="1: FP64 M2L as rotate, translate along z, rotate back (three sparse "
+                         "tile products) instead of one dense matrix per offset class")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 200 if args.workload == "c5" else 10
@@ -161,6 +164,7 @@ def main():
     def run(precision):
         t0 = time.time()
         plan = Plan.from_workload(w, timing=True, precision=precision,
+                                  m2l_rotation=bool(args.m2l_rotation) and precision == "fp64",
                                   **tree_opts(args))
         plan_wall = time.time() - t0
         st = plan.stats()
@@ -205,7 +209,9 @@ def main():
     for s, f in flops.items():
         ms = stage_ms[kern_stage.get(s, s)]
         per_stage[s] = {"ms": round(ms, 4), "tflops": round(f / (ms * 1e-3) / 1e12, 3) if ms > 0 else None}
-    m2l = {"engine": "fp64 mfma (v_mfma_f64_16x16x4f64)", "ms": round(stage_ms["m2l"], 4),
+    m2l = {"engine": "fp64 mfma (v_mfma_f64_16x16x4f64)"
+                     + (", rotation-factored" if args.m2l_rotation else ", dense"),
+           "ms": round(stage_ms["m2l"], 4),
            "tflops": per_stage["m2l"]["tflops"],
            "frac_of_fp64_mfma_peak": round(per_stage["m2l"]["tflops"] / PEAK_FP64_VALU_TFLOPS, 4)
            if per_stage["m2l"]["tflops"] else None}
@@ -268,7 +274,8 @@ def main():
                    "n_sources": w.n_src, "n_centers": w.n_ctr, "n_targets": w.n_tgt,
                    "nmax": w.nmax, "tcf": w.tcf, "n_densities": 1, "precision": "fp64",
                    "wfar_direct_max": args.wfar_direct_max,
-                   "level_restrict": bool(args.level_restrict)},
+                   "level_restrict": bool(args.level_restrict),
+                   "m2l_rotation": bool(args.m2l_rotation)},
         "rel_err_vs_direct_qbx": err_direct,
         "roofline": roofline,
         "cpu_baseline": cpu,

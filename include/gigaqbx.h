@@ -101,6 +101,11 @@ typedef struct {
      coarser leaf of each offending pair by the usual rule (a leaf where nothing can move
      stays); 0 (default) keeps the adaptive tree as built. */
   int level_restrict;
+  /* Stage 4 (M2L) arithmetic: 0 (default) one dense matrix per offset class; 1 the same
+     operator factored as rotate, translate along z, rotate back (T = B Z A; the rotation-
+     based translations of Appendix C's cost model), run as three sparse tile products on
+     the FP64 matrix cores.  1 needs GQ_FP64 and p_fmm <= 15 (else GQ_EUNSUPPORTED). */
+  int m2l_rotation;
 } gq_params;
 
 typedef struct gq_plan gq_plan; /* opaque */
@@ -282,7 +287,9 @@ gq_status gq_qbx_locals(gq_plan* plan, double* host_out);
 /*
  * Host computation of one dense translation matrix (column-major, (p+1)^2 square):
  *   kind 0: M2M child octant a -> parent;  kind 1: L2L parent -> child octant a;
- *   kind 2: M2L for integer offset (a, b, c) = (x_target - x_source) / (box width).
+ *   kind 2: M2L for integer offset (a, b, c) = (x_target - x_source) / (box width);
+ *   kinds 3, 4, 5: the factors A, Z, B of that M2L (kind 2 = B Z A): A rotates multipoles
+ *   so that the offset points along +z, Z translates along z, B rotates locals back.
  * Scaled real-packed form; for testing.
  */
 gq_status gq_translation_matrix(int kind, int p, int a, int b, int c, double* out);

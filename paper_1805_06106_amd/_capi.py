@@ -51,7 +51,7 @@ class gq_params(ctypes.Structure):
                 ("tcf", ctypes.c_double), ("kernel", ctypes.c_int), ("precision", ctypes.c_int),
                 ("n_densities", ctypes.c_int), ("flags", ctypes.c_uint),
                 ("wfar_direct_max", ctypes.c_int), ("tcr_norm", ctypes.c_int),
-                ("level_restrict", ctypes.c_int)]
+                ("level_restrict", ctypes.c_int), ("m2l_rotation", ctypes.c_int)]
 
 
 class gq_stats_t(ctypes.Structure):
@@ -156,7 +156,7 @@ def gq_last_error():
 
 def make_params(p_qbx, p_fmm, nmax=512, tcf=0.9, kernel="S", n_densities=1, flags=0,
                 lists=None, wfar_direct_max=0, precision="fp64", tcr_norm="l2",
-                level_restrict=False):
+                level_restrict=False, m2l_rotation=False):
     k = {"S": GQ_KERNEL_S, "D": GQ_KERNEL_D, "SP": GQ_KERNEL_SP}.get(kernel, kernel)
     prec = PRECISIONS.get(precision, precision)
     if lists is not None:
@@ -164,7 +164,8 @@ def make_params(p_qbx, p_fmm, nmax=512, tcf=0.9, kernel="S", n_densities=1, flag
             flags |= LIST_BITS[nm]
     return gq_params(int(p_qbx), int(p_fmm), int(nmax), float(tcf), int(k), int(prec),
                      int(n_densities), int(flags), int(wfar_direct_max),
-                     {"l2": 0, "linf": 1}.get(tcr_norm, tcr_norm), int(level_restrict))
+                     {"l2": 0, "linf": 1}.get(tcr_norm, tcr_norm), int(level_restrict),
+                     int(m2l_rotation))
 
 
 def gq_plan_create(params, src_xyz, src_w, src_normal, ctr_xyz, ctr_radius, tgt_xyz,

@@ -33,8 +33,8 @@ def build(verbose: bool = False) -> str:
     for f in ("planner.cpp", "translations.cpp"):
         jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, f),
                      "-o", os.path.join(BUILD, f + ".o")])
-    hip_sources = ("kernels.hip", "kernels_p2x.hip", "kernels_pt.hip", "oversample.hip",
-                   "associate.hip", "executor.hip")
+    hip_sources = ("kernels.hip", "kernels_p2x.hip", "kernels_pt.hip", "kernels_rot.hip",
+                   "oversample.hip", "associate.hip", "executor.hip")
     for f in hip_sources:
         jobs.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, f),
                      "-o", os.path.join(BUILD, f + ".o")])

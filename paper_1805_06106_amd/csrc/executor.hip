@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/gigaqbx.h"
@@ -131,6 +132,11 @@ struct gq_plan {
   int *d_pp_box = nullptr, *d_pp_t0 = nullptr, *d_pp_nt = nullptr;
   int *d_pm_t0 = nullptr, *d_pm_nt = nullptr, *d_pm_w0 = nullptr, *d_pm_w1 = nullptr;
   double *T_m2m = nullptr, *T_l2l = nullptr, *T_m2l = nullptr;
+  // M2L by rotation: per-class tiles of A, B and order blocks of Z, and their shared index
+  double *R_A = nullptr, *R_Z = nullptr, *R_B = nullptr;
+  int *d_rot_row_beg = nullptr, *d_rot_tile_c = nullptr, *d_rot_rowmap = nullptr,
+      *d_rot_row_order = nullptr;
+  gq::RotMats rot{};
   float *T32_m2m[2] = {nullptr, nullptr}, *T32_l2l[2] = {nullptr, nullptr},
         *T32_m2l[2] = {nullptr, nullptr};  // (hi, lo)
   gq::TransMats tm_m2m{}, tm_l2l{}, tm_m2l{};
@@ -338,7 +344,8 @@ gq_status build_work(gq_plan* P) {
         pairs.push_back({ci, d, b});
       }
     }
-    make_tiles(pairs, P->m2l);
+    make_tiles(pairs, P->m2l, P->prm.m2l_rotation ? gq::kRotCols : gq::kTileCols);
+    if (P->prm.m2l_rotation) P->m2l_cols = gq::kRotCols;
   }
   // Stage 6b
   if (on(GQ_LIST_XFAR)) {
@@ -452,6 +459,89 @@ gq_status build_work(gq_plan* P) {
   return GQ_OK;
 }
 
+// M2L by rotation: the factors A, Z, B of every class (host threads over classes), cut
+// into the device tiles: the nonzero 16 x 16 tiles of the block-diagonal A and B (the same
+// positions for every class) and the order blocks of Z.
+gq_status upload_rotation(gq_plan* P, hipStream_t s) {
+  const int p = P->prm.p_fmm, np = P->np;
+  const int ntr = (np + 15) / 16;
+  // tile positions of a matrix that is block diagonal by degree
+  std::vector<int> row_beg(ntr + 1, 0), tile_c;
+  for (int r = 0; r < ntr; ++r) {
+    row_beg[r] = (int)tile_c.size();
+    for (int c = 0; c < ntr; ++c) {
+      bool nz = false;
+      for (int n = 0; n <= p && !nz; ++n) {
+        const int lo = n * n, hi = (n + 1) * (n + 1) - 1;
+        nz = lo <= 16 * r + 15 && hi >= 16 * r && lo <= 16 * c + 15 && hi >= 16 * c;
+      }
+      if (nz) tile_c.push_back(c);
+    }
+  }
+  row_beg[ntr] = (int)tile_c.size();
+  const int ntile = (int)tile_c.size();
+  // order blocks: m = 0 (real parts), then (m, real), (m, imaginary) for m = 1..p
+  const int nblk = 2 * p + 1;
+  std::vector<int> rowmap((size_t)nblk * 16, -1);
+  for (int b = 0; b < nblk; ++b) {
+    const int m = (b + 1) / 2, im = b > 0 && (b % 2 == 0);
+    for (int n = m; n <= p; ++n) rowmap[b * 16 + n - m] = n * n + (m ? 2 * m - 1 + im : 0);
+  }
+  // wave assignment of the row tiles: heaviest first, dealt to the waves in snake order
+  std::vector<int> byc(ntr), row_order(16, -1);  // 4 waves x 4 slots; ntr <= 16
+  for (int r = 0; r < ntr; ++r) byc[r] = r;
+  std::stable_sort(byc.begin(), byc.end(), [&](int a, int b) {
+    return row_beg[a + 1] - row_beg[a] > row_beg[b + 1] - row_beg[b];
+  });
+  for (int i = 0; i < ntr; ++i) {
+    const int round = i / 4, pos = i % 4, wave = round % 2 ? 3 - pos : pos;
+    row_order[wave + 4 * round] = byc[i];
+  }
+  const size_t ncls = P->cls_keys.size();
+  std::vector<double> hA(ncls * ntile * 256, 0.0), hB(ncls * ntile * 256, 0.0),
+      hZ(ncls * nblk * 256, 0.0);
+  auto work = [&](size_t c0, size_t c1) {
+    std::vector<double> A((size_t)np * np), Z((size_t)np * np), B((size_t)np * np);
+    for (size_t c = c0; c < c1; ++c) {
+      const int key = P->cls_keys[c];
+      gq::m2l_rotation_factors(p, key / 121 - 5, (key / 11) % 11 - 5, key % 11 - 5, A.data(),
+                               Z.data(), B.data());
+      for (int r = 0; r < ntr; ++r)
+        for (int t = row_beg[r]; t < row_beg[r + 1]; ++t)
+          for (int k = 0; k < 16; ++k)
+            for (int i = 0; i < 16; ++i) {
+              const int row = 16 * r + i, col = 16 * tile_c[t] + k;
+              if (row >= np || col >= np) continue;
+              const size_t at = (c * ntile + t) * 256 + k * 16 + i;
+              hA[at] = A[(size_t)col * np + row];
+              hB[at] = B[(size_t)col * np + row];
+            }
+      for (int b = 0; b < nblk; ++b)
+        for (int k = 0; k < 16; ++k)
+          for (int i = 0; i < 16; ++i) {
+            const int row = rowmap[b * 16 + i], col = rowmap[b * 16 + k];
+            if (row >= 0 && col >= 0) hZ[(c * nblk + b) * 256 + k * 16 + i] = Z[(size_t)col * np + row];
+          }
+    }
+  };
+  const size_t nth = std::max<size_t>(1, std::min<size_t>(8, ncls / 16));
+  std::vector<std::thread> th;
+  for (size_t k = 0; k < nth; ++k)
+    th.emplace_back(work, ncls * k / nth, ncls * (k + 1) / nth);
+  for (auto& x : th) x.join();
+  GQ_TRY(upload(P, hA, &P->R_A, s));
+  GQ_TRY(upload(P, hZ, &P->R_Z, s));
+  GQ_TRY(upload(P, hB, &P->R_B, s));
+  GQ_TRY(upload(P, row_beg, &P->d_rot_row_beg, s));
+  GQ_TRY(upload(P, tile_c, &P->d_rot_tile_c, s));
+  GQ_TRY(upload(P, rowmap, &P->d_rot_rowmap, s));
+  GQ_TRY(upload(P, row_order, &P->d_rot_row_order, s));
+  GQ_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  P->rot = gq::RotMats{P->R_A, P->R_Z, P->R_B, P->d_rot_row_beg, P->d_rot_tile_c,
+                       P->d_rot_rowmap, P->d_rot_row_order, ntile, nblk, ntr};
+  return GQ_OK;
+}
+
 // Translation matrices for the plan's classes and the upload of every work list.
 gq_status upload_work(gq_plan* P) {
   if (P->prm.flags & GQ_FLAG_HOST_ONLY) return GQ_OK;
@@ -464,11 +554,13 @@ gq_status upload_work(gq_plan* P) {
     gq::m2m_matrix(p, o, Tm.data() + (size_t)o * np * np);
     gq::l2l_matrix(p, o, Tl.data() + (size_t)o * np * np);
   }
-  std::vector<double> Tv((size_t)cls_keys.size() * np * np);
-  for (size_t c = 0; c < cls_keys.size(); ++c) {
-    int key = cls_keys[c];
-    gq::m2l_matrix(p, key / 121 - 5, (key / 11) % 11 - 5, key % 11 - 5, Tv.data() + c * np * np);
-  }
+  const bool rot = P->prm.m2l_rotation != 0;
+  std::vector<double> Tv(rot ? 0 : (size_t)cls_keys.size() * np * np);
+  if (!rot)
+    for (size_t c = 0; c < cls_keys.size(); ++c) {
+      int key = cls_keys[c];
+      gq::m2l_matrix(p, key / 121 - 5, (key / 11) % 11 - 5, key % 11 - 5, Tv.data() + c * np * np);
+    }
 
   hipStream_t s = P->last_stream;
   // device layout: padded column-major (trans_ld rows, trans_kd columns, zero padding)
@@ -509,6 +601,7 @@ gq_status upload_work(gq_plan* P) {
   P->tm_m2m = {P->T_m2m, P->T32_m2m[0], P->T32_m2m[1]};
   P->tm_l2l = {P->T_l2l, P->T32_l2l[0], P->T32_l2l[1]};
   P->tm_m2l = {P->T_m2l, P->T32_m2l[0], P->T32_m2l[1]};
+  if (rot) GQ_TRY(upload_rotation(P, s));
   GQ_TRY(upload(P, P->p2m_boxes, &P->d_p2m_boxes, s));
   GQ_TRY(upload(P, P->p2m_ptr, &P->d_p2m_ptr, s));
   GQ_TRY(upload(P, P->p2m_idx, &P->d_p2m_idx, s));
@@ -681,7 +774,8 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
     make_tiles(m2m[l], B->m2m_levels[l]);
     make_tiles(l2l[l], B->l2l_levels[l]);
   }
-  make_tiles(m2l, B->m2l);
+  make_tiles(m2l, B->m2l, B->prm.m2l_rotation ? gq::kRotCols : gq::kTileCols);
+  if (B->prm.m2l_rotation) B->m2l_cols = gq::kRotCols;
   sort_near_items(B);
   return GQ_OK;
 }
@@ -760,7 +854,7 @@ gq_status merge_geometry(gq_plan* B, gq_plan* const* plans, int n, hipStream_t s
 // 64 and 32 and for XCD-aware or plain tile order, and keep the fastest.  The timed
 // launches read zeroed multipoles; the box locals are cleared by every apply.
 gq_status autotune_m2l(gq_plan* P, hipStream_t s) {
-  if (P->m2l.ntile() == 0) return GQ_OK;
+  if (P->m2l.ntile() == 0 || P->prm.m2l_rotation) return GQ_OK;  // one rotation kernel shape
   std::vector<std::array<int, 3>> pairs;
   tiles_to_pairs(P->m2l, 0, nullptr, pairs);
   struct Cand {
@@ -856,6 +950,10 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
   if (prm->tcr_norm != 0 && prm->tcr_norm != 1) return fail(GQ_EINVAL, "tcr_norm must be 0 or 1");
   if (prm->level_restrict != 0 && prm->level_restrict != 1)
     return fail(GQ_EINVAL, "level_restrict must be 0 or 1");
+  if (prm->m2l_rotation != 0 && prm->m2l_rotation != 1)
+    return fail(GQ_EINVAL, "m2l_rotation must be 0 or 1");
+  if (prm->m2l_rotation && (prm->precision != GQ_FP64 || prm->p_fmm > 15))
+    return fail(GQ_EUNSUPPORTED, "M2L by rotation needs GQ_FP64 and p_fmm <= 15");
   if ((prm->flags & GQ_FLAG_TIMING) && (prm->flags & GQ_FLAG_GRAPH))
     return fail(GQ_EINVAL, "GQ_FLAG_TIMING and GQ_FLAG_GRAPH are exclusive");
   if (prm->kernel == GQ_KERNEL_D && !src_normal) return fail(GQ_EINVAL, "double layer needs normals");
@@ -1089,9 +1187,13 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
                            P->M, P->M);
     }
     GQ_TRY(mark(4));
-    gq::launch_translate(s, 2, prec, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
-                         P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L, P->m2l_cols,
-                         P->m2l_xcd);
+    if (P->prm.m2l_rotation)
+      gq::launch_m2l_rot(s, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
+                         P->d_m2l[3], P->d_m2l[4], P->rot, P->M, P->L, P->m2l_xcd);
+    else
+      gq::launch_translate(s, 2, prec, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1],
+                           P->d_m2l[2], P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L,
+                           P->m2l_cols, P->m2l_xcd);
     GQ_TRY(mark(5));
     gq::launch_p2l(s, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_ptr,
                    P->d_p2l_idx, P->bctr, P->bh, src, P->q, P->L);
@@ -1452,6 +1554,7 @@ gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, vo
     if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "host-only plan in batch");
     if (P->prm.p_qbx != P0->prm.p_qbx || P->prm.p_fmm != P0->prm.p_fmm ||
         P->prm.kernel != P0->prm.kernel || P->prm.precision != P0->prm.precision ||
+        P->prm.m2l_rotation != P0->prm.m2l_rotation ||
         P->prm.n_densities != P0->prm.n_densities)
       return fail(GQ_EINVAL, "batch members must share p_qbx, p_fmm, kernel, precision and "
                              "n_densities");
@@ -1544,10 +1647,17 @@ gq_status gq_translation_matrix(int kind, int p, int a, int b, int c, double* ou
     (kind == 0 ? gq::m2m_matrix : gq::l2l_matrix)(p, a, out);
     return GQ_OK;
   }
-  if (kind == 2) {
+  if (kind >= 2 && kind <= 5) {
     if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 1)
       return fail(GQ_EINVAL, "offset must be nonzero");
-    gq::m2l_matrix(p, a, b, c, out);
+    if (kind == 2) {
+      gq::m2l_matrix(p, a, b, c, out);
+    } else {
+      const size_t np = (size_t)gq::ncoef(p);
+      std::vector<double> f(3 * np * np);
+      gq::m2l_rotation_factors(p, a, b, c, f.data(), f.data() + np * np, f.data() + 2 * np * np);
+      std::copy(f.begin() + (kind - 3) * np * np, f.begin() + (kind - 2) * np * np, out);
+    }
     return GQ_OK;
   }
   return fail(GQ_EINVAL, "unknown kind");

@@ -31,6 +31,23 @@ void launch_strength_interp(hipStream_t s, int64_t n, const int64_t* order, cons
                             double* q);
 void launch_fill(hipStream_t s, double* p, int64_t n, double v);
 
+// M2L by rotation (kernels_rot.hip), FP64, p_fmm <= 15: per class, the ntile nonzero 16 x 16
+// tiles of A and B (tile t: row tile r with row_beg[r] <= t < row_beg[r + 1], column tile
+// tile_c[t]; element (row i, column k) at [k * 16 + i]), and nblk order blocks of Z (block b
+// maps the packed rows rowmap[16 b + i], -1 = padding; element at [k * 16 + i]).
+constexpr int kRotCols = 32;   // pairs per tile
+constexpr int kRotRows = 256;  // rows of the LDS working matrix ((p+1)^2 <= 256)
+// row_order[16]: the row tiles in the order the 4 waves take them (wave w: entries w, w+4,
+// w+8, w+12; -1 = none), balancing their nonzero tile counts; at most 16 row tiles.
+struct RotMats {
+  const double *A, *Z, *B;
+  const int *row_beg, *tile_c, *rowmap, *row_order;
+  int ntile, nblk, ntr;
+};
+void launch_m2l_rot(hipStream_t s, int np, int ntile, const int* tile_cls, const int* tile_beg,
+                    const int* tile_cnt, const int* pair_src, const int* pair_dst,
+                    const RotMats& R, const double* X, double* Y, bool xcd_order);
+
 // Target association (associate.hip).  A uniform grid of n[0] x n[1] x n[2] cells of width
 // h from lo; cell (i, j, k) has linear index (k * n[1] + j) * n[0] + i.
 struct AssocGrid {

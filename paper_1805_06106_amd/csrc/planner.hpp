@@ -82,5 +82,9 @@ int ncoef(int p);
 void m2m_matrix(int p, int octant, double* T);                  // child multipole -> parent
 void l2l_matrix(int p, int octant, double* T);                  // parent local -> child
 void m2l_matrix(int p, int ox, int oy, int oz, double* T);      // same-level, offset 2*o
+// The same M2L factored as T = B Z A: A rotates multipoles so that the offset points along
+// +z, Z translates along z (it couples only equal orders), B rotates locals back.  A and B
+// are block diagonal by degree; all three np x np, column-major.
+void m2l_rotation_factors(int p, int ox, int oy, int oz, double* A, double* Z, double* B);
 
 }  // namespace gq

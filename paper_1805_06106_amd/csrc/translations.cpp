@@ -20,6 +20,7 @@
 // Matrices are stored column-major: T[col * np + row], y = T x.
 #include <cmath>
 #include <complex>
+#include <algorithm>
 #include <vector>
 
 #include "planner.hpp"
@@ -134,12 +135,151 @@ void l2l_matrix(int p, int octant, double* T) {
   }, T);
 }
 
-void m2l_matrix(int p, int ox, int oy, int oz, double* T) {
-  auto Ir = irregular_all(2 * p, 2.0 * ox, 2.0 * oy, 2.0 * oz);
+namespace {
+
+// M2L for a scaled offset t = x_target - x_source in units of the box half-width.
+void m2l_matrix_vec(int p, double tx, double ty, double tz, double* T) {
+  auto Ir = irregular_all(2 * p, tx, ty, tz);
   real_pack(p, [&](int j, int k, int n, int m) -> cd {
     cd v = std::conj(getc(Ir, 2 * p, n + j, m + k));
     return (j & 1) ? -v : v;
   }, T);
+}
+
+// Packed values of degree n, [Re c^0, Re c^1, Im c^1, ..., Re c^n, Im c^n], of a full
+// signed-order table, each multiplied by w(m).
+template <class W>
+void pack_degree(const std::vector<cd>& a, int pmax, int n, W w, double* out) {
+  out[0] = a[cid(n, 0)].real() * w(0);
+  for (int m = 1; m <= n; ++m) {
+    out[2 * m - 1] = a[cid(n, m)].real() * w(m);
+    out[2 * m] = a[cid(n, m)].imag() * w(m);
+  }
+  (void)pmax;
+}
+
+// Solve G X = H for X (d x d), G symmetric positive definite (Gauss-Jordan with pivoting).
+void solve_spd(int d, std::vector<double> G, std::vector<double>& H) {
+  for (int c = 0; c < d; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < d; ++r)
+      if (std::fabs(G[r * d + c]) > std::fabs(G[piv * d + c])) piv = r;
+    for (int k = 0; k < d; ++k) {
+      std::swap(G[c * d + k], G[piv * d + k]);
+      std::swap(H[c * d + k], H[piv * d + k]);
+    }
+    const double inv = 1.0 / G[c * d + c];
+    for (int k = 0; k < d; ++k) {
+      G[c * d + k] *= inv;
+      H[c * d + k] *= inv;
+    }
+    for (int r = 0; r < d; ++r) {
+      if (r == c) continue;
+      const double f = G[r * d + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < d; ++k) {
+        G[r * d + k] -= f * G[c * d + k];
+        H[r * d + k] -= f * H[c * d + k];
+      }
+    }
+  }
+}
+
+// The real (2n+1) x (2n+1) blocks D_n with pack(f_n(Q v)) = D_n pack(f_n(v)) for every v,
+// where f = R (regular, irregular = false) or conj(I) (irregular = true); written into the
+// column-major np x np matrix D (block diagonal by degree).  Each block is fitted by least
+// squares on sample directions, in a basis where the orders have comparable size.
+void rotation_blocks(int p, const double Q[9], bool irregular, double* D) {
+  const int np = ncoef(p);
+  for (int i = 0; i < np * np; ++i) D[i] = 0.0;
+  std::vector<double> lf(2 * p + 2, 0.0);  // log factorials
+  for (int i = 1; i < (int)lf.size(); ++i) lf[i] = lf[i - 1] + std::log((double)i);
+  const int K = 8 * (2 * p + 1);
+  std::vector<std::vector<cd>> F(K), FQ(K);
+  for (int s = 0; s < K; ++s) {
+    // a spread of unit directions (golden-angle spiral, slightly off the poles)
+    const double z = 1.0 - (2.0 * s + 1.0) / K;
+    const double rr = std::sqrt(1.0 - z * z), ph = 2.399963229728653 * s + 0.3;
+    const double v[3] = {rr * std::cos(ph), rr * std::sin(ph), z};
+    const double w[3] = {Q[0] * v[0] + Q[1] * v[1] + Q[2] * v[2],
+                         Q[3] * v[0] + Q[4] * v[1] + Q[5] * v[2],
+                         Q[6] * v[0] + Q[7] * v[1] + Q[8] * v[2]};
+    if (irregular) {
+      F[s] = irregular_all(p, v[0], v[1], v[2]);
+      FQ[s] = irregular_all(p, w[0], w[1], w[2]);
+      for (auto& x : F[s]) x = std::conj(x);
+      for (auto& x : FQ[s]) x = std::conj(x);
+    } else {
+      F[s] = regular_all(p, v[0], v[1], v[2]);
+      FQ[s] = regular_all(p, w[0], w[1], w[2]);
+    }
+  }
+  for (int n = 0; n <= p; ++n) {
+    const int d = 2 * n + 1;
+    // |R_n^m| ~ 1 / sqrt((n+m)! (n-m)!), |I_n^m| ~ sqrt((n+m)! (n-m)!) on the unit sphere
+    auto w = [&](int m) {
+      const double e = 0.5 * (lf[n + m] + lf[n - m]);
+      return std::exp(irregular ? -e : e);
+    };
+    std::vector<double> G(d * d, 0.0), H(d * d, 0.0), a(d), b(d);
+    for (int s = 0; s < K; ++s) {
+      pack_degree(F[s], p, n, w, a.data());
+      pack_degree(FQ[s], p, n, w, b.data());
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+          G[i * d + j] += a[i] * a[j];  // sum a a^T
+          H[i * d + j] += a[i] * b[j];  // sum a b^T
+        }
+    }
+    // H = (sum a a^T)^-1 sum a b^T = Dhat^T, with one step of iterative refinement
+    std::vector<double> H0 = H;
+    solve_spd(d, G, H);
+    std::vector<double> Rr(d * d);
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        double acc = H0[i * d + j];
+        for (int k = 0; k < d; ++k) acc -= G[i * d + k] * H[k * d + j];
+        Rr[i * d + j] = acc;
+      }
+    solve_spd(d, G, Rr);
+    for (int i = 0; i < d * d; ++i) H[i] += Rr[i];
+    // back to the unscaled packing: D = W^-1 Dhat W, Dhat[r][c] = H[c][r]
+    auto wm = [&](int i) { return w((i + 1) / 2); };
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c)
+        D[(size_t)(n * n + c) * np + n * n + r] = H[c * d + r] * wm(c) / wm(r);
+  }
+}
+
+}  // namespace
+
+void m2l_matrix(int p, int ox, int oy, int oz, double* T) {
+  m2l_matrix_vec(p, 2.0 * ox, 2.0 * oy, 2.0 * oz, T);
+}
+
+void m2l_rotation_factors(int p, int ox, int oy, int oz, double* A, double* Z, double* B) {
+  // a rotation Q taking the offset direction u to +z (Rodrigues about u x z)
+  const double len = std::sqrt((double)(ox * ox + oy * oy + oz * oz));
+  const double u[3] = {ox / len, oy / len, oz / len};
+  double Q[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  const double c = u[2];
+  const double kx = u[1], ky = -u[0];  // u x z
+  const double sn = std::sqrt(kx * kx + ky * ky);
+  if (sn < 1e-14) {
+    if (c < 0) {  // u = -z: half turn about x
+      Q[4] = -1.0;
+      Q[8] = -1.0;
+    }
+  } else {
+    const double ax = kx / sn, ay = ky / sn;  // unit axis (z component 0)
+    const double K[9] = {0, 0, ay, 0, 0, -ax, -ay, ax, 0};
+    const double kk[9] = {ax * ax, ax * ay, 0, ay * ax, ay * ay, 0, 0, 0, 0};
+    for (int i = 0; i < 9; ++i) Q[i] = (i % 4 == 0 ? c : 0.0) + sn * K[i] + (1.0 - c) * kk[i];
+  }
+  const double Qt[9] = {Q[0], Q[3], Q[6], Q[1], Q[4], Q[7], Q[2], Q[5], Q[8]};
+  rotation_blocks(p, Q, false, A);   // multipoles into the rotated frame
+  m2l_matrix_vec(p, 0.0, 0.0, 2.0 * len, Z);
+  rotation_blocks(p, Qt, true, B);   // locals back to the original frame
 }
 
 }  // namespace gq

@@ -210,6 +210,22 @@ def test_gpu_level_restricted_vs_tier_b(dev, case):
     assert rel(pot[0][tids], ref) < TOL
 
 
+@pytest.mark.parametrize("case", ["S-l1-n32", "D-l2-flat"])
+@pytest.mark.parametrize("p_fmm", [5, 15])
+def test_gpu_m2l_rotation_vs_tier_b(dev, case, p_fmm):
+    """M2L by rotation (T = B Z A on the matrix cores) against the oracle, whose M2L is the
+    plain translation formula, and against the dense-matrix M2L of the library."""
+    kw = dict(CASES[case])
+    kw["p_fmm"] = p_fmm
+    w = workload_tiny(**kw)
+    print(f"[gpu] case={case} p_fmm={p_fmm} m2l rotation", flush=True)
+    _, pot = run_gpu(w, dev, m2l_rotation=True)
+    _, dense = run_gpu(w, dev)
+    tids, ref, _ = OracleFMM(w).evaluate()
+    assert rel(pot[0][tids], ref) < TOL
+    assert rel(pot[0], dense[0]) < 1e-11
+
+
 @pytest.mark.parametrize("kernel", ["S", "D"])
 def test_gpu_point_targets_vs_tier_b(dev, kernel):
     """Conventional targets (tgt_center = -1) beside the QBX targets: both against the

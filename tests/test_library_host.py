@@ -307,3 +307,35 @@ def test_associate_targets_validation(gq):
     assert G.associate_targets(s3, [1.0, 1.0], c3, [1.0], np.zeros((0, 3))).shape == (0,)
     got = G.associate_targets(np.zeros((0, 3)), [], c3, [1.0], t3)  # no sources: no danger
     assert got.tolist() == [G.GQ_TARGET_FAR] * 3
+
+
+@pytest.mark.parametrize("p", [4, 10, 15])
+def test_m2l_rotation_factors(gq, p):
+    """The rotated form of M2L: T = B Z A to rounding, A and B block diagonal by degree
+    (rotations keep the degree), and Z couples only equal orders, real with real and
+    imaginary with imaginary parts (a translation along z)."""
+    np_ = (p + 1) ** 2
+    deg = np.repeat(np.arange(p + 1), 2 * np.arange(p + 1) + 1)
+    off = np.arange(np_) - deg ** 2
+    order = (off + 1) // 2
+    part = np.where(off == 0, 0, 2 - off % 2)  # 0: m = 0, 1: real, 2: imaginary
+    for o in [(2, 0, 0), (0, 0, -2), (1, 2, 3), (-3, 3, -2), (0, 2, -2)]:
+        T = gq.gq_translation_matrix(2, p, *o)
+        A, Z, B = (gq.gq_translation_matrix(k, p, *o) for k in (3, 4, 5))
+        BZA = B @ Z @ A
+        rowmax = np.max(np.abs(T), axis=1)
+        assert np.max(np.max(np.abs(BZA - T), axis=1) / rowmax) < 1e-11, o
+        for M in (A, B):
+            assert np.all(M[deg[:, None] != deg[None, :]] == 0.0)
+        same = (order[:, None] == order[None, :]) & (part[:, None] == part[None, :])
+        assert np.max(np.abs(Z[~same])) == 0.0
+
+
+def test_m2l_rotation_validation(gq):
+    w = workload_tiny(level=0, order=2, kernel="D", p_qbx=2, p_fmm=4, nmax=16)
+    G = gq
+    G.Plan(**_args(w, m2l_rotation=True))  # host-only FP64 plan: accepted
+    for over in (dict(precision="fp32_split"), dict(p_fmm=16)):
+        with pytest.raises(G.GQError) as e:
+            G.Plan(**_args(w, m2l_rotation=True, **over))
+        assert e.value.status == 4
