@@ -32,11 +32,11 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "d5c26154cfa095d05a03979dbe640350b80fad0ca8b510676ee2371afd08fc28",
+    "kernels_sha256": "6821418b79c45737906c5a70f3387c2e76d2ef1c487d907c2c8e1f31634c9650",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 8.10145e+09, "m2l": 1.40497e+10, "m2qbxl": 8.94795e+07,
-                         "l2qbxl": 9.40441e+08},
+    "bytes_per_launch": {"p2qbxl": 8.10117e+09, "m2l": 1.40455e+10, "m2qbxl": 8.94792e+07,
+                         "l2qbxl": 9.40442e+08},
 }
 
 
