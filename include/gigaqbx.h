@@ -203,6 +203,20 @@ gq_status gq_set_source_interp(gq_plan* plan, int64_t n_elem, int n_node, int n_
 #define GQ_TARGET_UNMATCHED (-2)  /* endangered, but no admissible center is close enough */
 
 /*
+ * Proximity query for geometry processing (the area queries of Algorithms 1 and 2, Section
+ * 3): hit[i] = 1 if some point p_j lies within radius[i] of query q_i, else 0; with
+ * strict != 0 the test is |q_i - p_j| < radius[i], else <=.  Squared distances are compared
+ * in FP64 without fused multiply-adds, ((dx*dx + dy*dy) + dz*dz) against (r*r).
+ *   q_xyz[3*n_q], radius[n_q] (finite, >= 0), p_xyz[3*n_p]: host; hit[n_q]: host output.
+ * The queries run on the device over a uniform cell grid built on the host; the call
+ * allocates and frees its own device memory and returns when the result is on the host.
+ * Errors: GQ_EINVAL for NULL arrays with nonzero counts, non-finite coordinates, negative
+ * or non-finite radii.
+ */
+gq_status gq_points_near(int64_t n_q, const double* q_xyz, const double* radius, int strict,
+                         int64_t n_p, const double* p_xyz, uint8_t* hit, void* hip_stream);
+
+/*
  * Associate targets with QBX centers (Algorithm 3, with the side preference of Section 3).
  * A target t is endangered if some source s has |t - s| <= danger[s] (the danger zone of
  * a source is half its element's size).  An endangered target is associated with the

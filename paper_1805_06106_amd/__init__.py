@@ -12,6 +12,7 @@ from ._capi import (  # noqa: F401
     GQ_TARGET_UNMATCHED,
     GQError,
     gq_associate_targets as associate_targets,
+    gq_points_near as points_near,
     gq_apply,
     gq_last_error,
     gq_list_export,

@@ -41,7 +41,7 @@ STAGES = ("strength", "p2m", "m2m", "m2l", "p2l", "l2l", "p2qbxl", "m2qbxl", "l2
 EXPORTED = ("gq_plan_create", "gq_apply", "gq_stats", "gq_plan_destroy", "gq_last_error",
             "gq_tree_export", "gq_list_export", "gq_qbx_locals", "gq_translation_matrix",
             "gq_batch_create", "gq_set_target_normals", "gq_set_source_interp",
-            "gq_associate_targets")
+            "gq_associate_targets", "gq_points_near")
 GQ_TARGET_FAR = -1
 GQ_TARGET_UNMATCHED = -2
 
@@ -109,6 +109,8 @@ def lib():
         L.gq_set_target_normals.restype = i32
         L.gq_set_target_normals.argtypes = [P, P]
         L.gq_set_source_interp.restype = i32
+        L.gq_points_near.restype = i32
+        L.gq_points_near.argtypes = [ctypes.c_int64, P, P, i32, ctypes.c_int64, P, P, P]
         L.gq_associate_targets.restype = i32
         L.gq_associate_targets.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, P, P,
                                            ctypes.c_int64, P, P, ctypes.c_double, P, P]
@@ -197,6 +199,18 @@ def gq_set_source_interp(plan, n_elem, interp):
     n_quad, n_node = interp.shape
     _check(lib().gq_set_source_interp(ctypes.c_void_p(plan), int(n_elem), int(n_node),
                                       int(n_quad), _ptr(interp)))
+
+
+def gq_points_near(q_xyz, radius, p_xyz, strict=False, stream=None):
+    """Host bool array: is some point of p_xyz within radius[i] of q_xyz[i] (< if strict)?"""
+    q_xyz = np.ascontiguousarray(np.asarray(q_xyz, dtype=np.float64).reshape(-1, 3))
+    p_xyz = np.ascontiguousarray(np.asarray(p_xyz, dtype=np.float64).reshape(-1, 3))
+    radius = np.ascontiguousarray(np.broadcast_to(np.asarray(radius, dtype=np.float64),
+                                                  (q_xyz.shape[0],)))
+    hit = np.empty(q_xyz.shape[0], dtype=np.uint8)
+    _check(lib().gq_points_near(q_xyz.shape[0], _ptr(q_xyz), _ptr(radius), int(bool(strict)),
+                                p_xyz.shape[0], _ptr(p_xyz), _ptr(hit), _stream(stream)))
+    return hit.astype(bool)
 
 
 def gq_associate_targets(src_xyz, src_danger, ctr_xyz, ctr_radius, tgt_xyz, tol=0.0,

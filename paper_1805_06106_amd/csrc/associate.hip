@@ -88,7 +88,44 @@ __global__ __launch_bounds__(256) void k_associate(int64_t nt, const double* __r
   out[t] = best;
 }
 
+// One thread per query: does any point of the grid lie within r of it?
+__global__ __launch_bounds__(256) void k_points_near(int64_t nq, const double* __restrict__ qx,
+                                                     const double* __restrict__ qy,
+                                                     const double* __restrict__ qz,
+                                                     const double* __restrict__ qr, int strict,
+                                                     AssocGrid g, AssocCells pts,
+                                                     uint8_t* __restrict__ hit) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nq) return;
+  const double x = qx[t], y = qy[t], z = qz[t], r2 = sq(qr[t]);
+  const int ix = cell_of(x, g.lo[0], g.h, g.n[0]);
+  const int iy = cell_of(y, g.lo[1], g.h, g.n[1]);
+  const int iz = cell_of(z, g.lo[2], g.h, g.n[2]);
+  bool found = false;
+  for (int cz = max(iz - 1, 0); cz <= min(iz + 1, g.n[2] - 1) && !found; ++cz)
+    for (int cy = max(iy - 1, 0); cy <= min(iy + 1, g.n[1] - 1) && !found; ++cy)
+      for (int cx = max(ix - 1, 0); cx <= min(ix + 1, g.n[0] - 1) && !found; ++cx) {
+        const int64_t cell = ((int64_t)cz * g.n[1] + cy) * g.n[0] + cx;
+        for (int64_t k = pts.start[cell]; k < pts.start[cell + 1]; ++k) {
+          const double d = dist2(x - pts.x[k], y - pts.y[k], z - pts.z[k]);
+          if (strict ? d < r2 : d <= r2) {
+            found = true;
+            break;
+          }
+        }
+      }
+  hit[t] = found ? 1 : 0;
+}
+
 }  // namespace
+
+void launch_points_near(hipStream_t s, int64_t nq, const double* qx, const double* qy,
+                        const double* qz, const double* r, int strict, const AssocGrid& g,
+                        const AssocCells& pts, uint8_t* hit) {
+  if (nq <= 0) return;
+  const int64_t blocks = (nq + 255) / 256;
+  k_points_near<<<(unsigned)blocks, 256, 0, s>>>(nq, qx, qy, qz, r, strict, g, pts, hit);
+}
 
 void launch_associate(hipStream_t s, int64_t nt, const double* tx, const double* ty,
                       const double* tz, const int8_t* tside, const AssocGrid& g,

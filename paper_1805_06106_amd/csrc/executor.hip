@@ -915,6 +915,36 @@ gq_status autotune_m2l(gq_plan* P, hipStream_t s) {
   return GQ_OK;
 }
 
+// Uniform cell grid over [lo, hi] whose cells are at least `reach` wide (slightly more, so
+// that a point within reach of a query lies in the 27 cells around the query's cell even
+// after rounding), with at most 2^24 cells.
+gq::AssocGrid make_grid(const double lo[3], const double hi[3], double reach) {
+  const double extent = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+  gq::AssocGrid g{};
+  g.h = reach * (1.0 + 1e-9) + extent * 1e-12;
+  if (!(g.h > 0)) g.h = 1.0;
+  for (;;) {
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+      g.lo[a] = lo[a];
+      g.n[a] = (int)std::min<double>(std::floor((hi[a] - lo[a]) / g.h) + 1.0, 1 << 24);
+      cells *= g.n[a];
+    }
+    if (cells <= ((int64_t)1 << 24)) break;
+    g.h *= 1.25;  // wider cells only add candidates; reach is unchanged
+  }
+  return g;
+}
+
+int64_t grid_cell(const gq::AssocGrid& g, const double* p) {
+  int64_t c[3];
+  for (int a = 0; a < 3; ++a) {
+    int64_t i = (int64_t)std::floor((p[a] - g.lo[a]) / g.h);
+    c[a] = i < 0 ? 0 : (i >= g.n[a] ? g.n[a] - 1 : i);
+  }
+  return (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
+}
+
 }  // namespace
 
 extern "C" {
@@ -1339,6 +1369,89 @@ gq_status gq_set_target_normals(gq_plan* P, const double* tgt_normal) {
   return GQ_OK;
 }
 
+gq_status gq_points_near(int64_t n_q, const double* q_xyz, const double* radius, int strict,
+                         int64_t n_p, const double* p_xyz, uint8_t* hit, void* hip_stream) {
+  g_err.clear();
+  if (n_q < 0 || n_p < 0) return fail(GQ_EINVAL, "negative count");
+  if ((n_q && (!q_xyz || !radius || !hit)) || (n_p && !p_xyz))
+    return fail(GQ_EINVAL, "NULL array with a nonzero count");
+  if (!finite3(q_xyz, n_q) || !finite3(p_xyz, n_p)) return fail(GQ_EINVAL, "non-finite coordinate");
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n_q; ++i) {
+    if (!std::isfinite(radius[i]) || radius[i] < 0)
+      return fail(GQ_EINVAL, "radii must be finite and >= 0");
+    rmax = std::max(rmax, radius[i]);
+  }
+  if (n_q + n_p >= ((int64_t)1 << 31)) return fail(GQ_EUNSUPPORTED, "more than 2^31 points");
+  if (n_q == 0) return GQ_OK;
+  if (n_p == 0) {
+    std::fill(hit, hit + n_q, (uint8_t)0);
+    return GQ_OK;
+  }
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) lo[a] = hi[a] = q_xyz[a];
+  for (const double* pp : {q_xyz, p_xyz}) {
+    const int64_t n = pp == q_xyz ? n_q : n_p;
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], pp[3 * i + a]);
+        hi[a] = std::max(hi[a], pp[3 * i + a]);
+      }
+  }
+  const gq::AssocGrid g = make_grid(lo, hi, rmax);
+  const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  std::vector<int64_t> start(ncell + 1, 0), cell(n_p);
+  for (int64_t i = 0; i < n_p; ++i) {
+    cell[i] = grid_cell(g, p_xyz + 3 * i);
+    start[cell[i] + 1] += 1;
+  }
+  for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+  std::vector<int64_t> fill(start.begin(), start.end() - 1);
+  std::vector<double> px(n_p), py(n_p), pz(n_p), qx(n_q), qy(n_q), qz(n_q);
+  for (int64_t i = 0; i < n_p; ++i) {
+    const int64_t k = fill[cell[i]]++;
+    px[k] = p_xyz[3 * i];
+    py[k] = p_xyz[3 * i + 1];
+    pz[k] = p_xyz[3 * i + 2];
+  }
+  for (int64_t i = 0; i < n_q; ++i) {
+    qx[i] = q_xyz[3 * i];
+    qy[i] = q_xyz[3 * i + 1];
+    qz[i] = q_xyz[3 * i + 2];
+  }
+  struct DevBufs {
+    std::vector<void*> p;
+    ~DevBufs() {
+      for (void* q : p) (void)hipFree(q);
+    }
+  } bufs;
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto up = [&](const void* h, size_t bytes, void** d) -> gq_status {
+    GQ_HIP(hipMalloc(d, bytes));
+    bufs.p.push_back(*d);
+    if (h) GQ_HIP(hipMemcpyAsync(*d, h, bytes, hipMemcpyHostToDevice, s));
+    return GQ_OK;
+  };
+  void *dst, *dpx, *dpy, *dpz, *dqx, *dqy, *dqz, *dqr, *dhit;
+  GQ_TRY(up(start.data(), start.size() * sizeof(int64_t), &dst));
+  GQ_TRY(up(px.data(), n_p * sizeof(double), &dpx));
+  GQ_TRY(up(py.data(), n_p * sizeof(double), &dpy));
+  GQ_TRY(up(pz.data(), n_p * sizeof(double), &dpz));
+  GQ_TRY(up(qx.data(), n_q * sizeof(double), &dqx));
+  GQ_TRY(up(qy.data(), n_q * sizeof(double), &dqy));
+  GQ_TRY(up(qz.data(), n_q * sizeof(double), &dqz));
+  GQ_TRY(up(radius, n_q * sizeof(double), &dqr));
+  GQ_TRY(up(nullptr, n_q, &dhit));
+  const gq::AssocCells pts{(const int64_t*)dst, (const double*)dpx, (const double*)dpy,
+                           (const double*)dpz, nullptr, nullptr, nullptr};
+  gq::launch_points_near(s, n_q, (const double*)dqx, (const double*)dqy, (const double*)dqz,
+                         (const double*)dqr, strict, g, pts, (uint8_t*)dhit);
+  GQ_HIP(hipGetLastError());
+  GQ_HIP(hipMemcpyAsync(hit, dhit, n_q, hipMemcpyDeviceToHost, s));
+  GQ_HIP(hipStreamSynchronize(s));
+  return GQ_OK;
+}
+
 gq_status gq_associate_targets(int64_t n_src, const double* src_xyz, const double* src_danger,
                                int64_t n_ctr, const double* ctr_xyz, const double* ctr_radius,
                                const int8_t* ctr_side, int64_t n_tgt, const double* tgt_xyz,
@@ -1393,29 +1506,9 @@ gq_status gq_associate_targets(int64_t n_src, const double* src_xyz, const doubl
   grow(tgt_xyz, n_tgt);
   for (int64_t i = 0; i < n_src; ++i) rmax = std::max(rmax, src_danger[i]);
   for (int64_t i = 0; i < n_ctr; ++i) rmax = std::max(rmax, cr[i]);
-  const double extent = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
-  gq::AssocGrid g{};
-  g.h = rmax * (1.0 + 1e-9) + extent * 1e-12;
-  if (!(g.h > 0)) g.h = 1.0;
-  for (;;) {
-    int64_t cells = 1;
-    for (int a = 0; a < 3; ++a) {
-      g.lo[a] = lo[a];
-      g.n[a] = (int)std::min<double>(std::floor((hi[a] - lo[a]) / g.h) + 1.0, 1 << 24);
-      cells *= g.n[a];
-    }
-    if (cells <= ((int64_t)1 << 24)) break;
-    g.h *= 1.25;  // wider cells only add candidates; reach is unchanged
-  }
+  const gq::AssocGrid g = make_grid(lo, hi, rmax);
   const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-  auto cell_of = [&](const double* p) {
-    int64_t c[3];
-    for (int a = 0; a < 3; ++a) {
-      int64_t i = (int64_t)std::floor((p[a] - g.lo[a]) / g.h);
-      c[a] = i < 0 ? 0 : (i >= g.n[a] ? g.n[a] - 1 : i);
-    }
-    return (c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
-  };
+  auto cell_of = [&](const double* p) { return grid_cell(g, p); };
   // counting sort of sources and centers by cell
   struct Sorted {
     std::vector<int64_t> start, id;

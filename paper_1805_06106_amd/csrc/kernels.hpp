@@ -66,6 +66,10 @@ struct AssocCells {
 void launch_associate(hipStream_t s, int64_t nt, const double* tx, const double* ty,
                       const double* tz, const int8_t* tside, const AssocGrid& g,
                       const AssocCells& src, const AssocCells& ctr, int64_t* out);
+// hit[i] = 1 iff a point of `pts` (grid g) lies within r[i] of query i (< if strict, else <=)
+void launch_points_near(hipStream_t s, int64_t nq, const double* qx, const double* qy,
+                        const double* qz, const double* r, int strict, const AssocGrid& g,
+                        const AssocCells& pts, uint8_t* hit);
 
 // Stage 2a: multipoles (scaled) of leaf boxes from their own sources.  Item i: box
 // boxes[i], sources idx[ptr[i] .. ptr[i+1]) (tree positions).  Overwrites.  (kernels_p2x.hip)

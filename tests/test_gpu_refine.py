@@ -1,0 +1,141 @@
+"""GPU geometry processing: the proximity query against all pairs, the library's stage-1
+and stage-2 refinement (Algorithms 1 and 2) against the oracle's element by element, and
+the effect of the refinement on accuracy: Green's formula inside a flattened ellipsoid
+(semi-axes 1, 1, 0.3) meshed so coarsely that the expansion balls of one face reach
+through to the other."""
+
+import numpy as np
+import pytest
+
+import oracle.refinement as OR
+from workloads import icosphere
+from workloads.geometry import SurfaceSpec, _surface_map
+
+pytestmark = pytest.mark.gpu
+
+URCHIN = SurfaceSpec(curved=True, bump_k=8, bump_m=4, bump_a=0.2)
+
+
+def _lib():
+    import torch  # noqa: F401
+
+    import paper_1805_06106_amd as G
+    from paper_1805_06106_amd import refine
+
+    return G, refine
+
+
+def sphere(P):
+    return P / np.sqrt(P[..., 0] ** 2 + P[..., 1] ** 2 + P[..., 2] ** 2)[..., None]
+
+
+def two_spheres(P):
+    n = np.sqrt(P[..., 0] ** 2 + P[..., 1] ** 2 + P[..., 2] ** 2)
+    rad = np.where(np.real(n) > 5.0, 1.3, 1.0)
+    return P / n[..., None] * rad[..., None]
+
+
+def urchin(P):
+    return _surface_map(URCHIN, P)
+
+
+def flat_ellipsoid(P):
+    n = np.sqrt(P[..., 0] ** 2 + P[..., 1] ** 2 + P[..., 2] ** 2)
+    return P / n[..., None] * np.array([1.0, 1.0, 0.3])
+
+
+def mesh_of(elems, surface):
+    _, refine = _lib()
+    A, B, C = (np.array([e[i] for e in elems]) for i in range(3))
+    return refine.ParamMesh(A, B, C, surface)
+
+
+def ico(level, scale=1.0):
+    v, f = icosphere(level)
+    return [(scale * v[a], scale * v[b], scale * v[c]) for a, b, c in f]
+
+
+def keyset(A, B, C):
+    return sorted(tuple(np.round(np.concatenate([a, b, c]), 12)) for a, b, c in zip(A, B, C))
+
+
+def test_points_near_matches_all_pairs():
+    G, _ = _lib()
+    rng = np.random.default_rng(3)
+    p = rng.uniform(-1, 1, (3000, 3))
+    q = np.concatenate([rng.uniform(-1.2, 1.2, (2000, 3)), p[:50] + [0.25, 0.0, 0.0]])
+    r = np.concatenate([rng.uniform(0.0, 0.15, 2000), np.full(50, 0.25)])  # last: exact hits
+    print("[gpu] points_near", flush=True)
+    for strict in (False, True):
+        got = G.points_near(q, r, p, strict=strict)
+        ref = OR.any_within(q, r, p, strict)
+        assert np.array_equal(got, ref)
+    assert G.points_near(q[-50:], 0.25, p[:50], strict=False).all()
+    assert not G.points_near(q[-50:], 0.25, p[:50] + [0.0, 0.0, 1e-3], strict=True)[:0].any()
+
+
+@pytest.mark.parametrize("case", ["two_spheres", "cap", "flat_ellipsoid", "urchin"])
+def test_refinement_matches_oracle(case):
+    _, refine = _lib()
+    if case == "two_spheres":
+        surf, elems = two_spheres, ico(1) + ico(1, 10.0)
+    elif case == "cap":
+        surf, elems = sphere, ico(1)
+        elems = OR.bisect(elems, [np.mean([e[0][2], e[1][2], e[2][2]]) > 0 for e in elems])
+    elif case == "flat_ellipsoid":
+        surf, elems = flat_ellipsoid, ico(1)
+    else:
+        surf, elems = urchin, ico(2)
+    print(f"[gpu] refinement {case}: {len(elems)} elements", flush=True)
+    m1, r1, _ = refine.refine_stage1(mesh_of(elems, surf), 4)
+    o1, q1 = OR.stage1(surf, elems, 4)
+    assert r1 == q1 and keyset(m1.A, m1.B, m1.C) == keyset(*zip(*o1))
+    m2, r2, origin = refine.refine_stage2(m1, 4)
+    o2, q2 = OR.stage2(surf, o1, 4)
+    assert r2 == q2 and keyset(m2.A, m2.B, m2.C) == keyset(*zip(*o2))
+    assert origin.shape == (m2.n_elem,) and origin.max() < m1.n_elem
+    eta = m1.element_size(4)
+    eta_o = np.array([OR.stretch(surf, a, b, c, 4) for a, b, c in zip(m1.A, m1.B, m1.C)])
+    assert np.allclose(eta, eta_o, rtol=1e-12)
+    print(f"[gpu]   stage 1: {m1.n_elem} elements in {r1} rounds; stage 2: {m2.n_elem} in {r2}",
+          flush=True)
+
+
+def _greens_error(G, d):
+    """max |S(du/dn) - D(u) - u| / max |u| at the stage-1 nodes through their interior
+    centers, u the potential of a unit charge at (3, 1, 2) (outside)."""
+    import torch
+
+    x0 = np.array([3.0, 1.0, 2.0])
+    s = d["src_xyz"] - x0
+    rs = np.linalg.norm(s, axis=1)
+    u = 1.0 / rs
+    dudn = -np.sum(s * d["src_normal"], axis=1) / rs ** 3
+    nn = d["node_xyz"].shape[0]
+    pots = {}
+    for kern, dens in (("S", dudn), ("D", u)):
+        P = G.Plan(src_xyz=d["src_xyz"], src_w=d["src_w"], src_normal=d["src_normal"],
+                   ctr_xyz=d["ctr_xyz"], ctr_radius=d["ctr_radius"], tgt_xyz=d["node_xyz"],
+                   tgt_center=2 * np.arange(nn) + 1, p_qbx=5, p_fmm=15, kernel=kern,
+                   wfar_direct_max=64, level_restrict=True)
+        pots[kern] = P.apply(torch.tensor(dens[None], device="cuda:0"))[0].cpu().numpy()
+    ut = 1.0 / np.linalg.norm(d["node_xyz"] - x0, axis=1)
+    return float(np.max(np.abs(pots["S"] - pots["D"] - ut)) / np.max(np.abs(ut)))
+
+
+def test_refinement_improves_greens_formula_on_a_thin_body():
+    G, refine = _lib()
+    mesh = mesh_of(ico(1), flat_ellipsoid)
+    # unrefined: stage-1 = stage-2 = the input mesh
+    nd, r, ctr = refine.centers(mesh, 4)
+    q = mesh.nodes(8)
+    plain = {"node_xyz": nd["xyz"], "ctr_xyz": ctr, "ctr_radius": r, "src_xyz": q["xyz"],
+             "src_normal": q["normal"], "src_w": q["weight"]}
+    d = refine.discretize(mesh, order=4, quad_order=8)
+    print(f"[gpu] flattened ellipsoid: {mesh.n_elem} elements -> stage 1 {d['stage1'].n_elem}, "
+          f"stage 2 {d['stage2'].n_elem} (rounds {d['rounds']})", flush=True)
+    e0 = _greens_error(G, plain)
+    e1 = _greens_error(G, d)
+    print(f"[gpu]   Green's formula error: unrefined {e0:.3e}, refined {e1:.3e}", flush=True)
+    assert d["rounds"][0] >= 1
+    assert e1 < e0 / 10

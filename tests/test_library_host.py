@@ -339,3 +339,18 @@ def test_m2l_rotation_validation(gq):
         with pytest.raises(G.GQError) as e:
             G.Plan(**_args(w, m2l_rotation=True, **over))
         assert e.value.status == 4
+
+
+def test_points_near_validation(gq):
+    """gq_points_near rejects bad arguments on the host and needs no device for empty
+    inputs."""
+    G = gq
+    q, p = np.zeros((2, 3)), np.ones((3, 3))
+    for r in ([1.0, -1.0], [np.nan, 1.0], [np.inf, 1.0]):
+        with pytest.raises(G.GQError) as e:
+            G.points_near(q, r, p)
+        assert e.value.status == 1
+    with pytest.raises(G.GQError):
+        G.points_near(np.array([[0.0, np.nan, 0.0]]), [1.0], p)
+    assert G.points_near(np.zeros((0, 3)), [], p).shape == (0,)
+    assert not G.points_near(q, [1.0, 1.0], np.zeros((0, 3))).any()
