@@ -13,8 +13,10 @@ r_k = eta_k / 2 (stage 1).  "Bisecting" an element splits it into the four trian
 edge midpoints in parameter space, which halves eta_k; the mesh need not stay conforming.
 
 * Stage 1 (truncation): a center c = x +- r_k n of a node x on element k whose ball of
-  radius (1 - eps) r_k holds another source point strictly inside marks element k; marked
-  elements are bisected until none is marked (eps = 0.025).
+  radius (1 - eps) r_k holds another source point strictly inside marks element k
+  (Algorithm 1, eps = 0.025), and so does a scaled curvature max(|k1|, |k2|) eta(x) above
+  0.8 at a node (the scaled-curvature criterion); marked elements are bisected until none
+  is marked.
 * Stage 2 (quadrature resolution): starting from the stage-1 elements, with the stage-1
   centers fixed, a stage-2 element with a source point within 0.5 (3/4) eta of some center
   is bisected, until none is.
@@ -83,21 +85,51 @@ class ParamMesh:
                 "weight": (w[None, :] * area).ravel(),
                 "elem": np.repeat(np.arange(self.n_elem), x.shape[0])}
 
-    def element_size(self, order: int):
-        """eta_k: the largest stretch factor 2 sigma_1 of the equilateral-reference map over
-        the element's order-`order` nodes and its vertices."""
+    def _stretch_points(self, order: int):
         x, y, _ = collapsed_rule(order)
-        x = np.concatenate([x, [0.0, 1.0, 1.0]])
-        y = np.concatenate([y, [0.0, 0.0, 1.0]])
+        return np.concatenate([x, [0.0, 1.0, 1.0]]), np.concatenate([y, [0.0, 0.0, 1.0]])
+
+    def scaled_curvature(self, order: int, h: float = 1e-5):
+        """kappa_k: the largest max(|k1|, |k2|) eta(x) over the element's nodes and vertices,
+        k1, k2 the principal curvatures (the scaled-curvature criterion of Section 3).  The
+        second derivatives are central differences of the exact first derivatives."""
+        x, y = self._stretch_points(order)
         _, Fx, Fy = self._map(x, y)
-        # columns of J M, M the equilateral map; sigma_1^2 = largest eigenvalue of the Gram
+        _, Fxp, Fyp = self._map(x + h, y)
+        _, Fxm, Fym = self._map(x - h, y)
+        _, Fxq, Fyq = self._map(x, y + h)
+        _, Fxr, Fyr = self._map(x, y - h)
+        Fxx = (Fxp - Fxm) / (2 * h)
+        Fyy = (Fyq - Fyr) / (2 * h)
+        Fxy = 0.5 * ((Fyp - Fym) / (2 * h) + (Fxq - Fxr) / (2 * h))
+        nrm = np.cross(Fx, Fy)
+        nrm /= np.linalg.norm(nrm, axis=2)[..., None]
+        E, Fm, Gm = (np.sum(a * b, axis=2) for a, b in ((Fx, Fx), (Fx, Fy), (Fy, Fy)))
+        L, M, N = (np.sum(a * nrm, axis=2) for a in (Fxx, Fxy, Fyy))
+        det = E * Gm - Fm * Fm
+        H = (E * N - 2.0 * Fm * M + Gm * L) / (2.0 * det)
+        K = (L * N - M * M) / det
+        kmax = np.abs(H) + np.sqrt(np.maximum(H * H - K, 0.0))
+        return np.max(kmax * self._stretch(Fx, Fy), axis=1)
+
+    @staticmethod
+    def _stretch(Fx, Fy):
+        """2 sigma_1 of the Jacobian of the equilateral-reference map, per point."""
         a = Fx * _EQ[0, 0] + Fy * _EQ[1, 0]
         b = Fx * _EQ[0, 1] + Fy * _EQ[1, 1]
         g11 = np.sum(a * a, axis=2)
         g22 = np.sum(b * b, axis=2)
         g12 = np.sum(a * b, axis=2)
         lam = 0.5 * (g11 + g22) + np.sqrt(0.25 * (g11 - g22) ** 2 + g12 * g12)
-        return np.max(2.0 * np.sqrt(lam), axis=1)
+        return 2.0 * np.sqrt(lam)
+
+    def element_size(self, order: int):
+        """eta_k: the largest stretch factor 2 sigma_1 of the equilateral-reference map over
+        the element's order-`order` nodes and its vertices."""
+        x, y = self._stretch_points(order)
+        _, Fx, Fy = self._map(x, y)
+        # columns of J M, M the equilateral map; sigma_1^2 = largest eigenvalue of the Gram
+        return np.max(self._stretch(Fx, Fy), axis=1)
 
     def bisect(self, mark):
         """A mesh with each marked element replaced by its four midpoint children (children
@@ -129,17 +161,20 @@ def centers(mesh: ParamMesh, order: int, eta=None):
     return nd, np.repeat(r, 2), c
 
 
-def refine_stage1(mesh: ParamMesh, order: int, eps: float = 0.025, max_rounds: int = 30,
-                  stream=None):
-    """Algorithm 1: bisect elements whose expansion balls of radius (1 - eps) r_k hold a
-    source point strictly inside, until none does.  Returns (mesh, rounds, origin) with
-    origin[k] the input element that element k came from."""
+def refine_stage1(mesh: ParamMesh, order: int, eps: float = 0.025, kappa_max=0.8,
+                  max_rounds: int = 30, stream=None):
+    """Stage-1 refinement: bisect elements whose expansion balls of radius (1 - eps) r_k
+    hold a source point strictly inside (Algorithm 1), or, unless kappa_max is None, whose
+    scaled curvature exceeds kappa_max (0.8 in the paper), until none does.  Returns
+    (mesh, rounds, origin) with origin[k] the input element that element k came from."""
     origin = np.arange(mesh.n_elem)
     for rounds in range(max_rounds + 1):
         nd, r, c = centers(mesh, order)
         hit = C.gq_points_near(c, (1.0 - eps) * r, nd["xyz"], strict=True, stream=stream)
         mark = np.zeros(mesh.n_elem, dtype=bool)
         mark[nd["elem"][np.nonzero(hit)[0] // 2]] = True
+        if kappa_max is not None:
+            mark |= mesh.scaled_curvature(order) > kappa_max
         if not mark.any() or rounds == max_rounds:
             return mesh, rounds, origin
         mesh = mesh.bisect(mark)
@@ -170,13 +205,13 @@ def refine_stage2(mesh1: ParamMesh, order: int, margin: float = 0.5 * 0.75,
 
 
 def discretize(mesh: ParamMesh, order: int = 4, quad_order: int = 8, eps: float = 0.025,
-               stream=None):
+               kappa_max=0.8, stream=None):
     """Stage 1 and 2 refinement of `mesh` and its stage-2 quadrature discretization.
 
     Returns a dict: the stage-1 nodes (targets, with their two centers each: ctr 2i exterior,
     2i+1 interior, and radii), the quadrature sources (xyz, normal, weight) on the stage-2
     elements with the order-`quad_order` rule, both meshes and the round counts."""
-    m1, rounds1, _ = refine_stage1(mesh, order, eps=eps, stream=stream)
+    m1, rounds1, _ = refine_stage1(mesh, order, eps=eps, kappa_max=kappa_max, stream=stream)
     eta1 = m1.element_size(order)
     nd1, r, ctr = centers(m1, order, eta1)
     m2, rounds2, origin2 = refine_stage2(m1, order, stream=stream)

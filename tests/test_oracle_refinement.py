@@ -10,6 +10,8 @@ Algorithms 1 and 2) on cases whose outcome follows from the definitions by hand:
 * one smooth sphere: Algorithm 1 changes nothing;
 * a sphere refined on one cap: Algorithm 2 bisects the coarse elements at the fringe and
   nothing far from it;
+* principal curvatures of an ellipsoid at its pole and rim (closed forms), and the scaled
+  curvature of a sphere of radius 1/2, which is exactly twice the stretch factor;
 and the postconditions of both algorithms, checked by a plain all-pairs test on samples.
 """
 
@@ -64,7 +66,7 @@ def test_stage1_two_concentric_spheres():
     elems = ico_elems(1) + ico_elems(1, scale=10.0)
     eta0 = np.array([R.stretch(two_spheres, *e, 4) for e in elems])
     assert eta0.min() > 0.6 and eta0.max() < 0.9
-    out, rounds = R.stage1(two_spheres, elems, 4, eps=EPS)
+    out, rounds = R.stage1(two_spheres, elems, 4, eps=EPS, kappa_max=None)
     eta = np.array([R.stretch(two_spheres, *e, 4) for e in out])
     bound = 2 * 0.3 / (2 - EPS)
     assert rounds == 2 and len(out) == 16 * len(elems)
@@ -76,7 +78,7 @@ def test_stage1_two_concentric_spheres():
 
 
 def test_stage1_leaves_a_smooth_sphere_alone():
-    elems = ico_elems(1)
+    elems = ico_elems(2)  # eta <= 0.45: scaled curvature below 0.8 as well
     out, rounds = R.stage1(sphere, elems, 4, eps=EPS)
     assert rounds == 0 and len(out) == len(elems)
 
@@ -87,7 +89,7 @@ def test_stage2_refines_the_fringe_of_a_refined_cap():
     elems = R.bisect(elems, top)
     cap = [np.mean([e[0][2], e[1][2], e[2][2]]) > 0.2 for e in elems]
     elems = R.bisect(elems, cap)
-    el1, r1 = R.stage1(sphere, elems, 4, eps=EPS)
+    el1, r1 = R.stage1(sphere, elems, 4, eps=EPS, kappa_max=None)
     assert r1 == 0 and len(el1) == len(elems)
     el2, r2 = R.stage2(sphere, el1, 4)
     assert r2 >= 1 and len(el2) > len(el1)
@@ -101,3 +103,40 @@ def test_stage2_refines_the_fringe_of_a_refined_cap():
     eta = np.array([R.stretch(sphere, *e, 4) for e in el2])
     pick = np.random.default_rng(1).choice(xyz.shape[0], 2000, replace=False)
     assert not brute_any(xyz[pick], 0.375 * eta[elem[pick]], ctr, strict=False).any()
+
+
+def _ref_point(A, B, C, P):
+    """Reference coordinates (x, y) of the parameter point P on the element's plane."""
+    M = np.stack([B - A, C - B], axis=1)
+    xy, *_ = np.linalg.lstsq(M, P - A, rcond=None)
+    return xy
+
+
+def test_principal_curvatures_of_an_ellipsoid():
+    """Semi-axes (1, 1, c): at the pole both principal curvatures are c; at the rim they
+    are 1/c^2 (across) and 1 (along); outward normals make them negative."""
+    c = 0.3
+    ell = lambda P: sphere(P) * np.array([1.0, 1.0, c])  # noqa: E731
+    A, B, C = np.array([0.1, 0.0, 1.0]), np.array([-0.05, 0.087, 1.0]), np.array([-0.05, -0.087, 1.0])
+    x, y = _ref_point(A, B, C, np.array([0.0, 0.0, 1.0]))
+    k = R.principal_curvatures(ell, A, B, C, [x], [y])[0]
+    assert np.allclose(k, [-c, -c], rtol=1e-7)
+    A, B, C = np.array([1.0, 0.1, 0.0]), np.array([1.0, -0.05, 0.087]), np.array([1.0, -0.05, -0.087])
+    x, y = _ref_point(A, B, C, np.array([1.0, 0.0, 0.0]))
+    k = R.principal_curvatures(ell, A, B, C, [x], [y])[0]
+    assert np.allclose(k, [-1.0 / c ** 2, -1.0], rtol=1e-7)
+
+
+def test_scaled_curvature_of_a_sphere_and_its_refinement():
+    """On a sphere of radius 1/2 the principal curvatures are 2, so kappa = 2 eta.  The
+    criterion is scale-free: the icosahedron's elements (kappa about 1.3) all exceed 0.8
+    and one bisection brings every element below it."""
+    half = lambda P: 0.5 * sphere(P)  # noqa: E731
+    for e in ico_elems(1)[:5]:
+        assert R.scaled_curvature(half, *e, 4) == pytest.approx(2.0 * R.stretch(half, *e, 4), rel=1e-7)
+    elems = ico_elems(0)
+    kap = np.array([R.scaled_curvature(half, *e, 4) for e in elems])
+    assert kap.min() > 0.8
+    out, rounds = R.stage1(half, elems, 4, eps=EPS, kappa_max=0.8)
+    assert rounds == 1 and len(out) == 4 * len(elems)
+    assert max(R.scaled_curvature(half, *e, 4) for e in out) <= 0.8
