@@ -114,6 +114,12 @@ def main():
                     help="1 (default): level-restricted tree, adjacent leaves differ by at most "
                          "one level (the remark on List 3 complexity); 0: the adaptive tree as "
                          "built")
+    ap.add_argument("--overlap", type=int, choices=[0, 1], default=0,
+                    help="1: the far-field chain (P2M, M2M, M2L, P2L, L2L) runs on a second "
+                         "stream beside the near field, and a few extra applies with every "
+                         "stage in order on one stream report each kernel's time alone; "
+                         "0 (default): every stage in order on one stream (no gain was "
+                         "measured from the second stream)")
     ap.add_argument("--m2l-rotation", type=int, choices=[0, 1], default=0,
                     help="1: FP64 M2L as rotate, translate along z, rotate back (three sparse "
                          "tile products) instead of one dense matrix per offset class")
@@ -165,7 +171,7 @@ def main():
         t0 = time.time()
         plan = Plan.from_workload(w, timing=True, precision=precision,
                                   m2l_rotation=bool(args.m2l_rotation) and precision == "fp64",
-                                  **tree_opts(args))
+                                  overlap=bool(args.overlap), **tree_opts(args))
         plan_wall = time.time() - t0
         st = plan.stats()
         log(f"[{precision}] plan: {st['n_boxes']} boxes, {st['n_levels']} levels, pairs "
@@ -188,10 +194,28 @@ def main():
         stage_ms = {s: v / k for s, v in st["stage_ms"].items()}
         log(f"[{precision}] {ms_per_step:.2f} ms/step, {w.n_tgt / (ms_per_step * 1e-3):.4g} "
             f"target evals/s; stage ms {stage_ms}")
+        alone = None
+        if args.overlap:
+            # outside the timed region: every stage in order on one stream, so that each
+            # stage time is its kernel's alone
+            plan.set_overlap(False)
+            n_alone = min(args.steps, 5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n_alone):
+                plan.apply(dens, pot, stream=stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st_a = plan.stats()
+            ka = max(st_a["timed_applies"], 1)
+            alone = {"ms_per_step": (t1 - t0) * 1e3 / n_alone, "steps": n_alone,
+                     "stage_ms": {s: v / ka for s, v in st_a["stage_ms"].items()}}
+            log(f"[{precision}] one stream: {alone['ms_per_step']:.2f} ms/step; stage ms "
+                f"{alone['stage_ms']}")
         plan.close()
-        return ms_per_step, stage_ms, st, plan_wall, pot
+        return ms_per_step, stage_ms, st, plan_wall, pot, alone
 
-    ms_per_step, stage_ms, st, plan_wall, pot = run("fp64")
+    ms_per_step, stage_ms, st, plan_wall, pot, alone = run("fp64")
     value = w.n_tgt / (ms_per_step * 1e-3)
 
     flops = CM.apply_flops(st, w.p_fmm, w.p_qbx, w.kernel)
@@ -205,6 +229,12 @@ def main():
                 "traffic": counter_traffic(dominant, w.name, args.wfar_direct_max,
                                            bool(args.level_restrict)),
                 "flops_per_launch": flops[dominant], "ms_per_launch": round(dom_ms, 4)}
+    if alone:
+        # the same kernel with the far field not running beside it
+        a_ms = alone["stage_ms"][kern_stage[dominant]]
+        roofline["ms_per_launch_alone"] = round(a_ms, 4)
+        roofline["frac_alone"] = round(flops[dominant] / (a_ms * 1e-3) / 1e12
+                                       / PEAK_FP64_VALU_TFLOPS, 4)
     per_stage = {}
     for s, f in flops.items():
         ms = stage_ms[kern_stage.get(s, s)]
@@ -215,6 +245,10 @@ def main():
            "tflops": per_stage["m2l"]["tflops"],
            "frac_of_fp64_mfma_peak": round(per_stage["m2l"]["tflops"] / PEAK_FP64_VALU_TFLOPS, 4)
            if per_stage["m2l"]["tflops"] else None}
+    if alone:
+        m2l["ms_alone"] = round(alone["stage_ms"]["m2l"], 4)
+        m2l["frac_of_fp64_mfma_peak_alone"] = round(
+            flops["m2l"] / (alone["stage_ms"]["m2l"] * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS, 4)
 
     # split-precision translations (FP32 matrix cores), with and without the hi/lo correction
     m2l_gemm_flops = flops["m2l"]
@@ -222,18 +256,22 @@ def main():
     if not args.no_fp32:
         p64 = pot[0].clone()
         for prec, products in (("fp32_split", 3), ("fp32", 1)):
-            ms_p, sm_p, _, _, pot_p = run(prec)
+            ms_p, sm_p, _, _, pot_p, alone_p = run(prec)
+            if alone_p:
+                sm_p = alone_p["stage_ms"]  # the M2L kernel's own time
             err = float((pot_p[0] - p64).abs().max() / p64.abs().max())
             m2l_ms = sm_p["m2l"]
             eff = m2l_gemm_flops / (m2l_ms * 1e-3) / 1e12
             split[prec] = {
                 "value": round(w.n_tgt / (ms_p * 1e-3), 1), "ms_per_step": round(ms_p, 4),
                 "rel_err_vs_fp64_path": err,
+                "ms_per_step_one_stream": round(alone_p["ms_per_step"], 4) if alone_p else None,
                 "m2l": {"ms": round(m2l_ms, 4), "mfma_products": products,
                         "executed_tflops": round(eff * products, 3),
                         "effective_tflops": round(eff, 3),
                         "frac_of_fp32_mfma_peak": round(eff * products / PEAK_FP32_MFMA_TFLOPS, 4)},
-                "stage_ms": {s: round(v, 4) for s, v in sm_p.items()},
+                ("stage_ms_one_stream" if alone_p else "stage_ms"):
+                    {s: round(v, 4) for s, v in sm_p.items()},
             }
             log(f"[{prec}] rel err vs fp64 path {err:.3e}")
 
@@ -275,7 +313,9 @@ def main():
                    "nmax": w.nmax, "tcf": w.tcf, "n_densities": 1, "precision": "fp64",
                    "wfar_direct_max": args.wfar_direct_max,
                    "level_restrict": bool(args.level_restrict),
-                   "m2l_rotation": bool(args.m2l_rotation)},
+                   "m2l_rotation": bool(args.m2l_rotation),
+                   "schedule": ("near and far field on two streams" if args.overlap
+                                else "one stream")},
         "rel_err_vs_direct_qbx": err_direct,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -283,6 +323,9 @@ def main():
         "split_precision": split,
         "stages": per_stage,
         "stage_ms": {s: round(v, 4) for s, v in stage_ms.items()},
+        "one_stream": ({"ms_per_step": round(alone["ms_per_step"], 4), "steps": alone["steps"],
+                        "stage_ms": {s: round(v, 4) for s, v in alone["stage_ms"].items()}}
+                       if alone else None),
         "plan_seconds": round(plan_wall, 3),
         "tree": {"boxes": st["n_boxes"], "levels": st["n_levels"], "pairs": st["pairs"]},
     }
@@ -399,7 +442,7 @@ def study_tcr(args, dev):
     variants = {"linf": dict(tcr_norm="linf"), "l2": dict(tcr_norm="l2"),
                 "l2_level_restricted": dict(tcr_norm="l2", level_restrict=True)}
     for tcr, kw in variants.items():
-        P = Plan.from_workload(w, timing=True, **kw)
+        P = Plan.from_workload(w, timing=True, overlap=False, **kw)  # stage times alone
         st = P.stats()
         model = CM.paper_list_model(st, w.p_fmm, w.p_qbx)
         pot = torch.empty((1, w.n_tgt), dtype=torch.float64, device=dev)

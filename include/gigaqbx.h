@@ -120,7 +120,8 @@ typedef struct {
   int64_t pairs[6];
   int64_t m2l_classes;      /* distinct M2L offsets in use (at most 1206) */
   double plan_seconds;      /* host tree + lists + matrices + upload */
-  /* With GQ_FLAG_TIMING: stage times (ms, HIP events on the apply stream) summed over all
+  /* With GQ_FLAG_TIMING: stage times (ms, HIP events on the stream that runs the stage;
+     see gq_set_overlap) summed over all
      gq_apply calls (and densities) since the previous gq_stats call, and their count:
      0 strength, 1 P2M, 2 M2M, 3 M2L, 4 P2L, 5 L2L, 6 P2QBXL, 7 M2QBXL, 8 L2QBXL,
      9 QBXL2P, 10 fill, 11 total */
@@ -171,6 +172,24 @@ gq_status gq_apply(gq_plan* plan, const double* density, double* potential, void
 /* Copy plan statistics.  With GQ_FLAG_TIMING this waits for the timed applies, sums
    their stage times into out->stage_ms and starts a new timing window. */
 gq_status gq_stats(gq_plan* plan, gq_stats_t* out);
+
+/*
+ * Concurrent near and far field inside one apply (default off: on = 0).  The stages of
+ * Algorithm 5 that build the box expansions (Stages 2, 4, 6b and 7: P2M, M2M, M2L, P2L,
+ * L2L) read only the strengths and write only M and L, and the near field (Stages 3, 5a and
+ * 6a) writes only the center locals, so the far-field chain runs on a stream owned by the
+ * plan, forked from the apply stream by an event after the expansions are cleared and
+ * joined back by an event before Stage 5b.  The apply is still ordered as a whole on the
+ * caller's stream; the plan's stream has the default priority.  on = 0 runs every stage in
+ * order on the apply stream.  It is off by default because on gfx950 the near-field
+ * kernel's waves fill every SIMD's registers, so the far-field workgroups wait for the near
+ * field to drain and the two streams gave no gain.  With GQ_FLAG_TIMING the far-field stage
+ * times are taken on
+ * the plan's stream, so with on = 1 the stage times overlap and may sum to more than the
+ * whole apply.  A captured graph (GQ_FLAG_GRAPH) is recaptured at the next apply after a
+ * change.  Errors: GQ_EINVAL for a NULL plan or on outside {0, 1}.
+ */
+gq_status gq_set_overlap(gq_plan* plan, int on);
 
 /*
  * Target normals for GQ_KERNEL_SP: tgt_normal[3*n_tgt] unit vectors (host, input target

@@ -41,7 +41,7 @@ STAGES = ("strength", "p2m", "m2m", "m2l", "p2l", "l2l", "p2qbxl", "m2qbxl", "l2
 EXPORTED = ("gq_plan_create", "gq_apply", "gq_stats", "gq_plan_destroy", "gq_last_error",
             "gq_tree_export", "gq_list_export", "gq_qbx_locals", "gq_translation_matrix",
             "gq_batch_create", "gq_set_target_normals", "gq_set_source_interp",
-            "gq_associate_targets", "gq_points_near")
+            "gq_associate_targets", "gq_points_near", "gq_set_overlap")
 GQ_TARGET_FAR = -1
 GQ_TARGET_UNMATCHED = -2
 
@@ -108,6 +108,8 @@ def lib():
         L.gq_qbx_locals.argtypes = [P, P]
         L.gq_set_target_normals.restype = i32
         L.gq_set_target_normals.argtypes = [P, P]
+        L.gq_set_overlap.restype = i32
+        L.gq_set_overlap.argtypes = [P, i32]
         L.gq_set_source_interp.restype = i32
         L.gq_points_near.restype = i32
         L.gq_points_near.argtypes = [ctypes.c_int64, P, P, i32, ctypes.c_int64, P, P, P]
@@ -184,6 +186,11 @@ def gq_plan_create(params, src_xyz, src_w, src_normal, ctr_xyz, ctr_radius, tgt_
                               _ptr(tgt_center), _stream(stream), ctypes.byref(out))
     _check(st)
     return out.value
+
+
+def gq_set_overlap(plan, on):
+    """1: far-field chain on the plan's own stream beside the near field; 0: all in order."""
+    _check(lib().gq_set_overlap(ctypes.c_void_p(plan), int(on)))
 
 
 def gq_set_target_normals(plan, normals):

@@ -59,6 +59,11 @@ void make_tiles(std::vector<std::array<int, 3>> pairs, TileSet& ts, int width = 
 
 }  // namespace
 
+// Timing events of one density pass: 0..11 close consecutive stages on the apply stream
+// (or, for the far-field chain, on the stream that runs it); 12 opens the near field and 13
+// the first stage after the join, so that neither interval counts the other stream's work.
+constexpr int kEvents = 14;
+
 struct gq_plan {
   gq_params prm{};
   int np = 0, nq = 0;
@@ -148,14 +153,23 @@ struct gq_plan {
   const double* graph_density = nullptr;
   double* graph_potential = nullptr;
   int64_t graph_launches = 0;
+  // near field and far field on two streams: the far-field chain (P2M, M2M, M2L, P2L,
+  // L2L) runs on `side`, forked from the apply stream after the fills and joined back before
+  // the first stage that reads M or L into the center locals
+  bool overlap = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // per-stage timing: one event set per density pass, summed by gq_stats()
-  std::vector<std::array<hipEvent_t, 12>> ev_sets;
+  std::vector<std::array<hipEvent_t, kEvents>> ev_sets;
   size_t ev_used = 0;
   int64_t timed_applies = 0;
 
   ~gq_plan() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     for (auto& set : ev_sets)
       for (auto& e : set) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
@@ -1180,76 +1194,91 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
   const bool sprime = P->prm.kernel == GQ_KERNEL_SP;
   const int prec = P->prm.precision;
   gq::SrcSoA src{P->sx, P->sy, P->sz, P->snx, P->sny, P->snz};
+  const bool overlap = P->overlap && P->side;
   hipEvent_t* ev = nullptr;
-  auto mark = [&](int i) -> gq_status {
-    if (timing) GQ_HIP(hipEventRecord(ev[i], s));
+  auto mark = [&](int i, hipStream_t st) -> gq_status {
+    if (timing) GQ_HIP(hipEventRecord(ev[i], st));
     return GQ_OK;
   };
   for (int d = 0; d < P->prm.n_densities; ++d) {
     if (timing) {
       if (P->ev_used == P->ev_sets.size()) {
-        std::array<hipEvent_t, 12> set{};
+        std::array<hipEvent_t, kEvents> set{};
         for (auto& e : set) GQ_HIP(hipEventCreate(&e));
         P->ev_sets.push_back(set);
       }
       ev = P->ev_sets[P->ev_used++].data();
     }
-    GQ_TRY(mark(0));
+    GQ_TRY(mark(0, s));
     if (P->interp)
       gq::launch_strength_interp(s, P->n_src, P->src_order, P->sw, P->n_node, P->n_quad,
                                  P->interp, density + (int64_t)d * P->n_elem * P->n_node, P->q);
     else
       gq::launch_strength(s, P->n_src, P->src_order, P->sw, density + (int64_t)d * P->n_src,
                           P->q);
-    GQ_TRY(mark(1));
+    GQ_TRY(mark(1, s));
     gq::launch_fill(s, P->M, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->L, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->Lq, (int64_t)P->n_ctr * P->nq, 0.0);
     if (P->n_pt > 0) gq::launch_fill(s, P->phi, P->n_pt, 0.0);
-    GQ_TRY(mark(2));
-    gq::launch_p2m(s, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_ptr,
+    GQ_TRY(mark(2, s));
+    // far-field chain: writes only M and L, so it may run beside the near field
+    hipStream_t f = s;
+    if (overlap) {
+      GQ_HIP(hipEventRecord(P->ev_fork, s));
+      GQ_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+      f = P->side;
+    }
+    gq::launch_p2m(f, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_ptr,
                    P->d_p2m_idx, P->bctr, P->bh, src, P->q, P->M);
-    GQ_TRY(mark(3));
+    GQ_TRY(mark(3, f));
     for (int l = T.nlevels - 1; l >= 1; --l) {
       const auto& t = P->m2m_levels[l];
       const auto& dd = P->d_m2m[l];
-      gq::launch_translate(s, 0, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_m2m,
+      gq::launch_translate(f, 0, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_m2m,
                            P->M, P->M);
     }
-    GQ_TRY(mark(4));
+    GQ_TRY(mark(4, f));
     if (P->prm.m2l_rotation)
-      gq::launch_m2l_rot(s, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
+      gq::launch_m2l_rot(f, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
                          P->d_m2l[3], P->d_m2l[4], P->rot, P->M, P->L, P->m2l_xcd);
     else
-      gq::launch_translate(s, 2, prec, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1],
+      gq::launch_translate(f, 2, prec, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1],
                            P->d_m2l[2], P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L,
                            P->m2l_cols, P->m2l_xcd);
-    GQ_TRY(mark(5));
-    gq::launch_p2l(s, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_ptr,
+    GQ_TRY(mark(5, f));
+    gq::launch_p2l(f, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_ptr,
                    P->d_p2l_idx, P->bctr, P->bh, src, P->q, P->L);
-    GQ_TRY(mark(6));
+    GQ_TRY(mark(6, f));
     for (int l = 1; l < T.nlevels; ++l) {
       const auto& t = P->l2l_levels[l];
       const auto& dd = P->d_l2l[l];
-      gq::launch_translate(s, 1, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_l2l,
+      gq::launch_translate(f, 1, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_l2l,
                            P->L, P->L);
     }
-    GQ_TRY(mark(7));
+    GQ_TRY(mark(7, f));
+    // near field: writes only Lq and the point-target potentials
+    GQ_TRY(mark(12, s));
     gq::launch_p2qbxl(s, kern, qo, (int)P->k3_box.size(), P->d_k3_box, P->d_k3_c0, P->d_k3_nc,
                       P->d_near_ptr, P->d_near_idx, src, P->q, P->cx, P->cy,
                       P->cz, P->Lq, P->n_ctr);
     gq::launch_p2p(s, kern, (int)P->pp_box.size(), P->d_pp_box, P->d_pp_t0, P->d_pp_nt,
                    P->d_near_ptr, P->d_near_idx, src, P->q, P->px, P->py, P->pz, P->phi);
-    GQ_TRY(mark(8));
+    GQ_TRY(mark(8, s));
+    if (overlap) {
+      GQ_HIP(hipEventRecord(P->ev_join, f));
+      GQ_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
+    }
+    GQ_TRY(mark(13, s));
     gq::launch_m2qbxl(s, p, qo, (int)P->k5_c0.size(), P->d_k5_c0, P->d_k5_nc, P->d_k5_w0,
                       P->d_k5_w1, P->d_wf_box, P->bctr, P->bh, P->M, P->cx, P->cy, P->cz,
                       P->Lq, P->n_ctr);
     gq::launch_m2p(s, p, (int)P->pm_t0.size(), P->d_pm_t0, P->d_pm_nt, P->d_pm_w0, P->d_pm_w1,
                    P->d_wf_box, P->bctr, P->bh, P->M, P->px, P->py, P->pz, P->phi);
-    GQ_TRY(mark(9));
+    GQ_TRY(mark(9, s));
     gq::launch_l2qbxl(s, p, qo, (int)P->k8_box.size(), P->d_k8_box, P->d_k8_c0, P->d_k8_nc,
                       P->bctr, P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
-    GQ_TRY(mark(10));
+    GQ_TRY(mark(10, s));
     if (sprime)
       gq::launch_qbxl2p_grad(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->tnx, P->tny,
                              P->tnz, P->cx, P->cy, P->cz, P->Lq, P->n_ctr, P->tgt_out,
@@ -1259,7 +1288,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
                         P->Lq, P->n_ctr, P->tgt_out, potential + (int64_t)d * P->n_tgt);
     gq::launch_l2p(s, p, P->n_pt, P->d_pt_box, P->bctr, P->bh, P->L, P->px, P->py, P->pz,
                    P->phi, P->d_pt_out, potential + (int64_t)d * P->n_tgt);
-    GQ_TRY(mark(11));
+    GQ_TRY(mark(11, s));
     GQ_HIP(hipGetLastError());
   }
   return GQ_OK;
@@ -1278,6 +1307,22 @@ gq_status gq_apply(gq_plan* P, const double* density, double* potential, void* h
     return fail(GQ_EINVAL, "S' needs the target normals (gq_set_target_normals)");
   hipStream_t s = (hipStream_t)hip_stream;
   P->last_stream = s;
+  if (P->overlap && !P->side) {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (join) (void)hipEventDestroy(join);
+      if (fork) (void)hipEventDestroy(fork);
+      if (side) (void)hipStreamDestroy(side);
+      return fail(GQ_EDEVICE, std::string("far-field stream: ") + hipGetErrorString(e));
+    }
+    P->side = side;
+    P->ev_fork = fork;
+    P->ev_join = join;
+  }
   const bool timing = (P->prm.flags & GQ_FLAG_TIMING) != 0;
   if (!(P->prm.flags & GQ_FLAG_GRAPH)) {
     GQ_TRY(apply_passes(P, density, potential, s, timing));
@@ -1323,7 +1368,8 @@ gq_status gq_stats(gq_plan* P, gq_stats_t* out) {
       auto& e = P->ev_sets[k];
       for (int i = 0; i < 11; ++i) {
         float t = 0.f;
-        GQ_HIP(hipEventElapsedTime(&t, e[i], e[i + 1]));
+        const hipEvent_t start = i == 7 ? e[12] : i == 8 ? e[13] : e[i];
+        GQ_HIP(hipEventElapsedTime(&t, start, e[i + 1]));
         ms[slot[i]] += t;
       }
       float tot = 0.f;
@@ -1339,6 +1385,20 @@ gq_status gq_stats(gq_plan* P, gq_stats_t* out) {
   P->stats.m2l_tile_cols = P->m2l_cols;
   P->stats.m2l_xcd_order = P->m2l_xcd ? 1 : 0;
   *out = P->stats;
+  return GQ_OK;
+}
+
+gq_status gq_set_overlap(gq_plan* P, int on) {
+  g_err.clear();
+  if (!P) return fail(GQ_EINVAL, "NULL plan");
+  if (on != 0 && on != 1) return fail(GQ_EINVAL, "on must be 0 or 1");
+  if (P->overlap == (on == 1)) return GQ_OK;
+  if (P->graph_exec) {  // the captured passes follow the old setting
+    if (P->last_stream) GQ_HIP(hipStreamSynchronize(P->last_stream));
+    GQ_HIP(hipGraphExecDestroy(P->graph_exec));
+    P->graph_exec = nullptr;
+  }
+  P->overlap = on == 1;
   return GQ_OK;
 }
 

@@ -16,7 +16,7 @@ class Plan:
                  p_qbx, p_fmm, kernel="S", nmax=512, tcf=0.9, n_densities=1, timing=False,
                  host_only=False, lists=None, wfar_direct_max=0, precision="fp64",
                  graph=False, autotune=False, tcr_norm="l2", level_restrict=False,
-                 m2l_rotation=False, stream=None):
+                 m2l_rotation=False, overlap=False, stream=None):
         flags = ((C.GQ_FLAG_TIMING if timing else 0) | (C.GQ_FLAG_HOST_ONLY if host_only else 0)
                  | (C.GQ_FLAG_GRAPH if graph else 0) | (C.GQ_FLAG_AUTOTUNE if autotune else 0))
         self.params = C.make_params(p_qbx, p_fmm, nmax=nmax, tcf=tcf, kernel=kernel,
@@ -33,6 +33,8 @@ class Plan:
         self.handle = None
         self.handle = C.gq_plan_create(self.params, src_xyz, src_w, src_normal, ctr_xyz,
                                        ctr_radius, tgt_xyz, tgt_center, stream=stream)
+        if overlap:
+            self.set_overlap(True)
 
     @classmethod
     def from_workload(cls, w, **kw):
@@ -45,7 +47,8 @@ class Plan:
         return plan
 
     @classmethod
-    def batch(cls, plans, *, timing=False, graph=False, autotune=False, stream=None):
+    def batch(cls, plans, *, timing=False, graph=False, autotune=False, overlap=False,
+              stream=None):
         """Merge plans (same orders, kernel, precision and density count) into one plan whose
         density/potential rows are the members' rows concatenated in the order given."""
         self = cls.__new__(cls)
@@ -60,6 +63,8 @@ class Plan:
         self.p_qbx = plans[0].p_qbx
         self.n_densities = plans[0].n_densities
         self.n_density_cols = self.n_src
+        if overlap:
+            self.set_overlap(True)
         return self
 
     def apply(self, density, potential=None, stream=None):
@@ -75,6 +80,11 @@ class Plan:
             raise ValueError(f"density shape {tuple(density.shape)} != {want}")
         C.gq_apply(self.handle, density, potential, stream=stream)
         return potential
+
+    def set_overlap(self, on):
+        """Run the far-field chain on a second stream beside the near field (True) or every
+        stage in order on the apply stream (False, the default)."""
+        C.gq_set_overlap(self.handle, 1 if on else 0)
 
     def set_target_normals(self, normals):
         """Target normals (n_tgt, 3) for the adjoint double layer (kernel "SP")."""

@@ -91,6 +91,46 @@ def test_graph_apply_replays_and_recaptures(members):
     assert rel(out2.cpu().numpy(), eager.apply(d1).cpu().numpy()) < 1e-14
 
 
+def test_overlapped_far_field_equals_serial(members):
+    """The far-field chain on the plan's own stream against every stage in order on one
+    stream (the default): eager, timed and graph applies, single and batch plans."""
+    import torch
+
+    from paper_1805_06106_amd import Plan
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(17)
+    for w in members[:2]:
+        serial = Plan.from_workload(w, n_densities=2)
+        d = torch.tensor(rng.standard_normal((2, w.n_src)), device=dev)
+        ref = serial.apply(d).cpu().numpy()
+        for kw in (dict(), dict(timing=True), dict(graph=True)):
+            print(f"[gpu] overlap vs serial {kw}", flush=True)
+            P = Plan.from_workload(w, n_densities=2, overlap=True, **kw)
+            out = torch.empty((2, w.n_tgt), dtype=torch.float64, device=dev)
+            for rep in range(3):
+                P.apply(d, out)
+                torch.cuda.synchronize()
+                assert rel(out.cpu().numpy(), ref) < 1e-14, (kw, rep)
+                d.mul_(1.0)  # eager work between replays
+            if kw.get("timing"):
+                st = P.stats()
+                assert st["timed_applies"] == 3
+                assert all(v >= 0 for v in st["stage_ms"].values())
+                assert st["stage_ms"]["total"] >= st["stage_ms"]["p2qbxl"]
+            # switching to serial recaptures the graph and gives the same result
+            P.set_overlap(False)
+            P.apply(d, out)
+            torch.cuda.synchronize()
+            assert rel(out.cpu().numpy(), ref) < 1e-14, kw
+            P.close()
+    plans = [Plan.from_workload(w, n_densities=2) for w in members]
+    dens = torch.tensor(np.concatenate([w.density for w in members], axis=1), device=dev)
+    a = Plan.batch(plans, graph=True, overlap=True).apply(dens).cpu().numpy()
+    b = Plan.batch(plans).apply(dens).cpu().numpy()
+    assert rel(a, b) < 1e-14
+
+
 def test_batch_rejects_mismatched_members(members):
     from paper_1805_06106_amd import GQError, Plan
 

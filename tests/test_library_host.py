@@ -247,6 +247,22 @@ def test_batch_and_graph_validation(gq):
     assert "exclusive" in str(e.value)
 
 
+def test_overlap_setting_validation(gq):
+    w = workload_tiny(level=0, order=2, kernel="D", p_qbx=2, p_fmm=4, nmax=16)
+    G = gq
+    P = G.Plan(**_args(w))  # host-only: the setting is stored, nothing is launched
+    P.set_overlap(False)
+    P.set_overlap(True)
+    from paper_1805_06106_amd import _capi as C
+
+    for bad in (2, -1):
+        with pytest.raises(G.GQError) as e:
+            C.gq_set_overlap(P.handle, bad)
+        assert e.value.status == 1
+    with pytest.raises(G.GQError):
+        C.gq_set_overlap(None, 1)
+
+
 def test_sprime_validation(gq):
     w = workload_tiny(level=1, order=2, kernel="S", p_qbx=2, p_fmm=4, nmax=16)
     G = gq
