@@ -720,17 +720,32 @@ __global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it
     for (int i = 0; i < NQ; ++i) unsafeAtomicAdd(&Lq[(int64_t)i * nctr + c], acc[i]);
 }
 
-template <int Q>
-__global__ __launch_bounds__(64) void k_l2qbxl(int P, const int* __restrict__ it_box,
-                                               const int* __restrict__ it_c0,
-                                               const int* __restrict__ it_nc,
-                                               const double* __restrict__ bctr,
-                                               const double* __restrict__ bh,
-                                               const double* __restrict__ L,
-                                               const double* __restrict__ cx,
-                                               const double* __restrict__ cy,
-                                               const double* __restrict__ cz,
-                                               double* __restrict__ Lq, int64_t nctr) {
+// Waves per L2QBXL item.  The padded table of the box local is shared by the item's waves,
+// which split the order loop and combine their sums at the end: with one wave per item the
+// 23 KB table of a 64-thread block held occupancy near 1.5 waves per SIMD.  From q = 9 on
+// the sums alone need most of a wave's registers, and one wave per item is kept.
+constexpr int l2q_waves(int q) { return q <= 8 ? 4 : 1; }
+
+// Wave that takes order mu: snake order over the NW waves, so that each gets the same
+// number of (order, degree) steps when the work of an order falls linearly with mu.
+template <int NW>
+__device__ __forceinline__ int l2q_owner(int mu) {
+  const int r = mu / NW, w = mu % NW;
+  return (r & 1) ? NW - 1 - w : w;
+}
+
+template <int Q, int NW = l2q_waves(Q)>
+__global__ __launch_bounds__(64 * NW) void k_l2qbxl(int P, const int* __restrict__ it_box,
+                                                           const int* __restrict__ it_c0,
+                                                           const int* __restrict__ it_nc,
+                                                           const double* __restrict__ bctr,
+                                                           const double* __restrict__ bh,
+                                                           const double* __restrict__ L,
+                                                           const double* __restrict__ cx,
+                                                           const double* __restrict__ cy,
+                                                           const double* __restrict__ cz,
+                                                           double* __restrict__ Lq,
+                                                           int64_t nctr) {
   using TB = L2qTab<Q>;
   constexpr int NQ = (Q + 1) * (Q + 1);
   __shared__ double2 tab[TB::ROWS * TB::W];
@@ -740,8 +755,9 @@ __global__ __launch_bounds__(64) void k_l2qbxl(int P, const int* __restrict__ it
   const int item = blockIdx.x;
   const int b = it_box[item];
   const int c0 = it_c0[item], nc = it_nc[item];
-  const bool active = (int)threadIdx.x < nc;
-  const int64_t c = (int64_t)c0 + (active ? threadIdx.x : 0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool active = lane < nc;
+  const int64_t c = (int64_t)c0 + (active ? lane : 0);
   const int np = (P + 1) * (P + 1);
   const double a = bh[b];
   __syncthreads();
@@ -755,12 +771,13 @@ __global__ __launch_bounds__(64) void k_l2qbxl(int P, const int* __restrict__ it
   for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
   double dr = 1.0, di = 0.0;
   for (int mu = 0; mu <= P; ++mu) {
-    if (mu > 0) {
+    if (mu > 0) {  // the diagonal R_mu^mu is carried by every wave
       const double f = -0.5 / mu;
       const double nr = f * (dr * vx - di * vy), ni = f * (dr * vy + di * vx);
       dr = nr;
       di = ni;
     }
+    if (l2q_owner<NW>(mu) != wave) continue;  // uniform over the wave
     const double sgn = (mu & 1) ? -1.0 : 1.0;
     double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
     for (int N = mu; N <= P; ++N) {
@@ -796,7 +813,25 @@ __global__ __launch_bounds__(64) void k_l2qbxl(int P, const int* __restrict__ it
       }
     }
   }
-  if (!active) return;
+  // Combine the waves' sums into wave 0 through LDS, reusing the table (no longer read):
+  // one wave's sums for up to CH coefficients at a time.
+  double* red = reinterpret_cast<double*>(tab);
+  constexpr int CH = (int)(sizeof(tab) / (64 * sizeof(double)));
+  static_assert(CH >= 1, "table too small to stage one coefficient of a wave");
+#pragma unroll
+  for (int i0 = 0; i0 < NQ; i0 += CH) {
+    for (int w = 1; w < NW; ++w) {
+      __syncthreads();
+      if (wave == w)
+#pragma unroll
+        for (int i = i0; i < (i0 + CH < NQ ? i0 + CH : NQ); ++i) red[(i - i0) * 64 + lane] = acc[i];
+      __syncthreads();
+      if (wave == 0)
+#pragma unroll
+        for (int i = i0; i < (i0 + CH < NQ ? i0 + CH : NQ); ++i) acc[i] += red[(i - i0) * 64 + lane];
+    }
+  }
+  if (wave != 0 || !active) return;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
 }
@@ -1004,8 +1039,8 @@ struct L2qbxlGo {
                  const int* it_nc, const double* bctr, const double* bh, const double* L,
                  const double* cx, const double* cy, const double* cz, double* Lq,
                  int64_t nctr) {
-    k_l2qbxl<Q><<<nitem, 64, 0, s>>>(p, it_box, it_c0, it_nc, bctr, bh, L, cx, cy, cz, Lq,
-                                     nctr);
+    k_l2qbxl<Q><<<nitem, 64 * l2q_waves(Q), 0, s>>>(p, it_box, it_c0, it_nc, bctr, bh, L, cx,
+                                                    cy, cz, Lq, nctr);
   }
 };
 
