@@ -630,11 +630,47 @@ __device__ __forceinline__ void cmac(double (&acc)[(Q + 1) * (Q + 1)], int j, in
   if (k) acc[cpk_im(j, k)] = fma(a.x, bi, fma(a.y, br, acc[cpk_im(j, k)]));
 }
 
+// Waves per M2QBXL and L2QBXL item.  The padded expansion table is shared by the item's
+// waves, which split the order loop and combine their sums at the end: with one wave per
+// item, the 20-23 KB table of a 64-thread block held occupancy near 1.5 waves per SIMD.
+// From q = 9 on the sums alone need most of a wave's registers, and one wave per item is
+// kept.
+constexpr int qbxl_waves(int q) { return q <= 8 ? 4 : 1; }
+
+// Wave that takes order mu: snake order over the NW waves, so that each gets the same
+// number of (order, degree) steps when the work of an order falls linearly with mu.
+template <int NW>
+__device__ __forceinline__ int order_owner(int mu) {
+  const int r = mu / NW, w = mu % NW;
+  return (r & 1) ? NW - 1 - w : w;
+}
+
+// Sum the NQ per-lane sums of the NW waves into wave 0 through the LDS array buf (of at
+// least 64 doubles, no longer read by the caller), up to bytes / 512 coefficients at a time.
+template <int NQ, int NW>
+__device__ __forceinline__ void sum_waves(double (&acc)[NQ], double* buf, int bytes) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ch = bytes / (64 * (int)sizeof(double));
+  for (int i0 = 0; i0 < NQ; i0 += ch)
+    for (int w = 1; w < NW; ++w) {
+      __syncthreads();
+      if (wave == w)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+          if (i >= i0 && i < i0 + ch) buf[(i - i0) * 64 + lane] = acc[i];
+      __syncthreads();
+      if (wave == 0)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+          if (i >= i0 && i < i0 + ch) acc[i] += buf[(i - i0) * 64 + lane];
+    }
+}
+
 // Item i: centers [it_c0, it_c0 + it_nc) of one target box and the List 3 far boxes
 // wf_box[it_w0 .. it_w1); long lists are split over several items, so the outputs are
 // added atomically.
-template <int Q, int PT>
-__global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it_c0,
+template <int Q, int PT, int NW = qbxl_waves(Q)>
+__global__ __launch_bounds__(64 * NW) void k_m2qbxl(int P, const int* __restrict__ it_c0,
                                                const int* __restrict__ it_nc,
                                                const int* __restrict__ it_w0,
                                                const int* __restrict__ it_w1,
@@ -652,8 +688,9 @@ __global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it
   for (int i = threadIdx.x; i < TB::ROWS * TB::W; i += blockDim.x) tab[i] = make_double2(0.0, 0.0);
   const int item = blockIdx.x;
   const int c0 = it_c0[item], nc = it_nc[item];
-  const bool active = (int)threadIdx.x < nc;
-  const int64_t c = (int64_t)c0 + (active ? threadIdx.x : 0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool active = lane < nc;
+  const int64_t c = (int64_t)c0 + (active ? lane : 0);
   const double xc = cx[c], yc = cy[c], zc = cz[c];
   const int np = (P + 1) * (P + 1);
   const int NT = P + Q;
@@ -672,13 +709,14 @@ __global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it
     // J'_N^M = (-1)^N conj(I_N^M)(v), generated for fixed M with increasing N
     double dr = sqrt(ir2), di = 0.0;
     for (int Mo = 0; Mo <= NT; ++Mo) {
-      if (Mo > 0) {
+      if (Mo > 0) {  // the diagonal is carried by every wave
         const double f = (2.0 * Mo - 1.0) * ir2;
         const double fr = f * vx, fi = -f * vy;
         const double nr = dr * fr - di * fi, ni = dr * fi + di * fr;
         dr = nr;
         di = ni;
       }
+      if (order_owner<NW>(Mo) != wave) continue;  // uniform over the wave
       const double sgn = (Mo & 1) ? -1.0 : 1.0;
       double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
       for (int N = Mo; N <= NT; ++N) {
@@ -715,26 +753,13 @@ __global__ __launch_bounds__(64) void k_m2qbxl(int P, const int* __restrict__ it
       }
     }
   }
-  if (active)
+  sum_waves<NQ, NW>(acc, reinterpret_cast<double*>(tab), (int)sizeof(tab));
+  if (wave == 0 && active)
 #pragma unroll
     for (int i = 0; i < NQ; ++i) unsafeAtomicAdd(&Lq[(int64_t)i * nctr + c], acc[i]);
 }
 
-// Waves per L2QBXL item.  The padded table of the box local is shared by the item's waves,
-// which split the order loop and combine their sums at the end: with one wave per item the
-// 23 KB table of a 64-thread block held occupancy near 1.5 waves per SIMD.  From q = 9 on
-// the sums alone need most of a wave's registers, and one wave per item is kept.
-constexpr int l2q_waves(int q) { return q <= 8 ? 4 : 1; }
-
-// Wave that takes order mu: snake order over the NW waves, so that each gets the same
-// number of (order, degree) steps when the work of an order falls linearly with mu.
-template <int NW>
-__device__ __forceinline__ int l2q_owner(int mu) {
-  const int r = mu / NW, w = mu % NW;
-  return (r & 1) ? NW - 1 - w : w;
-}
-
-template <int Q, int NW = l2q_waves(Q)>
+template <int Q, int NW = qbxl_waves(Q)>
 __global__ __launch_bounds__(64 * NW) void k_l2qbxl(int P, const int* __restrict__ it_box,
                                                            const int* __restrict__ it_c0,
                                                            const int* __restrict__ it_nc,
@@ -777,7 +802,7 @@ __global__ __launch_bounds__(64 * NW) void k_l2qbxl(int P, const int* __restrict
       dr = nr;
       di = ni;
     }
-    if (l2q_owner<NW>(mu) != wave) continue;  // uniform over the wave
+    if (order_owner<NW>(mu) != wave) continue;  // uniform over the wave
     const double sgn = (mu & 1) ? -1.0 : 1.0;
     double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
     for (int N = mu; N <= P; ++N) {
@@ -813,24 +838,7 @@ __global__ __launch_bounds__(64 * NW) void k_l2qbxl(int P, const int* __restrict
       }
     }
   }
-  // Combine the waves' sums into wave 0 through LDS, reusing the table (no longer read):
-  // one wave's sums for up to CH coefficients at a time.
-  double* red = reinterpret_cast<double*>(tab);
-  constexpr int CH = (int)(sizeof(tab) / (64 * sizeof(double)));
-  static_assert(CH >= 1, "table too small to stage one coefficient of a wave");
-#pragma unroll
-  for (int i0 = 0; i0 < NQ; i0 += CH) {
-    for (int w = 1; w < NW; ++w) {
-      __syncthreads();
-      if (wave == w)
-#pragma unroll
-        for (int i = i0; i < (i0 + CH < NQ ? i0 + CH : NQ); ++i) red[(i - i0) * 64 + lane] = acc[i];
-      __syncthreads();
-      if (wave == 0)
-#pragma unroll
-        for (int i = i0; i < (i0 + CH < NQ ? i0 + CH : NQ); ++i) acc[i] += red[(i - i0) * 64 + lane];
-    }
-  }
+  sum_waves<NQ, NW>(acc, reinterpret_cast<double*>(tab), (int)sizeof(tab));
   if (wave != 0 || !active) return;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
@@ -1019,16 +1027,16 @@ struct M2qbxlGo {
                  const double* cz, double* Lq, int64_t nctr) {
     // smallest compiled table bound covering p
     if (p <= 8)
-      k_m2qbxl<Q, 8><<<nitem, 64, 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
+      k_m2qbxl<Q, 8><<<nitem, 64 * qbxl_waves(Q), 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
                                           cx, cy, cz, Lq, nctr);
     else if (p <= 12)
-      k_m2qbxl<Q, 12><<<nitem, 64, 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
+      k_m2qbxl<Q, 12><<<nitem, 64 * qbxl_waves(Q), 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
                                            cx, cy, cz, Lq, nctr);
     else if (p <= 16)
-      k_m2qbxl<Q, 16><<<nitem, 64, 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
+      k_m2qbxl<Q, 16><<<nitem, 64 * qbxl_waves(Q), 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh, M,
                                            cx, cy, cz, Lq, nctr);
     else
-      k_m2qbxl<Q, kPmax><<<nitem, 64, 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh,
+      k_m2qbxl<Q, kPmax><<<nitem, 64 * qbxl_waves(Q), 0, s>>>(p, it_c0, it_nc, it_w0, it_w1, wf_box, bctr, bh,
                                               M, cx, cy, cz, Lq, nctr);
   }
 };
@@ -1039,7 +1047,7 @@ struct L2qbxlGo {
                  const int* it_nc, const double* bctr, const double* bh, const double* L,
                  const double* cx, const double* cy, const double* cz, double* Lq,
                  int64_t nctr) {
-    k_l2qbxl<Q><<<nitem, 64 * l2q_waves(Q), 0, s>>>(p, it_box, it_c0, it_nc, bctr, bh, L, cx,
+    k_l2qbxl<Q><<<nitem, 64 * qbxl_waves(Q), 0, s>>>(p, it_box, it_c0, it_nc, bctr, bh, L, cx,
                                                     cy, cz, Lq, nctr);
   }
 };
