@@ -36,8 +36,10 @@ constexpr int kTri = (kPmax + 2) * (kPmax + 3) / 2;     // entries 0 <= m <= N <
 __device__ __forceinline__ int tri(int N, int m) { return N * (N + 1) / 2 + m; }
 
 // EMAX >= NT + 2: entries per thread (its two columns); the diagonal table holds NT + 1.
+// Up to EMAX = 18 (p = 15 and below) the registers are capped for 4 waves per SIMD, which
+// the LDS footprint of a block also allows.
 template <int KERN, bool IRR, int EMAX>
-__global__ __launch_bounds__(256) void k_p2x(int P, const int* __restrict__ boxes,
+__global__ __launch_bounds__(256, EMAX <= 18 ? 4 : 1) void k_p2x(int P, const int* __restrict__ boxes,
                                              const int64_t* __restrict__ ptr,
                                              const int* __restrict__ idx,
                                              const double* __restrict__ bctr,
@@ -242,6 +244,8 @@ void launch_p2x_k(hipStream_t s, int p, int nitem, const int* boxes, const int64
     k_p2x<KERN, IRR, 12><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
   else if (e <= 16)
     k_p2x<KERN, IRR, 16><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
+  else if (e <= 18)
+    k_p2x<KERN, IRR, 18><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
   else if (e <= 20)
     k_p2x<KERN, IRR, 20><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
   else
