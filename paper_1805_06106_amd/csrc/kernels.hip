@@ -634,7 +634,8 @@ __device__ __forceinline__ void cmac(double (&acc)[(Q + 1) * (Q + 1)], int j, in
 // waves, which split the order loop and combine their sums at the end: with one wave per
 // item, the 20-23 KB table of a 64-thread block held occupancy near 1.5 waves per SIMD.
 // From q = 9 on the sums alone need most of a wave's registers, and one wave per item is
-// kept.
+// kept.  Up to q = 5 the registers are capped for 3 (M2QBXL) and 4 (L2QBXL) waves per SIMD,
+// at the cost of 2 spilled VGPRs.
 constexpr int qbxl_waves(int q) { return q <= 8 ? 4 : 1; }
 
 // Wave that takes order mu: snake order over the NW waves, so that each gets the same
@@ -670,7 +671,7 @@ __device__ __forceinline__ void sum_waves(double (&acc)[NQ], double* buf, int by
 // wf_box[it_w0 .. it_w1); long lists are split over several items, so the outputs are
 // added atomically.
 template <int Q, int PT, int NW = qbxl_waves(Q)>
-__global__ __launch_bounds__(64 * NW) void k_m2qbxl(int P, const int* __restrict__ it_c0,
+__global__ __launch_bounds__(64 * NW, Q <= 5 ? 3 : 1) void k_m2qbxl(int P, const int* __restrict__ it_c0,
                                                const int* __restrict__ it_nc,
                                                const int* __restrict__ it_w0,
                                                const int* __restrict__ it_w1,
@@ -760,7 +761,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2qbxl(int P, const int* __restrict
 }
 
 template <int Q, int NW = qbxl_waves(Q)>
-__global__ __launch_bounds__(64 * NW) void k_l2qbxl(int P, const int* __restrict__ it_box,
+__global__ __launch_bounds__(64 * NW, Q <= 5 ? 4 : 1) void k_l2qbxl(int P, const int* __restrict__ it_box,
                                                            const int* __restrict__ it_c0,
                                                            const int* __restrict__ it_nc,
                                                            const double* __restrict__ bctr,
