@@ -25,6 +25,8 @@ CASES = {
     "S-l2-tf05": dict(level=2, order=1, kernel="S", p_qbx=2, p_fmm=5, nmax=24, tcf=0.5),
     "D-l2-flat": dict(level=2, order=1, kernel="D", p_qbx=2, p_fmm=5, nmax=40, curved=False),
     "D-l2-q5p15": dict(level=2, order=2, kernel="D", p_qbx=5, p_fmm=15, nmax=48),
+    # smallest M2QBXL table (p <= 8) at q = 5: the waves' sums are combined in two rounds
+    "D-l2-q5p8": dict(level=2, order=2, kernel="D", p_qbx=5, p_fmm=8, nmax=32),
     "S-l2-q8p20": dict(level=2, order=2, kernel="S", p_qbx=8, p_fmm=20, nmax=48),
 }
 
