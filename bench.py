@@ -32,11 +32,11 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "6821418b79c45737906c5a70f3387c2e76d2ef1c487d907c2c8e1f31634c9650",
+    "kernels_sha256": "ff094571b584fece1f4d6342653afb6a8b27406c7b7c3060c292a20db9955eab",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 8.10117e+09, "m2l": 1.40455e+10, "m2qbxl": 8.94792e+07,
-                         "l2qbxl": 9.40442e+08},
+    "bytes_per_launch": {"p2qbxl": 8.09831e+09, "m2l": 1.40416e+10, "m2qbxl": 9.267e+07,
+                         "l2qbxl": 9.62257e+08},
 }
 
 
