@@ -35,8 +35,8 @@ COUNTER_TRAFFIC = {
     "kernels_sha256": "ff094571b584fece1f4d6342653afb6a8b27406c7b7c3060c292a20db9955eab",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 8.09831e+09, "m2l": 1.40416e+10, "m2qbxl": 9.267e+07,
-                         "l2qbxl": 9.62257e+08},
+    "bytes_per_launch": {"p2qbxl": 8.10219e+09, "m2l": 1.40425e+10, "m2qbxl": 9.26706e+07,
+                         "l2qbxl": 9.6222e+08},
 }
 
 
@@ -120,6 +120,11 @@ def main():
                          "stage in order on one stream report each kernel's time alone; "
                          "0 (default): every stage in order on one stream (no gain was "
                          "measured from the second stream)")
+    ap.add_argument("--autotune", type=int, choices=[0, 1], default=0,
+                    help="1: time the M2L launch at plan creation over tile widths 64 and 32, "
+                         "with and without the XCD-aware order, and keep the fastest (outside "
+                         "the timed region); 0 (default): the library's default tiles (FP64: "
+                         "width 32, FP32: 64; XCD-aware order)")
     ap.add_argument("--m2l-rotation", type=int, choices=[0, 1], default=0,
                     help="1: FP64 M2L as rotate, translate along z, rotate back (three sparse "
                          "tile products) instead of one dense matrix per offset class")
@@ -171,7 +176,8 @@ def main():
         t0 = time.time()
         plan = Plan.from_workload(w, timing=True, precision=precision,
                                   m2l_rotation=bool(args.m2l_rotation) and precision == "fp64",
-                                  overlap=bool(args.overlap), **tree_opts(args))
+                                  overlap=bool(args.overlap), autotune=bool(args.autotune),
+                                  **tree_opts(args))
         plan_wall = time.time() - t0
         st = plan.stats()
         log(f"[{precision}] plan: {st['n_boxes']} boxes, {st['n_levels']} levels, pairs "
@@ -314,6 +320,8 @@ def main():
                    "wfar_direct_max": args.wfar_direct_max,
                    "level_restrict": bool(args.level_restrict),
                    "m2l_rotation": bool(args.m2l_rotation),
+                   "m2l_autotune": bool(args.autotune),
+                   "m2l_tile": [st.get("m2l_tile_cols"), st.get("m2l_xcd_order")],
                    "schedule": ("near and far field on two streams" if args.overlap
                                 else "one stream")},
         "rel_err_vs_direct_qbx": err_direct,
@@ -491,7 +499,8 @@ def bench_fresh_densities(args, dev):
     log(f"workload {w.name}: {w.n_src} sources, {w.n_tgt} targets, {n} fresh densities "
         f"({time.time() - t0:.1f}s)")
     t0 = time.time()
-    plan = Plan.from_workload(w, **tree_opts(args), precision="fp32_split")
+    plan = Plan.from_workload(w, **tree_opts(args), precision="fp32_split",
+                              autotune=bool(args.autotune))
     plan_s = time.time() - t0
     out = torch.empty((n, w.n_tgt), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -534,7 +543,8 @@ def bench_fresh_densities(args, dev):
                    "kernel": w.kernel, "p_qbx": w.p_qbx, "p_fmm": w.p_fmm,
                    "n_sources": w.n_src, "n_targets": w.n_tgt, "precision": "fp32_split",
                    "densities": n, "wfar_direct_max": args.wfar_direct_max,
-                   "level_restrict": bool(args.level_restrict)},
+                   "level_restrict": bool(args.level_restrict),
+                   "m2l_autotune": bool(args.autotune)},
         "rel_err_vs_fp64_path": err64, "rel_err_vs_direct_qbx": err_direct,
         "plan_seconds": round(plan_s, 3)}), flush=True)
 

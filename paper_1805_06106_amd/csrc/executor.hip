@@ -57,6 +57,14 @@ void make_tiles(std::vector<std::array<int, 3>> pairs, TileSet& ts, int width = 
   }
 }
 
+// M2L tile width of a plan that is not autotuned.  FP64: 32 pairs, the autotuner's choice on
+// the urchin (7.6 against 8.4 ms for 64) and on the 8-surface batch.  The FP32 kernels keep
+// 64, and the rotation kernel has its own width.
+int default_m2l_cols(const gq_params& prm) {
+  if (prm.m2l_rotation) return gq::kRotCols;
+  return prm.precision == GQ_FP64 ? 32 : gq::kTileCols;
+}
+
 }  // namespace
 
 // Timing events of one density pass: 0..11 close consecutive stages on the apply stream
@@ -358,8 +366,8 @@ gq_status build_work(gq_plan* P) {
         pairs.push_back({ci, d, b});
       }
     }
-    make_tiles(pairs, P->m2l, P->prm.m2l_rotation ? gq::kRotCols : gq::kTileCols);
-    if (P->prm.m2l_rotation) P->m2l_cols = gq::kRotCols;
+    P->m2l_cols = default_m2l_cols(P->prm);
+    make_tiles(pairs, P->m2l, P->m2l_cols);
   }
   // Stage 6b
   if (on(GQ_LIST_XFAR)) {
@@ -788,8 +796,8 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
     make_tiles(m2m[l], B->m2m_levels[l]);
     make_tiles(l2l[l], B->l2l_levels[l]);
   }
-  make_tiles(m2l, B->m2l, B->prm.m2l_rotation ? gq::kRotCols : gq::kTileCols);
-  if (B->prm.m2l_rotation) B->m2l_cols = gq::kRotCols;
+  B->m2l_cols = default_m2l_cols(B->prm);
+  make_tiles(m2l, B->m2l, B->m2l_cols);
   sort_near_items(B);
   return GQ_OK;
 }
