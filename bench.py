@@ -35,8 +35,8 @@ COUNTER_TRAFFIC = {
     "kernels_sha256": "ff094571b584fece1f4d6342653afb6a8b27406c7b7c3060c292a20db9955eab",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 8.10219e+09, "m2l": 1.40425e+10, "m2qbxl": 9.26706e+07,
-                         "l2qbxl": 9.6222e+08},
+    "bytes_per_launch": {"p2qbxl": 8.10136e+09, "m2l": 1.40406e+10, "m2qbxl": 9.26715e+07,
+                         "l2qbxl": 9.62038e+08},
 }
 
 
@@ -123,8 +123,8 @@ def main():
     ap.add_argument("--autotune", type=int, choices=[0, 1], default=0,
                     help="1: time the M2L launch at plan creation over tile widths 64 and 32, "
                          "with and without the XCD-aware order, and keep the fastest (outside "
-                         "the timed region); 0 (default): the library's default tiles (FP64: "
-                         "width 32, FP32: 64; XCD-aware order)")
+                         "the timed region); 0 (default): the library's default tiles (width "
+                         "64 for split FP32, 32 otherwise; XCD-aware order)")
     ap.add_argument("--m2l-rotation", type=int, choices=[0, 1], default=0,
                     help="1: FP64 M2L as rotate, translate along z, rotate back (three sparse "
                          "tile products) instead of one dense matrix per offset class")

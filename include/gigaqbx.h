@@ -68,8 +68,8 @@ typedef enum { GQ_FP64 = 0, GQ_FP32_SPLIT = 1, GQ_FP32 = 2 } gq_precision;
 #define GQ_FLAG_GRAPH (1u << 2)
 /* At plan creation, time the Stage 4 (M2L) launch for tile widths 64 and 32 and for
    XCD-aware or plain tile order on the plan's own tiles, and keep the fastest (reported in
-   gq_stats_t).  Without it: XCD-aware order, width 32 for FP64 and 64 for the FP32
-   precisions (32 for the rotation M2L). */
+   gq_stats_t).  Without it: XCD-aware order, width 64 for GQ_FP32_SPLIT and 32 otherwise
+   (also for the rotation M2L). */
 #define GQ_FLAG_AUTOTUNE (1u << 3)
 /* Which interaction lists contribute (testing aid).  0 in bits 8..13 means all. */
 #define GQ_LIST_U (1u << 8)       /* List 1 (direct)            Stage 3 */

@@ -57,12 +57,13 @@ void make_tiles(std::vector<std::array<int, 3>> pairs, TileSet& ts, int width = 
   }
 }
 
-// M2L tile width of a plan that is not autotuned.  FP64: 32 pairs, the autotuner's choice on
-// the urchin (7.6 against 8.4 ms for 64) and on the 8-surface batch.  The FP32 kernels keep
-// 64, and the rotation kernel has its own width.
+// M2L tile width of a plan that is not autotuned: the autotuner's choices on the urchin.
+// FP64 and FP32: 32 pairs (FP64 7.6 against 8.4 ms for 64, FP32 5.2 against 6.1 ms); the
+// split FP32 kernel, with three products per tile, keeps 64 (equal or better), and the
+// rotation kernel has its own width.
 int default_m2l_cols(const gq_params& prm) {
   if (prm.m2l_rotation) return gq::kRotCols;
-  return prm.precision == GQ_FP64 ? 32 : gq::kTileCols;
+  return prm.precision == GQ_FP32_SPLIT ? gq::kTileCols : 32;
 }
 
 }  // namespace
