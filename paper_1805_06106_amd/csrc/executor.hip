@@ -66,6 +66,10 @@ int default_m2l_cols(const gq_params& prm) {
   return prm.precision == GQ_FP32_SPLIT ? gq::kTileCols : 32;
 }
 
+// M2M and L2L tile width, by the same rule as M2L: the level passes have few tiles at the
+// coarse levels, where narrower tiles give more workgroups.
+int level_cols(const gq_params& prm) { return prm.precision == GQ_FP32_SPLIT ? gq::kTileCols : 32; }
+
 }  // namespace
 
 // Timing events of one density pass: 0..11 close consecutive stages on the apply stream
@@ -108,6 +112,7 @@ struct gq_plan {
   std::vector<int> pm_t0, pm_nt, pm_w0, pm_w1;  // multipole-evaluation items
   std::vector<int> cls_keys;           // M2L class index -> offset key
   int m2l_cols = gq::kTileCols;        // M2L tile width (32 or 64)
+  int lvl_cols = gq::kTileCols;        // M2M and L2L tile width (32 or 64)
   bool m2l_xcd = true;                 // XCD-aware M2L tile order
   std::vector<int64_t> h_tgt_ctr, h_tgt_out;  // host copies of tgt_ctr / tgt_out
   bool is_batch = false;               // made by gq_batch_create
@@ -338,7 +343,8 @@ gq_status build_work(gq_plan* P) {
         if (T.child[pb][o] == b) oct = o;
       per[T.level[b]].push_back({oct, b, pb});
     }
-    for (int l = 0; l < T.nlevels; ++l) make_tiles(per[l], P->m2m_levels[l]);
+    P->lvl_cols = level_cols(P->prm);
+    for (int l = 0; l < T.nlevels; ++l) make_tiles(per[l], P->m2m_levels[l], P->lvl_cols);
   }
   // Stage 4
   std::map<int, int> cls_index;
@@ -400,7 +406,8 @@ gq_status build_work(gq_plan* P) {
         if (T.child[pb][o] == b) oct = o;
       per[T.level[b]].push_back({oct, pb, b});
     }
-    for (int l = 0; l < T.nlevels; ++l) make_tiles(per[l], P->l2l_levels[l]);
+    P->lvl_cols = level_cols(P->prm);
+    for (int l = 0; l < T.nlevels; ++l) make_tiles(per[l], P->l2l_levels[l], P->lvl_cols);
   }
   // Stages 3, 5a, 6a (near sources), 5b (W-far), 8
   P->near_ptr.assign(nb + 1, 0);
@@ -793,9 +800,10 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
   S.m2l_classes = (int64_t)B->cls_keys.size();
   B->m2m_levels.assign(nlev, TileSet());
   B->l2l_levels.assign(nlev, TileSet());
+  B->lvl_cols = level_cols(B->prm);
   for (int l = 0; l < nlev; ++l) {
-    make_tiles(m2m[l], B->m2m_levels[l]);
-    make_tiles(l2l[l], B->l2l_levels[l]);
+    make_tiles(m2m[l], B->m2m_levels[l], B->lvl_cols);
+    make_tiles(l2l[l], B->l2l_levels[l], B->lvl_cols);
   }
   B->m2l_cols = default_m2l_cols(B->prm);
   make_tiles(m2l, B->m2l, B->m2l_cols);
@@ -1245,7 +1253,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
       const auto& t = P->m2m_levels[l];
       const auto& dd = P->d_m2m[l];
       gq::launch_translate(f, 0, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_m2m,
-                           P->M, P->M);
+                           P->M, P->M, P->lvl_cols);
     }
     GQ_TRY(mark(4, f));
     if (P->prm.m2l_rotation)
@@ -1263,7 +1271,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
       const auto& t = P->l2l_levels[l];
       const auto& dd = P->d_l2l[l];
       gq::launch_translate(f, 1, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_l2l,
-                           P->L, P->L);
+                           P->L, P->L, P->lvl_cols);
     }
     GQ_TRY(mark(7, f));
     // near field: writes only Lq and the point-target potentials
