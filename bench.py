@@ -35,8 +35,8 @@ COUNTER_TRAFFIC = {
     "kernels_sha256": "ff094571b584fece1f4d6342653afb6a8b27406c7b7c3060c292a20db9955eab",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 8.10136e+09, "m2l": 1.40406e+10, "m2qbxl": 9.26715e+07,
-                         "l2qbxl": 9.62038e+08},
+    "bytes_per_launch": {"p2qbxl": 8.10322e+09, "m2l": 1.40428e+10, "m2qbxl": 9.26699e+07,
+                         "l2qbxl": 9.62256e+08},
 }
 
 
