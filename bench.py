@@ -32,7 +32,7 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "ff094571b584fece1f4d6342653afb6a8b27406c7b7c3060c292a20db9955eab",
+    "kernels_sha256": "fd9e0aa6dd3b902df7e7cc069919266b2dc4487b521f5ee23618e40921dbdfd2",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
     "precision": "fp64",
     "bytes_per_launch": {"p2qbxl": 8.10322e+09, "m2l": 1.40428e+10, "m2qbxl": 9.26699e+07,

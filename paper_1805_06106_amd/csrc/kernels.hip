@@ -565,13 +565,13 @@ __global__ __launch_bounds__(64) void k_p2qbxl(const int* __restrict__ it_box,
 }
 
 // ------------------------------------------------------------------------------------
-// M2QBXL and L2QBXL: one thread per center.  The box expansion is rescaled to its
-// physical (unscaled) form and expanded to all signed orders in a zero-padded LDS table of
-// complex pairs; the solid harmonics of the center offset are generated column by column
-// (fixed order M, increasing degree N) and each value is scattered into the order-Q
-// outputs it feeds.  Table addresses are a per-(M, N) base plus a compile-time offset per
-// output (j, k); entries outside |m| <= n <= P read zeros, so the inner body is
-// branch-free apart from one uniform degree check per j.
+// M2QBXL and L2QBXL: one lane per center in each wave of an item.  The box expansion is
+// rescaled to its physical form and expanded to all signed orders in a zero-padded LDS table
+// of complex pairs; the solid harmonics of the center offset are generated column by column
+// (fixed order M, increasing degree N; the orders are dealt to the waves) and each value is
+// scattered into the order-Q outputs it feeds.  Table addresses are a per-(M, N) base plus a
+// compile-time offset per output (j, k); entries outside |m| <= n <= P read zeros, so the
+// inner body is branch-free apart from one uniform degree check per j.
 // ------------------------------------------------------------------------------------
 
 // M2QBXL: l_j^k(c) = sum_{n,m} [(-1)^n mu_n^m] [(-1)^N J_N^{m+k}(c - x_d)], N = n + j
