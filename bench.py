@@ -106,10 +106,13 @@ def main():
                     help="first run one plain elementwise copy (y = -x) over 1 GiB, so that a "
                          "hardware-counter pass can scale its byte counters by a kernel of "
                          "known traffic")
-    ap.add_argument("--wfar-direct-max", type=int, default=64,
+    ap.add_argument("--wfar-direct-max", type=int, default=None,
                     help="Remark 4: List 3 far boxes with at most this many sources are "
-                         "evaluated directly (0 disables); 64 with the level-restricted tree "
-                         "(128 without it) is the measured optimum here")
+                         "evaluated directly (0 disables). Default: 64 for the urchin "
+                         "workloads (the measured optimum for D 5/15 on the level-restricted "
+                         "tree; 128 without it); for c1 and c4 the cost-model crossover, the "
+                         "flops of one M2QBXL pair over those of one direct pair (89 at S "
+                         "3/10, 335 at S 8/20)")
     ap.add_argument("--level-restrict", type=int, choices=[0, 1], default=1,
                     help="1 (default): level-restricted tree, adjacent leaves differ by at most "
                          "one level (the remark on List 3 complexity); 0: the adaptive tree as "
@@ -141,6 +144,18 @@ def main():
 
     from paper_1805_06106_amd import Plan
     from paper_1805_06106_amd import costmodel as CM
+
+    if args.wfar_direct_max is None:
+        # Remark 4's crossover: a W-far box of n sources is cheaper to evaluate directly
+        # than through its multipole while n is below the flops of one (box, center) M2QBXL
+        # pair over those of one direct (source, center) pair (72 at D 5/15, where 64 was
+        # measured best on the urchin)
+        orders = {"c1": (10, 3, "S"), "c4": (20, 8, "S")}
+        if args.workload in orders and args.study is None:
+            p, q, k = orders[args.workload]
+            args.wfar_direct_max = round(CM.m2qbxl_pair(p, q) / CM.p2qbxl_pair(q, k))
+        else:
+            args.wfar_direct_max = 64
 
     if args.study == "scaling":
         return study_scaling(args)
