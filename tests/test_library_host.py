@@ -247,6 +247,18 @@ def test_batch_and_graph_validation(gq):
     assert "exclusive" in str(e.value)
 
 
+def test_default_translation_tile_widths(gq):
+    """Without autotuning: 32-pair M2L tiles for FP64 and plain FP32, 64 for split FP32 (its
+    three products per tile), 32 for the rotation M2L; XCD-aware tile order throughout."""
+    w = workload_tiny(level=1, order=2, kernel="D", p_qbx=3, p_fmm=6, nmax=32)
+    G = gq
+    for prec, cols in (("fp64", 32), ("fp32", 32), ("fp32_split", 64)):
+        st = G.Plan(**_args(w, precision=prec)).stats()
+        assert (st["m2l_tile_cols"], st["m2l_xcd_order"]) == (cols, True), prec
+    st = G.Plan(**_args(w, m2l_rotation=True)).stats()
+    assert st["m2l_tile_cols"] == 32
+
+
 def test_overlap_setting_validation(gq):
     w = workload_tiny(level=0, order=2, kernel="D", p_qbx=2, p_fmm=4, nmax=16)
     G = gq
