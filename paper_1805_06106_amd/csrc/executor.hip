@@ -101,7 +101,8 @@ struct gq_plan {
   std::vector<int> k3_box, k3_c0, k3_nc;
   std::vector<int> wf_box;
   std::vector<int> k5_c0, k5_nc, k5_w0, k5_w1;
-  std::vector<int> k8_box, k8_c0, k8_nc;
+  std::vector<int> k8_box, k8_c0, k8_nc;  // single items, then pairs (pair_center_items)
+  int k8_nsingle = 0, k8_npair = 0;
   // conventional targets (no QBX center), in tree order grouped by owning box
   int64_t n_pt = 0, n_qt = 0;             // point targets, QBX targets
   std::vector<int64_t> pt_count_box;      // per box: point targets owned
@@ -293,6 +294,37 @@ void near_center_items(const gq::Tree& T, int b, std::vector<int>& box, std::vec
 
 // Near-field items, most expensive first (passes over the near sources times slice length),
 // so that the longest workgroups start early.
+// Stage 8 items of at most 32 centers go two to a wave, one per half-wave: the arrays hold
+// the single items first, then the pairs as consecutive entries.  Rebuilds the order from
+// any input order (a batch re-pairs its members' items).
+void pair_center_items(gq_plan* P) {
+  std::vector<int> box, c0, nc, sb, sc, sn;
+  for (size_t i = 0; i < P->k8_box.size(); ++i) {
+    auto& b = P->k8_nc[i] <= 32 ? sb : box;
+    auto& c = P->k8_nc[i] <= 32 ? sc : c0;
+    auto& n = P->k8_nc[i] <= 32 ? sn : nc;
+    b.push_back(P->k8_box[i]);
+    c.push_back(P->k8_c0[i]);
+    n.push_back(P->k8_nc[i]);
+  }
+  if (sb.size() % 2) {  // the odd one out runs as a single item
+    box.push_back(sb.back());
+    c0.push_back(sc.back());
+    nc.push_back(sn.back());
+    sb.pop_back();
+    sc.pop_back();
+    sn.pop_back();
+  }
+  P->k8_nsingle = (int)box.size();
+  P->k8_npair = (int)(sb.size() / 2);
+  box.insert(box.end(), sb.begin(), sb.end());
+  c0.insert(c0.end(), sc.begin(), sc.end());
+  nc.insert(nc.end(), sn.begin(), sn.end());
+  P->k8_box.swap(box);
+  P->k8_c0.swap(c0);
+  P->k8_nc.swap(nc);
+}
+
 void sort_near_items(gq_plan* P) {
   const size_t n = P->k3_box.size();
   std::vector<size_t> ord(n);
@@ -462,6 +494,7 @@ gq_status build_work(gq_plan* P) {
     P->near_ptr[b + 1] = (int64_t)P->near_idx.size();
   }
   sort_near_items(P);
+  pair_center_items(P);
   P->stats.m2l_classes = (int64_t)cls_keys.size();
   // statistics
   gq_stats_t& S = P->stats;
@@ -808,6 +841,7 @@ gq_status merge_plans(gq_plan* B, gq_plan* const* plans, int n) {
   B->m2l_cols = default_m2l_cols(B->prm);
   make_tiles(m2l, B->m2l, B->m2l_cols);
   sort_near_items(B);
+  pair_center_items(B);
   return GQ_OK;
 }
 
@@ -1293,8 +1327,11 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     gq::launch_m2p(s, p, (int)P->pm_t0.size(), P->d_pm_t0, P->d_pm_nt, P->d_pm_w0, P->d_pm_w1,
                    P->d_wf_box, P->bctr, P->bh, P->M, P->px, P->py, P->pz, P->phi);
     GQ_TRY(mark(9, s));
-    gq::launch_l2qbxl(s, p, qo, (int)P->k8_box.size(), P->d_k8_box, P->d_k8_c0, P->d_k8_nc,
-                      P->bctr, P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
+    gq::launch_l2qbxl(s, p, qo, P->k8_nsingle, P->d_k8_box, P->d_k8_c0, P->d_k8_nc, P->bctr,
+                      P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
+    gq::launch_l2qbxl_pairs(s, p, qo, P->k8_npair, P->d_k8_box + P->k8_nsingle,
+                            P->d_k8_c0 + P->k8_nsingle, P->d_k8_nc + P->k8_nsingle, P->bctr,
+                            P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
     GQ_TRY(mark(10, s));
     if (sprime)
       gq::launch_qbxl2p_grad(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->tnx, P->tny,

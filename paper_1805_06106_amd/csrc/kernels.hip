@@ -760,8 +760,11 @@ __global__ __launch_bounds__(64 * NW, Q <= 5 ? 3 : 1) void k_m2qbxl(int P, const
     for (int i = 0; i < NQ; ++i) unsafeAtomicAdd(&Lq[(int64_t)i * nctr + c], acc[i]);
 }
 
-template <int Q, int NW = qbxl_waves(Q)>
-__global__ __launch_bounds__(64 * NW, Q <= 5 ? 4 : 1) void k_l2qbxl(int P, const int* __restrict__ it_box,
+// PAIR: the item is two consecutive entries of at most 32 centers each (of two boxes); the
+// lower half of every wave serves the first, the upper half the second, each with its own
+// table, so the order loop stays uniform over the wave.
+template <int Q, int NW = qbxl_waves(Q), bool PAIR = false>
+__global__ __launch_bounds__(64 * NW, Q <= 5 ? (PAIR ? 3 : 4) : 1) void k_l2qbxl(int P, const int* __restrict__ it_box,
                                                            const int* __restrict__ it_c0,
                                                            const int* __restrict__ it_nc,
                                                            const double* __restrict__ bctr,
@@ -774,22 +777,31 @@ __global__ __launch_bounds__(64 * NW, Q <= 5 ? 4 : 1) void k_l2qbxl(int P, const
                                                            int64_t nctr) {
   using TB = L2qTab<Q>;
   constexpr int NQ = (Q + 1) * (Q + 1);
-  __shared__ double2 tab[TB::ROWS * TB::W];
+  constexpr int NTAB = PAIR ? 2 : 1;
+  constexpr int TSZ = TB::ROWS * TB::W;
+  __shared__ double2 tab[NTAB * TSZ];
   __shared__ double invtab[kInvTab * kInvTab];
-  for (int i = threadIdx.x; i < TB::ROWS * TB::W; i += blockDim.x) tab[i] = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < NTAB * TSZ; i += blockDim.x) tab[i] = make_double2(0.0, 0.0);
   fill_invtab(invtab);
   const int item = blockIdx.x;
-  const int b = it_box[item];
-  const int c0 = it_c0[item], nc = it_nc[item];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const bool active = lane < nc;
-  const int64_t c = (int64_t)c0 + (active ? lane : 0);
+  const int sub = PAIR ? lane >> 5 : 0;        // entry of the pair this lane serves
+  const int li = PAIR ? lane & 31 : lane;      // its center within the entry
+  const int e = PAIR ? 2 * item + sub : item;
+  const int b = it_box[e];
+  const int c0 = it_c0[e], nc = it_nc[e];
+  const bool active = li < nc;
+  const int64_t c = (int64_t)c0 + (active ? li : 0);
   const int np = (P + 1) * (P + 1);
-  const double a = bh[b];
   __syncthreads();
-  fill_padded(L + (int64_t)b * np, P, tab, 0, TB::W, TB::MOFF,
-              [a](int n) { return pow(a, -(double)(n + 1)); });
+  for (int k = 0; k < NTAB; ++k) {
+    const int bk = it_box[PAIR ? 2 * item + k : item];
+    const double a = bh[bk];
+    fill_padded(L + (int64_t)bk * np, P, tab + k * TSZ, 0, TB::W, TB::MOFF,
+                [a](int n) { return pow(a, -(double)(n + 1)); });
+  }
   __syncthreads();
+  const double2* tb = tab + sub * TSZ;  // this lane's table
   const double vx = cx[c] - bctr[3 * b], vy = cy[c] - bctr[3 * b + 1], vz = cz[c] - bctr[3 * b + 2];
   const double r2 = vx * vx + vy * vy + vz * vz;
   double acc[NQ];
@@ -822,8 +834,8 @@ __global__ __launch_bounds__(64 * NW, Q <= 5 ? 4 : 1) void k_l2qbxl(int P, const
       p1r = rr;
       p1i = ri;
       const double rnr = sgn * rr, rni = -sgn * ri;  // R^{-mu} = (-1)^mu conj(R^mu)
-      const double2* t1 = tab + (N * TB::W + mu + TB::MOFF);
-      const double2* t2 = tab + (N * TB::W - mu + TB::MOFF);
+      const double2* t1 = tb + (N * TB::W + mu + TB::MOFF);
+      const double2* t2 = tb + (N * TB::W - mu + TB::MOFF);
 #pragma unroll
       for (int j = 0; j <= Q; ++j) {
         const int n = N + j;
@@ -1054,6 +1066,17 @@ struct L2qbxlGo {
 };
 
 template <int Q>
+struct L2qbxlPairGo {
+  static void go(hipStream_t s, int p, int nitem, const int* it_box, const int* it_c0,
+                 const int* it_nc, const double* bctr, const double* bh, const double* L,
+                 const double* cx, const double* cy, const double* cz, double* Lq,
+                 int64_t nctr) {
+    k_l2qbxl<Q, qbxl_waves(Q), true><<<nitem, 64 * qbxl_waves(Q), 0, s>>>(
+        p, it_box, it_c0, it_nc, bctr, bh, L, cx, cy, cz, Lq, nctr);
+  }
+};
+
+template <int Q>
 struct Qbxl2pGradGo {
   static void go(hipStream_t s, int64_t ntgt, const int64_t* tgt_ctr, const double* tx,
                  const double* ty, const double* tz, const double* tnx, const double* tny,
@@ -1155,6 +1178,15 @@ void launch_l2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
   if (nitem <= 0) return;
   QDispatch<L2qbxlGo>::run(q, s, p, nitem, it_box, it_c0, it_nc, bctr, bh, L, cx, cy, cz, Lq,
                            nctr);
+}
+
+void launch_l2qbxl_pairs(hipStream_t s, int p, int q, int npair, const int* it_box,
+                         const int* it_c0, const int* it_nc, const double* bctr,
+                         const double* bh, const double* L, const double* cx, const double* cy,
+                         const double* cz, double* Lq, int64_t nctr) {
+  if (npair <= 0) return;
+  QDispatch<L2qbxlPairGo>::run(q, s, p, npair, it_box, it_c0, it_nc, bctr, bh, L, cx, cy, cz,
+                               Lq, nctr);
 }
 
 void launch_qbxl2p(hipStream_t s, int q, int64_t ntgt, const int64_t* tgt_ctr,

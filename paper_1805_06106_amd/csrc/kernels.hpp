@@ -123,6 +123,13 @@ void launch_l2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_box,
                    const double* L, const double* cx, const double* cy, const double* cz,
                    double* Lq, int64_t nctr);
 
+// Stage 8 for pairs of items: item i is entries 2i and 2i+1 of the arrays, each of at most
+// 32 centers (of one box each); one wave serves both.
+void launch_l2qbxl_pairs(hipStream_t s, int p, int q, int npair, const int* it_box,
+                         const int* it_c0, const int* it_nc, const double* bctr,
+                         const double* bh, const double* L, const double* cx, const double* cy,
+                         const double* cz, double* Lq, int64_t nctr);
+
 // Conventional targets (kernels_pt.hip), point targets in tree order, phi accumulates:
 // Stages 3, 5a, 6a: direct sums from the box's near sources.  Item i: box it_box[i],
 // point targets [it_t0[i], it_t0[i] + it_nt[i]) (at most 64).
