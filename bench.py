@@ -32,11 +32,11 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "fd9e0aa6dd3b902df7e7cc069919266b2dc4487b521f5ee23618e40921dbdfd2",
+    "kernels_sha256": "842cae395184d928ff85af239e7e1c5547c5b6fc763143ced1e0487ca1526e35",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 8.10322e+09, "m2l": 1.40428e+10, "m2qbxl": 9.26699e+07,
-                         "l2qbxl": 9.62256e+08},
+    "bytes_per_launch": {"p2qbxl": 8.09767e+09, "m2l": 1.40425e+10, "m2qbxl": 9.26699e+07,
+                         "l2qbxl": 9.46716e+08},
 }
 
 
