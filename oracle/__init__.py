@@ -32,11 +32,19 @@ _lib = None
 KERNELS = {"S": 0, "D": 1}
 
 
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
+if os.environ.get("ORACLE_SANITIZED"):
+    # a process started with gcc's ASan runtime preloaded uses the sanitized build
+    _LIB = _SAN_LIB
+
+
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (plain C11 + OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+        san = (["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-g"]
+               if _LIB == _SAN_LIB else [])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", *san,
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -220,6 +228,24 @@ def direct_qbx_sprime(p_qbx, src, strength, ctr, tgt, tgt_center, tgt_normal, nt
                                              tgt[i], tn[i]) for i in range(tgt.shape[0])])
 
 
+def source_density(w):
+    """Density at the sources, shape (n_densities, N_S): the workload's density itself, or,
+    with an oversampled quadrature (Section 3: the density lives on the nodes of each
+    element and the potential uses a finer quadrature on the same element), each
+    element's node values mapped to its quadrature nodes by the interpolation matrix."""
+    if getattr(w, "interp", None) is None:
+        return w.density
+    nd = w.density.shape[0]
+    nodes = w.density.reshape(nd, w.n_elem, w.interp.shape[1])
+    return np.einsum("dek,jk->dej", nodes, w.interp).reshape(nd, -1)
+
+
+def strengths(w):
+    """Quadrature strengths q_j = w_j mu_j at the sources (the discretized layer potential
+    of Section 2.3), shape (n_densities, N_S)."""
+    return source_density(w) * w.src_w[None, :]
+
+
 def direct_qbx_sampled(w, center_ids, density_index=0, nthreads=0):
     """Tier A on a subset of centers of a workload: returns (target ids, potentials)."""
     center_ids = np.asarray(center_ids, dtype=np.int64)
@@ -227,7 +253,7 @@ def direct_qbx_sampled(w, center_ids, density_index=0, nthreads=0):
     tids = np.nonzero(tmask)[0]
     remap = {int(c): i for i, c in enumerate(center_ids)}
     tc = np.array([remap[int(c)] for c in w.tgt_center[tids]], dtype=np.int64)
-    pot, used = direct_qbx(w.kernel, w.p_qbx, w.src_xyz, w.strengths()[density_index],
+    pot, used = direct_qbx(w.kernel, w.p_qbx, w.src_xyz, strengths(w)[density_index],
                            w.ctr_xyz[center_ids], w.tgt_xyz[tids], tc,
                            nrm=w.src_normal, nthreads=nthreads)
     return tids, pot, used

@@ -53,7 +53,7 @@ import math
 
 import numpy as np
 
-from . import KERNELS, _f64, _i64, _p, eval_local, eval_mpole, lib, ncoef
+from . import KERNELS, _f64, _i64, _p, eval_local, eval_mpole, lib, ncoef, strengths
 from . import m2l as _m2l_one
 
 SQRT3 = math.sqrt(3.0)
@@ -518,7 +518,7 @@ class OracleFMM:
         t, L, w = self.tree, self.lists, self.w
         p, q = self.p, self.q
         kern = KERNELS[self.kernel]
-        strength = _f64(w.strengths()[density_index])
+        strength = _f64(strengths(w)[density_index])
         self._mpole = {}
         centers = np.arange(w.n_ctr) if centers is None else np.asarray(centers, dtype=np.int64)
         owners = sorted(set(int(t.ctr_owner[c]) for c in centers))
@@ -640,7 +640,7 @@ class OracleFMM:
         t, L, w = self.tree, self.lists, self.w
         p = self.p
         kern = KERNELS[self.kernel]
-        strength = _f64(w.strengths()[density_index])
+        strength = _f64(strengths(w)[density_index])
         conv = np.nonzero(w.tgt_center < 0)[0]
         tids = conv if targets is None else np.intersect1d(conv, np.asarray(targets))
         owner = self.point_target_owner()

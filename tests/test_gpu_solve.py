@@ -51,9 +51,9 @@ def test_oversampled_parity(kernel):
           flush=True)
     P = Plan.from_workload(w, n_densities=2)
     pot = P.apply(torch.tensor(w.density, device=dev)).cpu().numpy()
-    F = Plan.from_workload(dataclasses.replace(w, interp=None, density=w.source_density()),
+    F = Plan.from_workload(dataclasses.replace(w, interp=None, density=O.source_density(w)),
                            n_densities=2)
-    pot_f = F.apply(torch.tensor(w.source_density(), device=dev)).cpu().numpy()
+    pot_f = F.apply(torch.tensor(O.source_density(w), device=dev)).cpu().numpy()
     for d in range(2):
         assert rel(pot[d], pot_f[d]) < 1e-12
         tids, ref, _ = OracleFMM(w).evaluate(density_index=d)
@@ -114,7 +114,7 @@ def test_interior_dirichlet_solve():
     assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(g_np)
     # the same solution in the unaccelerated discrete system: residual at the level of the
     # acceleration error (Theorem 1 bound at p_fmm = 15 is far above what is observed)
-    q = (dataclasses.replace(w, density=mu_np[None])).strengths()[0]
+    q = O.strengths(dataclasses.replace(w, density=mu_np[None]))[0]
     direct, _ = O.direct_qbx("D", w.p_qbx, w.src_xyz, q, w.ctr_xyz, w.tgt_xyz, w.tgt_center,
                              nrm=w.src_normal)
     assert np.linalg.norm(g_np - direct) <= 1e-6 * np.linalg.norm(g_np)

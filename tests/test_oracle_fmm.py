@@ -37,7 +37,7 @@ def fmm(request):
 
 
 def _tier_a(w):
-    pot, _ = O.direct_qbx(w.kernel, w.p_qbx, w.src_xyz, w.strengths()[0], w.ctr_xyz, w.tgt_xyz,
+    pot, _ = O.direct_qbx(w.kernel, w.p_qbx, w.src_xyz, O.strengths(w)[0], w.ctr_xyz, w.tgt_xyz,
                           w.tgt_center, nrm=w.src_normal)
     return pot
 
@@ -210,7 +210,7 @@ def test_linf_prec_tcr_is_the_box_distance():
 
 def _point_direct(w, tids, d=0):
     x = w.tgt_xyz[tids]
-    pot, _ = O.direct_qbx(w.kernel, 0, w.src_xyz, w.strengths()[d], x, x,
+    pot, _ = O.direct_qbx(w.kernel, 0, w.src_xyz, O.strengths(w)[d], x, x,
                           np.arange(len(tids)), nrm=w.src_normal)
     return pot
 

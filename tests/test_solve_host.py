@@ -105,9 +105,9 @@ def test_oversampling_sharpens_gauss_law():
                               sides="interior", node_order=4, quad_order=4, sub=4)
     ws.density = np.ones_like(ws.density)
     inner = np.arange(1, w0.n_ctr, 2)
-    pot0, _ = O.direct_qbx("D", 5, w0.src_xyz, w0.strengths()[0], w0.ctr_xyz, w0.tgt_xyz[inner],
+    pot0, _ = O.direct_qbx("D", 5, w0.src_xyz, O.strengths(w0)[0], w0.ctr_xyz, w0.tgt_xyz[inner],
                            inner, nrm=w0.src_normal)
-    pots, _ = O.direct_qbx("D", 5, ws.src_xyz, ws.strengths()[0], ws.ctr_xyz, ws.tgt_xyz,
+    pots, _ = O.direct_qbx("D", 5, ws.src_xyz, O.strengths(ws)[0], ws.ctr_xyz, ws.tgt_xyz,
                            ws.tgt_center, nrm=ws.src_normal)
     e0 = np.max(np.abs(pot0 + 1.0))
     es = np.max(np.abs(pots + 1.0))

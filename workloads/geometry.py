@@ -251,19 +251,6 @@ class Workload:
     def n_tgt(self):
         return self.tgt_xyz.shape[0]
 
-    def source_density(self):
-        """Density at the sources, shape (n_densities, N_S): `density` itself, or with an
-        oversampled quadrature each element's node values mapped by `interp`."""
-        if self.interp is None:
-            return self.density
-        nd = self.density.shape[0]
-        nodes = self.density.reshape(nd, self.n_elem, self.interp.shape[1])
-        return np.einsum("dek,jk->dej", nodes, self.interp).reshape(nd, -1)
-
-    def strengths(self):
-        """q = w * mu at the sources, shape (n_densities, N_S)."""
-        return self.source_density() * self.src_w[None, :]
-
 
 def _nodes(level: int, order: int, spec: SurfaceSpec):
     verts, faces = icosphere(level)
