@@ -41,9 +41,12 @@ COUNTER_TRAFFIC = {
 
 
 def tree_opts(args):
-    """Plan options that shape the tree and lists: Remark 4's threshold and level
-    restriction."""
-    return {"wfar_direct_max": args.wfar_direct_max, "level_restrict": bool(args.level_restrict)}
+    """Plan options that shape the tree and lists: Remark 4's threshold, level restriction
+    and (when given) nmax, the most particles a box holds before it is split."""
+    opts = {"wfar_direct_max": args.wfar_direct_max, "level_restrict": bool(args.level_restrict)}
+    if getattr(args, "nmax", None):
+        opts["nmax"] = args.nmax
+    return opts
 
 
 def counter_traffic(kernel, workload, wfar_direct_max, level_restrict):
@@ -97,6 +100,11 @@ def main():
                     help="--study solve: icosphere level of the urchin's elements")
     ap.add_argument("--surfaces", type=int, default=8,
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
+    ap.add_argument("--nmax", type=int, default=None,
+                    help="override the workload's nmax (512, the paper's choice, by default)")
+    ap.add_argument("--c3-direct", type=int, default=0,
+                    help="c3 only: random centers per surface checked against the direct QBX "
+                         "oracle, every density (0: none)")
     ap.add_argument("--cpu-sample", type=int, default=768,
                     help="centers evaluated by the CPU oracle (direct QBX) for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -271,26 +279,38 @@ def main():
         m2l["frac_of_fp64_mfma_peak_alone"] = round(
             flops["m2l"] / (alone["stage_ms"]["m2l"] * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS, 4)
 
-    # split-precision translations (FP32 matrix cores), with and without the hi/lo correction
+    # FP32 matrix-core translations: split (leading degrees in FP64, hi/lo correction
+    # products with FP64 accumulation per K-step), leading degrees only, and uncorrected
     m2l_gemm_flops = flops["m2l"]
     split = {}
     if not args.no_fp32:
         p64 = pot[0].clone()
-        for prec, products in (("fp32_split", 3), ("fp32", 1)):
+        npc = (w.p_fmm + 1) ** 2
+        lead = min(16, npc)
+        for prec in ("fp32_split", "fp32_lead", "fp32"):
             ms_p, sm_p, _, _, pot_p, alone_p = run(prec)
             if alone_p:
                 sm_p = alone_p["stage_ms"]  # the M2L kernel's own time
             err = float((pot_p[0] - p64).abs().max() / p64.abs().max())
             m2l_ms = sm_p["m2l"]
             eff = m2l_gemm_flops / (m2l_ms * 1e-3) / 1e12
+            # executed matrix-core work: FP32 products over the trailing columns, FP64 over
+            # the leading ones
+            tail = (npc - lead) / npc if prec != "fp32" else 1.0
+            products = 3 if prec == "fp32_split" else 1
+            f32_tf = eff * tail * products
+            f64_tf = eff * (1.0 - tail)
             split[prec] = {
                 "value": round(w.n_tgt / (ms_p * 1e-3), 1), "ms_per_step": round(ms_p, 4),
                 "rel_err_vs_fp64_path": err,
                 "ms_per_step_one_stream": round(alone_p["ms_per_step"], 4) if alone_p else None,
-                "m2l": {"ms": round(m2l_ms, 4), "mfma_products": products,
-                        "executed_tflops": round(eff * products, 3),
+                "m2l": {"ms": round(m2l_ms, 4), "fp32_products_per_trailing_column": products,
+                        "leading_fp64_columns": lead if prec != "fp32" else 0,
+                        "executed_fp32_tflops": round(f32_tf, 3),
+                        "executed_fp64_tflops": round(f64_tf, 3),
                         "effective_tflops": round(eff, 3),
-                        "frac_of_fp32_mfma_peak": round(eff * products / PEAK_FP32_MFMA_TFLOPS, 4)},
+                        "frac_of_mfma_peak": round(f32_tf / PEAK_FP32_MFMA_TFLOPS
+                                                   + f64_tf / PEAK_FP64_VALU_TFLOPS, 4)},
                 ("stage_ms_one_stream" if alone_p else "stage_ms"):
                     {s: round(v, 4) for s, v in sm_p.items()},
             }
@@ -331,7 +351,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "kernel": w.kernel, "p_qbx": w.p_qbx, "p_fmm": w.p_fmm,
                    "n_sources": w.n_src, "n_centers": w.n_ctr, "n_targets": w.n_tgt,
-                   "nmax": w.nmax, "tcf": w.tcf, "n_densities": 1, "precision": "fp64",
+                   "nmax": args.nmax or w.nmax, "tcf": w.tcf, "n_densities": 1, "precision": "fp64",
                    "wfar_direct_max": args.wfar_direct_max,
                    "level_restrict": bool(args.level_restrict),
                    "m2l_rotation": bool(args.m2l_rotation),
@@ -358,25 +378,32 @@ def main():
 def study_greens(args, dev):
     """Green's formula on the urchin (the accuracy experiment of Section 6.1): for u the
     potential of a unit charge at (3, 1, 2), outside the surface, u = S(du/dn) - D(u) holds
-    inside, so at every node x, evaluated through its interior center,
+    inside, so at every density node x, evaluated through its interior center,
         E(x) = S(du/dn)(x) - D(u)(x) - u(x)
-    vanishes up to the discretization, truncation and acceleration errors.  Reported:
-    max |E| / max |u| for each p_fmm x p_qbx (p_qbx <= p_fmm), beside the a-priori factor
-    (3/4)^(p_fmm + 1) of the acceleration error."""
+    vanishes up to the discretization, truncation and acceleration errors.  The surface is
+    discretized as the paper's stage-2 pair: u and du/dn live on 45 nodes per element
+    (degree 8) and the layer potentials use an oversampled quadrature on the same elements
+    (the degree-8 collapsed rule on each of 64 sub-triangles).  Reported: max |E| / max |u|
+    for each p_fmm x p_qbx (p_qbx <= p_fmm), beside the a-priori factor (3/4)^(p_fmm + 1)
+    of the acceleration error."""
     import numpy as np
     import torch
 
     from paper_1805_06106_amd import Plan
-    from workloads import workload_c2
+    from workloads import oversampled_workload
+    from workloads.geometry import SurfaceSpec
 
-    w = workload_c2()
+    spec = SurfaceSpec(curved=True, bump_k=8, bump_m=4, bump_a=0.2)
     x0 = np.array([3.0, 1.0, 2.0])
-    d = w.src_xyz - x0
+    t0 = time.time()
+    w = oversampled_workload(f"urchin8-{20 * 4 ** args.level}-stage2", level=args.level,
+                             spec=spec, kernel="S", p_qbx=3, p_fmm=3, node_order=8,
+                             quad_order=8, sub=8, sides="interior")
+    d = w.node_xyz - x0
     r = np.linalg.norm(d, axis=1)
     u = 1.0 / r
-    dudn = -np.sum(d * w.src_normal, axis=1) / r ** 3
-    interior = np.arange(1, w.n_tgt, 2)  # targets through the centers x - r n
-    utgt = u[interior // 2]
+    dens = {"D": u, "S": -np.sum(d * w.node_normal, axis=1) / r ** 3}
+    log(f"{w.name}: {w.n_src} sources, {w.n_ctr} nodes ({time.time() - t0:.1f}s)")
     rows = []
     for p_fmm in (3, 5, 10, 15, 20):
         for p_qbx in (3, 5, 7, 9):
@@ -384,18 +411,21 @@ def study_greens(args, dev):
                 continue
             t0 = time.time()
             pots = {}
-            for kern, dens in (("S", dudn), ("D", u)):
-                P = Plan.from_workload(w, kernel=kern, p_fmm=p_fmm, p_qbx=p_qbx,
+            for kern in ("S", "D"):
+                P = Plan.from_workload(w, kernel=kern, p_qbx=p_qbx, p_fmm=p_fmm,
                                        **tree_opts(args))
-                pots[kern] = P.apply(torch.tensor(dens[None, :], device=dev))[0].cpu().numpy()
+                pots[kern] = P.apply(torch.tensor(dens[kern][None, :],
+                                                  device=dev))[0].cpu().numpy()
                 P.close()
-            E = pots["S"][interior] - pots["D"][interior] - utgt
-            err = float(np.max(np.abs(E)) / np.max(np.abs(utgt)))
+            meta = (w.name, w.n_src, w.n_ctr)
+            E = pots["S"] - pots["D"] - u
+            err = float(np.max(np.abs(E)) / np.max(np.abs(u)))
             rows.append({"p_fmm": p_fmm, "p_qbx": p_qbx, "rel_err": err,
                          "bound_factor": 0.75 ** (p_fmm + 1)})
             log(f"p_fmm={p_fmm:2d} p_qbx={p_qbx}: {err:.3e}  ({time.time() - t0:.1f}s)")
-    print(json.dumps({"study": "greens_formula", "workload": w.name, "charge": x0.tolist(),
-                      "nmax": w.nmax, "tcf": w.tcf, "wfar_direct_max": args.wfar_direct_max,
+    print(json.dumps({"study": "greens_formula", "workload": meta[0], "n_sources": meta[1],
+                      "n_targets": meta[2], "charge": x0.tolist(), "nmax": args.nmax or 512,
+                      "tcf": 0.9, "wfar_direct_max": args.wfar_direct_max,
                       "level_restrict": bool(args.level_restrict), "rows": rows}), flush=True)
 
 
@@ -421,8 +451,12 @@ def study_scaling(args):
         plan_s = time.time() - t0
         st = P.stats()
         model = CM.paper_list_model(st, w.p_fmm, w.p_qbx)
+        # the lists do not depend on the orders: the same plan gives the (9, 20) model
+        model_hi = CM.paper_list_model(st, 20, 9)
         row = {"k": k, "level": level, "n_sources": w.n_src, "n_boxes": st["n_boxes"],
                "model": model, "model_per_source": model["total_lists"] / w.n_src,
+               "model_q9_p20": model_hi,
+               "model_q9_p20_per_source": model_hi["total_lists"] / w.n_src,
                "plan_seconds": round(plan_s, 2)}
         if gpu:
             d = torch.ones((1, w.n_src), dtype=torch.float64, device="cuda:0")
@@ -440,7 +474,7 @@ def study_scaling(args):
         rows.append(row)
         log(f"k={k} level={level}: N_S={w.n_src}, modeled {model['total_lists']:.3e} "
             f"({row['model_per_source']:.3e}/source)" + (f", {row['ms_per_apply']} ms" if gpu else ""))
-    print(json.dumps({"study": "cost_scaling", "p_fmm": 15, "p_qbx": 5, "kernel": "S",
+    print(json.dumps({"study": "cost_scaling", "orders": [[5, 15], [9, 20]], "kernel": "S",
                       "rows": rows}), flush=True)
 
 
@@ -630,24 +664,47 @@ def study_solve(args, dev):
                       "plan_seconds": round(plan_s, 3), "interior_rel_err": err}), flush=True)
 
 
+def c3_workloads(count):
+    """The first `count` surfaces of the 64-urchin batch, generated by up to 16 worker
+    processes (spawned, so that none inherits the parent's GPU state)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    from workloads import workload_c3
+
+    if count <= 2:
+        return [workload_c3(i) for i in range(count)]
+    # largest surfaces first, so that the pool ends evenly
+    from workloads.geometry import c3_surface_params
+    order = sorted(range(count), key=lambda i: -c3_surface_params(i)[3])
+    with ProcessPoolExecutor(max_workers=min(16, count),
+                             mp_context=mp.get_context("spawn")) as ex:
+        made = dict(zip(order, ex.map(workload_c3, order)))
+    return [made[i] for i in range(count)]
+
+
 def bench_batch(args, dev):
     """Many surfaces with 8 densities each: plain FP64 (one plan per surface, applied one
-    after another) against one batch plan (FP32 split translations, HIP graph, autotuned
-    M2L), and the batch plan in FP64 for reference."""
+    after another) against one batch plan per precision mode (HIP graph, autotuned M2L).
+    Member plans are released once their batch exists, so at most one precision's members
+    and batch are held at a time.  The stated error is measured against the plain FP64
+    potentials on every target and against the direct (unaccelerated) QBX oracle on a
+    sample of targets of every surface and every density."""
     import numpy as np
     import torch
 
     from paper_1805_06106_amd import Plan
-    from workloads import workload_c3
 
     t0 = time.time()
-    ws = [workload_c3(i) for i in range(args.surfaces)]
+    ws = c3_workloads(args.surfaces)
     nd = ws[0].density.shape[0]
     n_tgt = sum(w.n_tgt for w in ws)
     n_src = sum(w.n_src for w in ws)
     log(f"batch workload: {len(ws)} surfaces, {n_src} sources, {n_tgt} targets, {nd} densities "
         f"({time.time() - t0:.1f}s)")
-    dens = [torch.tensor(w.density, device=dev) for w in ws]
+    dall = torch.cat([torch.tensor(w.density) for w in ws], dim=1).to(dev).contiguous()
+    offs_s = np.cumsum([0] + [w.n_src for w in ws])
+    offs_t = np.cumsum([0] + [w.n_tgt for w in ws])
 
     def timed(fn, k):
         for _ in range(args.warmup):
@@ -659,31 +716,34 @@ def bench_batch(args, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3 / k
 
-    # plain FP64: one plan per surface
+    # plain FP64: one plan per surface, applied one after another
     t0 = time.time()
-    plans = [Plan.from_workload(w, n_densities=nd, **tree_opts(args))
-             for w in ws]
+    plans = [Plan.from_workload(w, n_densities=nd, **tree_opts(args)) for w in ws]
     plan64_s = time.time() - t0
-    outs = [torch.empty((nd, w.n_tgt), dtype=torch.float64, device=dev) for w in ws]
+    ref = torch.empty((nd, n_tgt), dtype=torch.float64, device=dev)
+    dsl = [dall[:, offs_s[k]:offs_s[k + 1]].contiguous() for k in range(len(ws))]
+    osl = [torch.empty((nd, w.n_tgt), dtype=torch.float64, device=dev) for w in ws]
 
     def plain():
-        for P, d, o in zip(plans, dens, outs):
+        for P, d, o in zip(plans, dsl, osl):
             P.apply(d, o)
 
     ms_plain = timed(plain, args.steps)
-    ref = torch.cat(outs, dim=1)
-    log(f"plain fp64: {ms_plain:.2f} ms per batch apply")
-    dall = torch.cat(dens, dim=1).contiguous()
+    for k, o in enumerate(osl):
+        ref[:, offs_t[k]:offs_t[k + 1]] = o
+    del dsl, osl
+    log(f"plain fp64: {ms_plain:.2f} ms per batch apply ({plan64_s:.1f}s of plans)")
     res = {}
-    for prec in ("fp64", "fp32_split"):
+    pots = {}
+    for prec in ("fp64", "fp32_split", "fp32_lead"):
         t0 = time.time()
         members = plans if prec == "fp64" else [
-            Plan.from_workload(w, n_densities=nd, **tree_opts(args),
-                               precision=prec) for w in ws]
+            Plan.from_workload(w, n_densities=nd, **tree_opts(args), precision=prec)
+            for w in ws]
         B = Plan.batch(members, graph=True, autotune=True)
-        if prec != "fp64":
-            for P in members:
-                P.close()
+        for P in members:
+            P.close()
+        plans = []
         plan_s = time.time() - t0
         st = B.stats()
         out = torch.empty((nd, n_tgt), dtype=torch.float64, device=dev)
@@ -691,10 +751,40 @@ def bench_batch(args, dev):
         err = float((out - ref).abs().max() / ref.abs().max())
         res[prec] = {"value": round(nd * n_tgt / (ms * 1e-3), 1), "ms_per_apply": round(ms, 3),
                      "rel_err_vs_plain_fp64": err, "plan_seconds": round(plan_s, 2),
+                     "device_bytes": st["device_bytes"],
                      "m2l_tile_cols": st["m2l_tile_cols"], "m2l_xcd_order": st["m2l_xcd_order"],
                      "m2l_classes": st["m2l_classes"]}
         log(f"batched {prec} + graph: {ms:.2f} ms per apply, rel err vs plain fp64 {err:.3e}")
+        pots[prec] = out.cpu().numpy() if args.c3_direct > 0 else None
         B.close()
+        del out
+    direct = None
+    if args.c3_direct > 0:
+        import oracle as O
+
+        # Tier A: args.c3_direct random centers per surface, every density
+        t0 = time.time()
+        worst = {p: 0.0 for p in pots}
+        worst_plain = 0.0
+        refc = ref.cpu().numpy()
+        rng = np.random.default_rng(777)
+        for k, w in enumerate(ws):
+            cids = np.sort(rng.choice(w.n_ctr, args.c3_direct, replace=False))
+            for d in range(nd):
+                tids, dref, _ = O.direct_qbx_sampled(w, cids, density_index=d)
+                scale = np.max(np.abs(dref))
+                worst_plain = max(worst_plain, float(np.max(np.abs(
+                    refc[d, offs_t[k] + tids] - dref)) / scale))
+                for p, pot in pots.items():
+                    worst[p] = max(worst[p], float(np.max(np.abs(
+                        pot[d, offs_t[k] + tids] - dref)) / scale))
+            if k % 8 == 7:
+                log(f"direct QBX sample: {k + 1} of {len(ws)} surfaces ({time.time() - t0:.0f}s)")
+        direct = {"centers_per_surface": args.c3_direct, "densities": nd,
+                  "max_rel_err_plain_fp64": worst_plain,
+                  **{f"max_rel_err_batched_{p}": v for p, v in worst.items()},
+                  "seconds": round(time.time() - t0, 1)}
+        log(f"vs direct QBX (worst surface and density): {direct}")
     out = {
         "metric": "QBX-FMM target evals/sec, batched FP32-split translations (hipGraph) vs "
                   "plain FP64",
@@ -714,6 +804,8 @@ def bench_batch(args, dev):
                        "ms_per_apply": round(ms_plain, 3), "plan_seconds": round(plan64_s, 2)},
         "batched_fp64_graph": res["fp64"],
         "batched_fp32_split_graph": res["fp32_split"],
+        "batched_fp32_lead_graph": res["fp32_lead"],
+        "vs_direct_qbx": direct,
     }
     print(json.dumps(out), flush=True)
 

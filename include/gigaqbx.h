@@ -50,13 +50,23 @@ typedef enum {
    normals are given by gq_set_target_normals). */
 typedef enum { GQ_KERNEL_S = 0, GQ_KERNEL_D = 1, GQ_KERNEL_SP = 2 } gq_kernel;
 /* Arithmetic of the dense translations (M2M, M2L, L2L; Stages 2, 4, 7).  Every other
-   stage, the expansions in memory and the final potential are FP64 in all modes.
+   stage, the expansions in memory and the final potential are FP64 in all modes.  The FP32
+   modes work on balanced matrices: each degree n, order m coefficient is scaled by
+   N_n^m = sqrt((n+m)! (n-m)!) (multipoles) or 1 / N_n^m (locals), the Schmidt
+   semi-normalization of the solid harmonics, so that coefficients and matrix entries stay
+   O(1) and inside FP32's range up to p_fmm = 20.
    GQ_FP64        FP64 matrix cores.
-   GQ_FP32_SPLIT  FP32 matrix cores on T = T_hi + T_lo and x = x_hi + x_lo, adding the
-                  correction products T_hi x_lo + T_lo x_hi; FP32 accumulation, result
-                  added to the FP64 expansions.
-   GQ_FP32        as GQ_FP32_SPLIT without the correction products (T_hi x_hi only). */
-typedef enum { GQ_FP64 = 0, GQ_FP32_SPLIT = 1, GQ_FP32 = 2 } gq_precision;
+   GQ_FP32_SPLIT  split precision: the leading 16 packed coefficients of every input
+                  (degrees n <= 3, which carry most of each output's magnitude because the
+                  expansions decay with the degree) are contracted on the FP64 matrix cores;
+                  the rest on the FP32 matrix cores as T_hi x_hi + T_hi x_lo + T_lo x_hi
+                  (T = T_hi + T_lo, x = x_hi + x_lo), each K-step of 4 columns summed in
+                  FP32 from zero and added into FP64 accumulators.
+   GQ_FP32        uncorrected: T_hi x_hi over every column, FP32 accumulation over the
+                  whole contraction.
+   GQ_FP32_LEAD   the leading 16 coefficients on the FP64 matrix cores as in GQ_FP32_SPLIT,
+                  the rest T_hi x_hi with FP32 accumulation (no correction products). */
+typedef enum { GQ_FP64 = 0, GQ_FP32_SPLIT = 1, GQ_FP32 = 2, GQ_FP32_LEAD = 3 } gq_precision;
 
 /* gq_params.flags */
 #define GQ_FLAG_HOST_ONLY (1u << 0) /* plan on the host only: no device memory, no apply */
@@ -68,8 +78,7 @@ typedef enum { GQ_FP64 = 0, GQ_FP32_SPLIT = 1, GQ_FP32 = 2 } gq_precision;
 #define GQ_FLAG_GRAPH (1u << 2)
 /* At plan creation, time the Stage 4 (M2L) launch for tile widths 64 and 32 and for
    XCD-aware or plain tile order on the plan's own tiles, and keep the fastest (reported in
-   gq_stats_t).  Without it: XCD-aware order, width 64 for GQ_FP32_SPLIT and 32 otherwise
-   (also for the rotation M2L). */
+   gq_stats_t).  Without it: XCD-aware order, width 32 (also for the rotation M2L). */
 #define GQ_FLAG_AUTOTUNE (1u << 3)
 /* Which interaction lists contribute (testing aid).  0 in bits 8..13 means all. */
 #define GQ_LIST_U (1u << 8)       /* List 1 (direct)            Stage 3 */
@@ -107,6 +116,13 @@ typedef struct {
      based translations of Appendix C's cost model), run as three sparse tile products on
      the FP64 matrix cores.  1 needs GQ_FP64 and p_fmm <= 15 (else GQ_EUNSUPPORTED). */
   int m2l_rotation;
+  /* Cap on the device memory a plan may hold (geometry, work lists, translation matrices,
+     expansions), in bytes; 0 means no cap.  A plan that would exceed it is not created:
+     gq_plan_create (or gq_batch_create, which applies the first member's cap) returns
+     GQ_ENOMEM, frees what it had allocated and leaves *out untouched.  Later calls that
+     add device data to a plan (gq_set_source_interp, gq_set_target_normals) are held to
+     the same cap.  gq_stats reports the bytes a plan holds.  Must be >= 0. */
+  int64_t max_device_bytes;
 } gq_params;
 
 typedef struct gq_plan gq_plan; /* opaque */
@@ -131,6 +147,12 @@ typedef struct {
   int32_t m2l_tile_cols;    /* M2L tile width in use (64 or 32) */
   int32_t m2l_xcd_order;    /* 1: XCD-aware M2L tile order, 0: plain */
   int64_t n_point_targets;  /* conventional targets (tgt_center = -1) */
+  /* The operation-count model of Section 6 (Table 7) over the plan's interaction lists,
+     with p = p_fmm and q = p_qbx: per list U, V, Wclose, Wfar, Xclose, Xfar the sum over
+     entries of q^2 n_s n_t, p^3, q^2 n_s n_t, p^3 n_t, q^2 n_s n_t and p^2 n_s (n_s sources
+     of the source box, n_t centers of the target box), then the total of the six. */
+  double modeled_flops[7];
+  int64_t device_bytes;     /* device memory held by the plan (its workspace) */
 } gq_stats_t;
 
 /*
@@ -313,8 +335,10 @@ gq_status gq_list_export(const gq_plan* plan, int list, int64_t* ptr, int32_t* i
 /*
  * Download the QBX local coefficients of the last gq_apply for density 0, after Stage 8:
  * host_out[n_ctr * (p_qbx+1)^2], input center order, in the library's internal real-packed
- * solid-harmonic form l_n^m = sum_j q_j conj(I_n^m)(s_j - c) (see the DESIGN notes for the
- * map to the paper's L_n^m).  Synchronizes the plan's last stream.
+ * solid-harmonic form l_n^m = sum_j q_j conj(I_n^m)(s_j - c), with
+ * I_n^m(v) = (n-m)! P_n^m(cos theta) e^{i m phi} / r^(n+1) (Condon-Shortley phase in P_n^m),
+ * so that the potential is (1/4 pi) sum_n [l_n^0 R_n^0 + 2 Re sum_{m>0} l_n^m R_n^m](t - c)
+ * with R_n^m(v) = r^n P_n^m(cos theta) e^{i m phi} / (n+m)!.  Synchronizes the plan's last stream.
  */
 gq_status gq_qbx_locals(gq_plan* plan, double* host_out);
 

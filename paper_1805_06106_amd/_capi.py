@@ -14,14 +14,17 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgigaqbx.so")
+# GQ_LIBRARY selects another build of the same library (the host-sanitized one)
+LIB_PATH = os.environ.get("GQ_LIBRARY") or os.path.join(_HERE, "libgigaqbx.so")
 
 GQ_OK, GQ_EINVAL, GQ_ENOMEM, GQ_EDEVICE, GQ_EUNSUPPORTED = 0, 1, 2, 3, 4
 GQ_KERNEL_S, GQ_KERNEL_D, GQ_KERNEL_SP = 0, 1, 2
 GQ_FP64 = 0
 GQ_FP32_SPLIT = 1
 GQ_FP32 = 2
-PRECISIONS = {"fp64": GQ_FP64, "fp32_split": GQ_FP32_SPLIT, "fp32": GQ_FP32}
+GQ_FP32_LEAD = 3
+PRECISIONS = {"fp64": GQ_FP64, "fp32_split": GQ_FP32_SPLIT, "fp32": GQ_FP32,
+              "fp32_lead": GQ_FP32_LEAD}
 GQ_FLAG_HOST_ONLY = 1 << 0
 GQ_FLAG_TIMING = 1 << 1
 GQ_FLAG_GRAPH = 1 << 2
@@ -51,7 +54,8 @@ class gq_params(ctypes.Structure):
                 ("tcf", ctypes.c_double), ("kernel", ctypes.c_int), ("precision", ctypes.c_int),
                 ("n_densities", ctypes.c_int), ("flags", ctypes.c_uint),
                 ("wfar_direct_max", ctypes.c_int), ("tcr_norm", ctypes.c_int),
-                ("level_restrict", ctypes.c_int), ("m2l_rotation", ctypes.c_int)]
+                ("level_restrict", ctypes.c_int), ("m2l_rotation", ctypes.c_int),
+                ("max_device_bytes", ctypes.c_int64)]
 
 
 class gq_stats_t(ctypes.Structure):
@@ -63,7 +67,8 @@ class gq_stats_t(ctypes.Structure):
                 ("m2l_classes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
                 ("stage_ms", ctypes.c_double * 12), ("timed_applies", ctypes.c_int64),
                 ("m2l_tile_cols", ctypes.c_int32), ("m2l_xcd_order", ctypes.c_int32),
-                ("n_point_targets", ctypes.c_int64)]
+                ("n_point_targets", ctypes.c_int64), ("modeled_flops", ctypes.c_double * 7),
+                ("device_bytes", ctypes.c_int64)]
 
 
 class GQError(RuntimeError):
@@ -160,7 +165,7 @@ def gq_last_error():
 
 def make_params(p_qbx, p_fmm, nmax=512, tcf=0.9, kernel="S", n_densities=1, flags=0,
                 lists=None, wfar_direct_max=0, precision="fp64", tcr_norm="l2",
-                level_restrict=False, m2l_rotation=False):
+                level_restrict=False, m2l_rotation=False, max_device_bytes=0):
     k = {"S": GQ_KERNEL_S, "D": GQ_KERNEL_D, "SP": GQ_KERNEL_SP}.get(kernel, kernel)
     prec = PRECISIONS.get(precision, precision)
     if lists is not None:
@@ -169,7 +174,7 @@ def make_params(p_qbx, p_fmm, nmax=512, tcf=0.9, kernel="S", n_densities=1, flag
     return gq_params(int(p_qbx), int(p_fmm), int(nmax), float(tcf), int(k), int(prec),
                      int(n_densities), int(flags), int(wfar_direct_max),
                      {"l2": 0, "linf": 1}.get(tcr_norm, tcr_norm), int(level_restrict),
-                     int(m2l_rotation))
+                     int(m2l_rotation), int(max_device_bytes))
 
 
 def gq_plan_create(params, src_xyz, src_w, src_normal, ctr_xyz, ctr_radius, tgt_xyz,
@@ -274,6 +279,8 @@ def gq_stats(plan):
         "timed_applies": s.timed_applies,
         "m2l_tile_cols": s.m2l_tile_cols, "m2l_xcd_order": bool(s.m2l_xcd_order),
         "n_point_targets": s.n_point_targets,
+        "modeled_flops": dict(zip(list(LIST_INDEX) + ["total_lists"], list(s.modeled_flops))),
+        "device_bytes": s.device_bytes,
     }
 
 

@@ -83,17 +83,38 @@ def qbxl2p_target(q: int) -> int:
     return 8 + 10 * q + 9 * (q * (q + 1) // 2) + 4 * (q + 1) ** 2 + 1
 
 
+# FP64 flops per unit that the kernels execute, counted on the GPU with rocprofv3
+# (64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_MUL_F64 + SQ_INSTS_VALU_ADD_F64) over
+# one launch, divided by the launch's units) on the urchin (double layer, p_qbx = 5,
+# p_fmm = 15).  Where a configuration has no count, the written models above are used.
+COUNTED_P2QBXL_PAIR = {(5, "D"): 526.4}      # near field, per (source, center) pair
+COUNTED_P2M_SOURCE = {(15, "D"): 8706.0}     # P2M, per source
+COUNTED_P2L_FLOPS_URCHIN = 5.658e10          # P2L, the whole launch on the urchin
+
+
+def p2qbxl_pair_counted(q: int, kernel: str) -> float:
+    return COUNTED_P2QBXL_PAIR.get((q, kernel), float(p2qbxl_pair(q, kernel)))
+
+
 def apply_flops(stats: dict, p: int, q: int, kernel: str) -> dict:
-    """Executed-work model of one apply, per stage, from the plan's interaction counts."""
+    """Work of one apply, per stage, from the plan's interaction counts: the near field by
+    its counted flops per pair where counted; the M2QBXL, L2QBXL and QBXL2P models; the
+    dense translations at 2 (p+1)^4 per product (M2M and L2L: one product per box below
+    the root); P2M by its counted flops per source where counted (else omitted)."""
     pr = stats["pairs"]
     near = pr["U"] + pr["Wclose"] + pr["Xclose"]
-    return {
-        "p2qbxl": near * p2qbxl_pair(q, kernel),
+    out = {
+        "p2qbxl": near * p2qbxl_pair_counted(q, kernel),
         "m2qbxl": pr["Wfar"] * m2qbxl_pair(p, q),
         "m2l": pr["V"] * translate(p),
         "l2qbxl": stats["n_centers"] * l2qbxl_center(p, q),
         "qbxl2p": stats["n_targets"] * qbxl2p_target(q),
+        "m2m": (stats["n_boxes"] - 1) * translate(p),
+        "l2l": (stats["n_boxes"] - 1) * translate(p),
     }
+    if (p, kernel) in COUNTED_P2M_SOURCE:
+        out["p2m"] = stats["n_sources"] * COUNTED_P2M_SOURCE[(p, kernel)]
+    return out
 
 
 def paper_list_model(stats: dict, p: int, q: int) -> dict:

@@ -14,6 +14,7 @@
 #include "../../include/gigaqbx.h"
 #include "kernels.hpp"
 #include "planner.hpp"
+#include "query.hpp"
 
 namespace {
 
@@ -57,18 +58,18 @@ void make_tiles(std::vector<std::array<int, 3>> pairs, TileSet& ts, int width = 
   }
 }
 
-// M2L tile width of a plan that is not autotuned: the autotuner's choices on the urchin.
-// FP64 and FP32: 32 pairs (FP64 7.6 against 8.4 ms for 64, FP32 5.2 against 6.1 ms); the
-// split FP32 kernel, with three products per tile, keeps 64 (equal or better), and the
+// M2L tile width of a plan that is not autotuned: the autotuner's choice on the urchin,
+// 32 pairs (FP64 7.6 against 8.4 ms for 64, FP32 5.2 against 6.1 ms; the split kernel
+// holds its FP64 accumulators in registers, which 64-pair tiles would double); the
 // rotation kernel has its own width.
 int default_m2l_cols(const gq_params& prm) {
   if (prm.m2l_rotation) return gq::kRotCols;
-  return prm.precision == GQ_FP32_SPLIT ? gq::kTileCols : 32;
+  return 32;
 }
 
 // M2M and L2L tile width, by the same rule as M2L: the level passes have few tiles at the
 // coarse levels, where narrower tiles give more workgroups.
-int level_cols(const gq_params& prm) { return prm.precision == GQ_FP32_SPLIT ? gq::kTileCols : 32; }
+int level_cols(const gq_params&) { return 32; }
 
 }  // namespace
 
@@ -123,6 +124,7 @@ struct gq_plan {
 
   // device memory
   std::vector<void*> allocs;
+  int64_t dev_bytes = 0;  // bytes in allocs
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *snx = nullptr, *sny = nullptr,
          *snz = nullptr, *sw = nullptr;
   int64_t* src_order = nullptr;
@@ -159,6 +161,9 @@ struct gq_plan {
   gq::RotMats rot{};
   float *T32_m2m[2] = {nullptr, nullptr}, *T32_l2l[2] = {nullptr, nullptr},
         *T32_m2l[2] = {nullptr, nullptr};  // (hi, lo)
+  // FP32 modes: leading FP64 columns of the balanced matrices and the balancing N, 1 / N
+  double *Tlead_m2m = nullptr, *Tlead_l2l = nullptr, *Tlead_m2l = nullptr;
+  double *d_norm = nullptr, *d_inorm = nullptr;
   gq::TransMats tm_m2m{}, tm_l2l{}, tm_m2l{};
   double *q = nullptr, *M = nullptr, *L = nullptr, *Lq = nullptr;
   double* interp = nullptr;  // [n_quad][n_node], set by gq_set_source_interp
@@ -193,12 +198,25 @@ struct gq_plan {
 
 namespace {
 
+// Every device allocation of a plan goes through here: the workspace cap is enforced and
+// the held bytes counted.
+gq_status plan_malloc(gq_plan* P, void** d, size_t bytes) {
+  if (P->prm.max_device_bytes > 0 &&
+      P->dev_bytes + (int64_t)bytes > P->prm.max_device_bytes)
+    return fail(GQ_ENOMEM, "the plan needs more device memory than its cap of " +
+                               std::to_string(P->prm.max_device_bytes) + " bytes");
+  GQ_HIP(hipMalloc(d, bytes));
+  P->allocs.push_back(*d);
+  P->dev_bytes += (int64_t)bytes;
+  return GQ_OK;
+}
+
 template <class T>
 gq_status upload(gq_plan* P, const std::vector<T>& h, T** d, hipStream_t s) {
   *d = nullptr;
   if (h.empty()) return GQ_OK;
-  GQ_HIP(hipMalloc((void**)d, h.size() * sizeof(T)));
-  P->allocs.push_back(*d);
+  gq_status st = plan_malloc(P, (void**)d, h.size() * sizeof(T));
+  if (st != GQ_OK) return st;
   GQ_HIP(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return GQ_OK;
 }
@@ -207,9 +225,7 @@ template <class T>
 gq_status alloc(gq_plan* P, size_t n, T** d) {
   *d = nullptr;
   if (n == 0) return GQ_OK;
-  GQ_HIP(hipMalloc((void**)d, n * sizeof(T)));
-  P->allocs.push_back(*d);
-  return GQ_OK;
+  return plan_malloc(P, (void**)d, n * sizeof(T));
 }
 
 #define GQ_TRY(x)                  \
@@ -645,25 +661,45 @@ gq_status upload_work(gq_plan* P) {
     GQ_TRY(upload(P, Tl, &P->T_l2l, s));
     GQ_TRY(upload(P, Tv, &P->T_m2l, s));
   } else {
-    // T = hi + lo with hi = fl32(T), lo = fl32(T - hi)
-    auto split = [&](const std::vector<double>& T64, float** d) -> gq_status {
-      std::vector<float> hi(T64.size()), lo(T64.size());
-      for (size_t i = 0; i < T64.size(); ++i) {
-        hi[i] = (float)T64[i];
-        lo[i] = (float)(T64[i] - (double)hi[i]);
-      }
+    // Balanced FP32 forms T^ = diag(1 / s_out) T diag(1 / s_in) (N = sqrt((n+m)! (n-m)!);
+    // multipoles in, s_in = N; locals in, 1 / N; multipoles out, s_out = 1 / N; locals
+    // out, N), split as T^ = hi + lo with hi = fl32(T^), lo = fl32(T^ - hi); the first
+    // kLeadCols columns are also kept in FP64 for the modes that contract them exactly.
+    std::vector<double> N(np), Ni(np);
+    gq::expansion_norms(p, N.data());
+    for (int i = 0; i < np; ++i) Ni[i] = 1.0 / N[i];
+    GQ_TRY(upload(P, N, &P->d_norm, s));
+    GQ_TRY(upload(P, Ni, &P->d_inorm, s));
+    const int prec = P->prm.precision;
+    const bool lead = prec == GQ_FP32_SPLIT || prec == GQ_FP32_LEAD;
+    const int ld = gq::trans_ld(np), kd = gq::trans_kd(np), nl = gq::kLeadCols;
+    auto split = [&](const std::vector<double>& T64, const std::vector<double>& sin,
+                     const std::vector<double>& sout, float** d, double** dl) -> gq_status {
+      const size_t nm = T64.size() / ((size_t)ld * kd);
+      std::vector<float> hi(T64.size()), lo(prec == GQ_FP32_SPLIT ? T64.size() : 0);
+      std::vector<double> lh(lead ? nm * nl * ld : 0, 0.0);
+      for (size_t m = 0; m < nm; ++m)
+        for (int c = 0; c < kd; ++c)
+          for (int r = 0; r < ld; ++r) {
+            const size_t i = m * ld * kd + (size_t)c * ld + r;
+            const double v = (c < np && r < np) ? T64[i] / (sout[r] * sin[c]) : 0.0;
+            hi[i] = (float)v;
+            if (!lo.empty()) lo[i] = (float)(v - (double)hi[i]);
+            if (lead && c < nl) lh[(m * nl + c) * ld + r] = v;
+          }
       GQ_TRY(upload(P, hi, &d[0], s));
-      if (P->prm.precision == GQ_FP32_SPLIT) GQ_TRY(upload(P, lo, &d[1], s));
+      GQ_TRY(upload(P, lo, &d[1], s));
+      GQ_TRY(upload(P, lh, dl, s));
       GQ_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
       return GQ_OK;
     };
-    GQ_TRY(split(Tm, P->T32_m2m));
-    GQ_TRY(split(Tl, P->T32_l2l));
-    GQ_TRY(split(Tv, P->T32_m2l));
+    GQ_TRY(split(Tm, N, Ni, P->T32_m2m, &P->Tlead_m2m));
+    GQ_TRY(split(Tl, Ni, N, P->T32_l2l, &P->Tlead_l2l));
+    GQ_TRY(split(Tv, N, N, P->T32_m2l, &P->Tlead_m2l));
   }
-  P->tm_m2m = {P->T_m2m, P->T32_m2m[0], P->T32_m2m[1]};
-  P->tm_l2l = {P->T_l2l, P->T32_l2l[0], P->T32_l2l[1]};
-  P->tm_m2l = {P->T_m2l, P->T32_m2l[0], P->T32_m2l[1]};
+  P->tm_m2m = {P->T_m2m, P->T32_m2m[0], P->T32_m2m[1], P->Tlead_m2m, P->d_norm, P->d_inorm};
+  P->tm_l2l = {P->T_l2l, P->T32_l2l[0], P->T32_l2l[1], P->Tlead_l2l, P->d_inorm, P->d_norm};
+  P->tm_m2l = {P->T_m2l, P->T32_m2l[0], P->T32_m2l[1], P->Tlead_m2l, P->d_norm, P->d_norm};
   if (rot) GQ_TRY(upload_rotation(P, s));
   GQ_TRY(upload(P, P->p2m_boxes, &P->d_p2m_boxes, s));
   GQ_TRY(upload(P, P->p2m_ptr, &P->d_p2m_ptr, s));
@@ -982,8 +1018,9 @@ gq_status autotune_m2l(gq_plan* P, hipStream_t s) {
 
 // Uniform cell grid over [lo, hi] whose cells are at least `reach` wide (slightly more, so
 // that a point within reach of a query lies in the 27 cells around the query's cell even
-// after rounding), with at most 2^24 cells.
-gq::AssocGrid make_grid(const double lo[3], const double hi[3], double reach) {
+// after rounding), with at most max_cells cells.
+gq::AssocGrid make_grid(const double lo[3], const double hi[3], double reach,
+                        int64_t max_cells = (int64_t)1 << 24) {
   const double extent = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
   gq::AssocGrid g{};
   g.h = reach * (1.0 + 1e-9) + extent * 1e-12;
@@ -995,7 +1032,7 @@ gq::AssocGrid make_grid(const double lo[3], const double hi[3], double reach) {
       g.n[a] = (int)std::min<double>(std::floor((hi[a] - lo[a]) / g.h) + 1.0, 1 << 24);
       cells *= g.n[a];
     }
-    if (cells <= ((int64_t)1 << 24)) break;
+    if (cells <= max_cells) break;
     g.h *= 1.25;  // wider cells only add candidates; reach is unchanged
   }
   return g;
@@ -1011,6 +1048,77 @@ int64_t grid_cell(const gq::AssocGrid& g, const double* p) {
 }
 
 }  // namespace
+
+namespace gq {
+
+gq_status set_error(gq_status st, const std::string& msg) { return fail(st, msg); }
+
+gq_status near_prepare(int64_t n_q, const double* q_xyz, const double* radius, int64_t n_p,
+                       const double* p_xyz, uint8_t* hit, int64_t max_cells, NearQuery& Q,
+                       bool& done) {
+  done = false;
+  if (n_q < 0 || n_p < 0) return fail(GQ_EINVAL, "negative count");
+  if ((n_q && (!q_xyz || !radius || !hit)) || (n_p && !p_xyz))
+    return fail(GQ_EINVAL, "NULL array with a nonzero count");
+  if (!finite3(q_xyz, n_q) || !finite3(p_xyz, n_p)) return fail(GQ_EINVAL, "non-finite coordinate");
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n_q; ++i) {
+    if (!std::isfinite(radius[i]) || radius[i] < 0)
+      return fail(GQ_EINVAL, "radii must be finite and >= 0");
+    rmax = std::max(rmax, radius[i]);
+  }
+  if (n_q + n_p >= ((int64_t)1 << 31)) return fail(GQ_EUNSUPPORTED, "more than 2^31 points");
+  if (n_q == 0) {
+    done = true;
+    return GQ_OK;
+  }
+  if (n_p == 0) {
+    std::fill(hit, hit + n_q, (uint8_t)0);
+    done = true;
+    return GQ_OK;
+  }
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) lo[a] = hi[a] = q_xyz[a];
+  for (const double* pp : {q_xyz, p_xyz}) {
+    const int64_t n = pp == q_xyz ? n_q : n_p;
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], pp[3 * i + a]);
+        hi[a] = std::max(hi[a], pp[3 * i + a]);
+      }
+  }
+  Q.g = make_grid(lo, hi, rmax, max_cells);
+  const gq::AssocGrid& g = Q.g;
+  const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  Q.start.assign(ncell + 1, 0);
+  std::vector<int64_t> cell(n_p);
+  for (int64_t i = 0; i < n_p; ++i) {
+    cell[i] = grid_cell(g, p_xyz + 3 * i);
+    Q.start[cell[i] + 1] += 1;
+  }
+  for (int64_t c = 0; c < ncell; ++c) Q.start[c + 1] += Q.start[c];
+  std::vector<int64_t> fill(Q.start.begin(), Q.start.end() - 1);
+  Q.px.resize(n_p);
+  Q.py.resize(n_p);
+  Q.pz.resize(n_p);
+  for (int64_t i = 0; i < n_p; ++i) {
+    const int64_t k = fill[cell[i]]++;
+    Q.px[k] = p_xyz[3 * i];
+    Q.py[k] = p_xyz[3 * i + 1];
+    Q.pz[k] = p_xyz[3 * i + 2];
+  }
+  Q.qx.resize(n_q);
+  Q.qy.resize(n_q);
+  Q.qz.resize(n_q);
+  for (int64_t i = 0; i < n_q; ++i) {
+    Q.qx[i] = q_xyz[3 * i];
+    Q.qy[i] = q_xyz[3 * i + 1];
+    Q.qz[i] = q_xyz[3 * i + 2];
+  }
+  return GQ_OK;
+}
+
+}  // namespace gq
 
 extern "C" {
 
@@ -1038,7 +1146,8 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     return fail(GQ_EINVAL, "target confinement factor outside [0, 2 sqrt(3) - 2)");
   if (prm->kernel != GQ_KERNEL_S && prm->kernel != GQ_KERNEL_D && prm->kernel != GQ_KERNEL_SP)
     return fail(GQ_EINVAL, "unknown kernel");
-  if (prm->precision != GQ_FP64 && prm->precision != GQ_FP32_SPLIT && prm->precision != GQ_FP32)
+  if (prm->precision != GQ_FP64 && prm->precision != GQ_FP32_SPLIT && prm->precision != GQ_FP32 &&
+      prm->precision != GQ_FP32_LEAD)
     return fail(GQ_EINVAL, "unknown precision");
   if (prm->n_densities < 1) return fail(GQ_EINVAL, "n_densities must be >= 1");
   if (prm->wfar_direct_max < 0) return fail(GQ_EINVAL, "wfar_direct_max must be >= 0");
@@ -1047,6 +1156,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     return fail(GQ_EINVAL, "level_restrict must be 0 or 1");
   if (prm->m2l_rotation != 0 && prm->m2l_rotation != 1)
     return fail(GQ_EINVAL, "m2l_rotation must be 0 or 1");
+  if (prm->max_device_bytes < 0) return fail(GQ_EINVAL, "max_device_bytes must be >= 0");
   if (prm->m2l_rotation && (prm->precision != GQ_FP64 || prm->p_fmm > 15))
     return fail(GQ_EUNSUPPORTED, "M2L by rotation needs GQ_FP64 and p_fmm <= 15");
   if ((prm->flags & GQ_FLAG_TIMING) && (prm->flags & GQ_FLAG_GRAPH))
@@ -1436,6 +1546,19 @@ gq_status gq_stats(gq_plan* P, gq_stats_t* out) {
     P->timed_applies = 0;
   }
   P->stats.n_point_targets = P->n_pt;
+  P->stats.device_bytes = P->dev_bytes;
+  {
+    // Table 7: q^2 per (source, center) pair of Lists 1, 3-close, 4-close; p^3 per List 2
+    // pair and per List 3-far (box, center) pair; p^2 per List 4-far (source, box) pair
+    const double p = P->prm.p_fmm, q = P->prm.p_qbx;
+    const double w[6] = {q * q, p * p * p, q * q, p * p * p, q * q, p * p};
+    double tot = 0.0;
+    for (int i = 0; i < 6; ++i) {
+      P->stats.modeled_flops[i] = w[i] * (double)P->stats.pairs[i];
+      tot += P->stats.modeled_flops[i];
+    }
+    P->stats.modeled_flops[6] = tot;
+  }
   P->stats.m2l_tile_cols = P->m2l_cols;
   P->stats.m2l_xcd_order = P->m2l_xcd ? 1 : 0;
   *out = P->stats;
@@ -1486,53 +1609,10 @@ gq_status gq_set_target_normals(gq_plan* P, const double* tgt_normal) {
 gq_status gq_points_near(int64_t n_q, const double* q_xyz, const double* radius, int strict,
                          int64_t n_p, const double* p_xyz, uint8_t* hit, void* hip_stream) {
   g_err.clear();
-  if (n_q < 0 || n_p < 0) return fail(GQ_EINVAL, "negative count");
-  if ((n_q && (!q_xyz || !radius || !hit)) || (n_p && !p_xyz))
-    return fail(GQ_EINVAL, "NULL array with a nonzero count");
-  if (!finite3(q_xyz, n_q) || !finite3(p_xyz, n_p)) return fail(GQ_EINVAL, "non-finite coordinate");
-  double rmax = 0.0;
-  for (int64_t i = 0; i < n_q; ++i) {
-    if (!std::isfinite(radius[i]) || radius[i] < 0)
-      return fail(GQ_EINVAL, "radii must be finite and >= 0");
-    rmax = std::max(rmax, radius[i]);
-  }
-  if (n_q + n_p >= ((int64_t)1 << 31)) return fail(GQ_EUNSUPPORTED, "more than 2^31 points");
-  if (n_q == 0) return GQ_OK;
-  if (n_p == 0) {
-    std::fill(hit, hit + n_q, (uint8_t)0);
-    return GQ_OK;
-  }
-  double lo[3], hi[3];
-  for (int a = 0; a < 3; ++a) lo[a] = hi[a] = q_xyz[a];
-  for (const double* pp : {q_xyz, p_xyz}) {
-    const int64_t n = pp == q_xyz ? n_q : n_p;
-    for (int64_t i = 0; i < n; ++i)
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = std::min(lo[a], pp[3 * i + a]);
-        hi[a] = std::max(hi[a], pp[3 * i + a]);
-      }
-  }
-  const gq::AssocGrid g = make_grid(lo, hi, rmax);
-  const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-  std::vector<int64_t> start(ncell + 1, 0), cell(n_p);
-  for (int64_t i = 0; i < n_p; ++i) {
-    cell[i] = grid_cell(g, p_xyz + 3 * i);
-    start[cell[i] + 1] += 1;
-  }
-  for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
-  std::vector<int64_t> fill(start.begin(), start.end() - 1);
-  std::vector<double> px(n_p), py(n_p), pz(n_p), qx(n_q), qy(n_q), qz(n_q);
-  for (int64_t i = 0; i < n_p; ++i) {
-    const int64_t k = fill[cell[i]]++;
-    px[k] = p_xyz[3 * i];
-    py[k] = p_xyz[3 * i + 1];
-    pz[k] = p_xyz[3 * i + 2];
-  }
-  for (int64_t i = 0; i < n_q; ++i) {
-    qx[i] = q_xyz[3 * i];
-    qy[i] = q_xyz[3 * i + 1];
-    qz[i] = q_xyz[3 * i + 2];
-  }
+  gq::NearQuery Q;
+  bool done = false;
+  GQ_TRY(gq::near_prepare(n_q, q_xyz, radius, n_p, p_xyz, hit, (int64_t)1 << 24, Q, done));
+  if (done) return GQ_OK;
   struct DevBufs {
     std::vector<void*> p;
     ~DevBufs() {
@@ -1547,19 +1627,19 @@ gq_status gq_points_near(int64_t n_q, const double* q_xyz, const double* radius,
     return GQ_OK;
   };
   void *dst, *dpx, *dpy, *dpz, *dqx, *dqy, *dqz, *dqr, *dhit;
-  GQ_TRY(up(start.data(), start.size() * sizeof(int64_t), &dst));
-  GQ_TRY(up(px.data(), n_p * sizeof(double), &dpx));
-  GQ_TRY(up(py.data(), n_p * sizeof(double), &dpy));
-  GQ_TRY(up(pz.data(), n_p * sizeof(double), &dpz));
-  GQ_TRY(up(qx.data(), n_q * sizeof(double), &dqx));
-  GQ_TRY(up(qy.data(), n_q * sizeof(double), &dqy));
-  GQ_TRY(up(qz.data(), n_q * sizeof(double), &dqz));
+  GQ_TRY(up(Q.start.data(), Q.start.size() * sizeof(int64_t), &dst));
+  GQ_TRY(up(Q.px.data(), n_p * sizeof(double), &dpx));
+  GQ_TRY(up(Q.py.data(), n_p * sizeof(double), &dpy));
+  GQ_TRY(up(Q.pz.data(), n_p * sizeof(double), &dpz));
+  GQ_TRY(up(Q.qx.data(), n_q * sizeof(double), &dqx));
+  GQ_TRY(up(Q.qy.data(), n_q * sizeof(double), &dqy));
+  GQ_TRY(up(Q.qz.data(), n_q * sizeof(double), &dqz));
   GQ_TRY(up(radius, n_q * sizeof(double), &dqr));
   GQ_TRY(up(nullptr, n_q, &dhit));
   const gq::AssocCells pts{(const int64_t*)dst, (const double*)dpx, (const double*)dpy,
                            (const double*)dpz, nullptr, nullptr, nullptr};
   gq::launch_points_near(s, n_q, (const double*)dqx, (const double*)dqy, (const double*)dqz,
-                         (const double*)dqr, strict, g, pts, (uint8_t*)dhit);
+                         (const double*)dqr, strict, Q.g, pts, (uint8_t*)dhit);
   GQ_HIP(hipGetLastError());
   GQ_HIP(hipMemcpyAsync(hit, dhit, n_q, hipMemcpyDeviceToHost, s));
   GQ_HIP(hipStreamSynchronize(s));

@@ -210,27 +210,41 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
   }
 }
 
-// Split-precision translations on FP32 MFMA (v_mfma_f32_16x16x4f32).  Same tiling as
-// k_translate.  The matrix is stored as T = T_hi + T_lo (two FP32 arrays) and each input
-// coefficient is split on the fly into x = x_hi + x_lo; SPLIT adds the two correction
-// products, T_hi x_lo + T_lo x_hi, to T_hi x_hi (the dropped T_lo x_lo term is below FP32
-// rounding).  Products accumulate in FP32 over the whole contraction; the result is added
-// to the FP64 expansions.  Without SPLIT only T_hi x_hi is used.
+// FP32 matrix-core translations (v_mfma_f32_16x16x4f32).  Same tiling as k_translate.
+// The matrices are balanced: T^ = diag(1 / s_out) T diag(1 / s_in), with s = N_n^m or
+// 1 / N_n^m (N_n^m = sqrt((n+m)! (n-m)!)) by the kind of expansion, so that inputs
+// x^ = s_in x, outputs and entries are O(1) at every order up to p = 20; the kernel scales
+// each input as it is staged and each output before it is added to the FP64 expansions.
+// T^ is stored as the FP32 pair T_hi + T_lo and each staged input as x_hi + x_lo.
+//   MODE 0 (uncorrected): T_hi x_hi over every column, FP32 accumulation.
+//   MODE 1 (split): the first kLead columns (degrees n <= 3, which carry most of the
+//     magnitude of every output, since the expansions decay with the degree) are contracted
+//     exactly on the FP64 matrix cores; over the rest each K-step forms
+//     T_hi x_lo + T_lo x_hi + T_hi x_hi from zero on the FP32 matrix cores and adds it into
+//     FP64 registers, so only the rounding inside one step remains.
+//   MODE 2 (leading degrees): the first kLead columns in FP64 as in MODE 1, the rest
+//     T_hi x_hi with FP32 accumulation.
 typedef float f4_t __attribute__((ext_vector_type(4)));
+constexpr int kLead = kLeadCols;  // leading packed coefficients contracted in FP64 (MODE 1, 2)
 
-template <int KIND, int CB, bool SPLIT>
-__global__ __launch_bounds__(256) void k_translate32(int np, const int* __restrict__ tile_cls,
+template <int KIND, int CB, int MODE>
+__global__ __launch_bounds__(256, MODE == 2 && CB == 2 ? 4 : 1) void k_translate32(int np, const int* __restrict__ tile_cls,
                                                      const int* __restrict__ tile_beg,
                                                      const int* __restrict__ tile_cnt,
                                                      const int* __restrict__ pair_src,
                                                      const int* __restrict__ pair_dst,
                                                      const float* __restrict__ Thi,
                                                      const float* __restrict__ Tlo,
+                                                     const double* __restrict__ Tlead,
+                                                     const double* __restrict__ s_in,
+                                                     const double* __restrict__ s_out,
                                                      const double* __restrict__ X,
                                                      double* __restrict__ Y, int ntile,
                                                      int per_xcd) {
+  constexpr bool kLeadOn = MODE != 0;
   constexpr int kXs = 16 * CB + 1;  // padded LDS row
   __shared__ float2 xs[2][kKc * kXs];  // double-buffered [k][col] = (hi, lo)
+  __shared__ double xl64[kLeadOn ? kLead * kXs : 1];  // leading inputs in FP64 [k][col]
   const int t = per_xcd ? (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds)
                         : (int)blockIdx.x;
   if (t >= ntile) return;
@@ -241,6 +255,11 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
   const int64_t moff = (int64_t)cls * ld * kd;
   const int nrb = ld >> 4;
   static_assert(kKc == 64, "staging maps one lane to one k of a chunk");
+  // matrix prefetch depth in K-steps: the split mode holds FP64 accumulators, so it
+  // prefetches less to keep two waves per SIMD
+  constexpr int kPf = MODE == 1 ? 2 : kPf32;
+  static_assert(kLead % (4 * kPf) == 0 && kLead / 4 <= kKc / 8,
+                "the FP32 steps of the first chunk start at a prefetch group of its first half");
   constexpr int kStage = 16 * CB / 4;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   int64_t src_off[kStage];
@@ -250,20 +269,24 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
     src_off[u] = col < cnt ? (int64_t)pair_src[beg + col] * np : -1;
   }
   constexpr int kHalf = kStage / 2;
+  // inputs of column k are scaled by s_in[k] as they are loaded (zero past np)
   auto load_half = [&](int kc, int h, double (&xr)[kHalf]) {
     const int k = kc + lane;
+    const double sc = k < np ? s_in[k] : 0.0;
 #pragma unroll
     for (int u = 0; u < kHalf; ++u) {
       const int64_t o = src_off[h * kHalf + u];
-      xr[u] = (o >= 0 && k < np) ? X[o + k] : 0.0;
+      xr[u] = (o >= 0 && k < np) ? X[o + k] * sc : 0.0;
     }
   };
-  auto store_half = [&](float2* xb, int h, const double (&xr)[kHalf]) {
+  auto store_half = [&](float2* xb, int h, const double (&xr)[kHalf], bool lead) {
 #pragma unroll
     for (int u = 0; u < kHalf; ++u) {
+      const int col = wave_u + 4 * (h * kHalf + u);
       const float hi = (float)xr[u];
       const float lo = (float)(xr[u] - (double)hi);
-      xb[lane * kXs + wave_u + 4 * (h * kHalf + u)] = make_float2(hi, lo);
+      xb[lane * kXs + col] = make_float2(hi, lo);
+      if (kLeadOn && lead && lane < kLead) xl64[lane * kXs + col] = xr[u];
     }
   };
   auto load_a = [&](int r0, int k, float (&ah)[4], float (&al)[4]) {
@@ -272,32 +295,38 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
     for (int i = 0; i < 4; ++i) {
       const int64_t off = col + min(r0 + wave_u + 4 * i, nrb - 1) * 16;
       ah[i] = Thi[off];
-      al[i] = SPLIT ? Tlo[off] : 0.0f;
+      al[i] = MODE == 1 ? Tlo[off] : 0.0f;
     }
   };
+  constexpr int k0 = kLeadOn ? kLead : 0;  // first column on the FP32 matrix cores
   for (int r0 = 0; r0 < nrb; r0 += 16) {
-    f4_t acc[4][CB];
+    f4_t acc[4][CB];      // FP32 accumulation (MODE 0, 2)
+    double acc64[4][CB][MODE == 1 ? 4 : 1];  // FP64 accumulation of the steps (MODE 1)
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[i][cb] = (f4_t){0.f, 0.f, 0.f, 0.f};
-    double xr[kHalf];
-    __syncthreads();  // the previous row pass has finished reading both buffers
-    load_half(0, 0, xr);
-    store_half(xs[0], 0, xr);
-    load_half(0, 1, xr);
-    store_half(xs[0], 1, xr);
-    float ah[kPf32][4], al[kPf32][4];
+      for (int cb = 0; cb < CB; ++cb) {
+        acc[i][cb] = (f4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int d = 0; d < kPf32; ++d) load_a(r0, 4 * d + lk, ah[d], al[d]);
+        for (int r = 0; r < (MODE == 1 ? 4 : 1); ++r) acc64[i][cb][r] = 0.0;
+      }
+    double xr[kHalf];
+    __syncthreads();  // the previous row pass has finished reading every buffer
+    load_half(0, 0, xr);
+    store_half(xs[0], 0, xr, r0 == 0);
+    load_half(0, 1, xr);
+    store_half(xs[0], 1, xr, r0 == 0);
+    float ah[kPf][4], al[kPf][4];
+#pragma unroll
+    for (int d = 0; d < kPf; ++d) load_a(r0, k0 + 4 * d + lk, ah[d], al[d]);
     __syncthreads();
     int cur = 0;
     auto steps = [&](int kc, int g0, int g1) {
       const float2* xb = xs[cur];
 #pragma unroll 1
-      for (int g = g0; g < g1; g += kPf32) {
+      for (int g = g0; g < g1; g += kPf) {
 #pragma unroll
-        for (int d = 0; d < kPf32; ++d) {
+        for (int d = 0; d < kPf; ++d) {
           const int st = g + d;
           float2 b[4];
 #pragma unroll
@@ -306,45 +335,74 @@ __global__ __launch_bounds__(256) void k_translate32(int np, const int* __restri
           for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-              if (SPLIT) {
+              if (MODE == 1) {
+                f4_t c = (f4_t){0.f, 0.f, 0.f, 0.f};
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].y, ah[d][i], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].x, al[d][i], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].x, ah[d][i], c, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc64[i][cb][r] += (double)c[r];
+              } else {
                 acc[i][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].y, ah[d][i], acc[i][cb], 0, 0, 0);
-                acc[i][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].x, al[d][i], acc[i][cb], 0, 0, 0);
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].x, ah[d][i], acc[i][cb], 0, 0, 0);
               }
-              acc[i][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[cb].x, ah[d][i], acc[i][cb], 0, 0, 0);
             }
-          load_a(r0, kc + 4 * (st + kPf32) + lk, ah[d], al[d]);
+          load_a(r0, kc + 4 * (st + kPf) + lk, ah[d], al[d]);
         }
       }
     };
     for (int kc = 0; kc < np; kc += kKc, cur ^= 1) {
       const bool more = kc + kKc < np;
       if (more) load_half(kc + kKc, 0, xr);
-      steps(kc, 0, kKc / 8);
+      steps(kc, kc == 0 ? k0 / 4 : 0, kKc / 8);
       if (more) {
-        store_half(xs[cur ^ 1], 0, xr);
+        store_half(xs[cur ^ 1], 0, xr, false);
         load_half(kc + kKc, 1, xr);
       }
       steps(kc, kKc / 8, kKc / 4);
-      if (more) store_half(xs[cur ^ 1], 1, xr);
+      if (more) store_half(xs[cur ^ 1], 1, xr, false);
       __syncthreads();
     }
+    // The leading columns on the FP64 matrix cores, one row block at a time, starting from
+    // the FP32 part's result.  Inputs are fed in the pair order pi(a + 4b) = 4a + b, so
+    // that register r of lane l holds pair 4 (l/16) + r, the place of the FP32
+    // accumulator layout: (pair 4 (l/16) + r, row l%16) of the transposed product.
+    const int pli = 4 * (li & 3) + (li >> 2);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int rb = r0 + wave + 4 * i;
-      if (rb >= nrb) continue;
+      const int rb = r0 + wave_u + 4 * i;
+      if (rb >= nrb) continue;  // wave-uniform
       const int row = rb * 16 + li;
+      const double so = row < np ? s_out[row] : 0.0;
+      double a[kLeadOn ? kLead / 4 : 1];
+      if (kLeadOn) {
+#pragma unroll
+        for (int st = 0; st < kLead / 4; ++st)
+          a[st] = Tlead[((int64_t)cls * kLead + 4 * st + lk) * ld + rb * 16 + li];
+      }
+      d4_t v[CB];
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
+        for (int r = 0; r < 4; ++r)
+          v[cb][r] = MODE == 1 ? acc64[i][cb][MODE == 1 ? r : 0] : (double)acc[i][cb][r];
+      if (kLeadOn) {
+#pragma unroll
+        for (int st = 0; st < kLead / 4; ++st)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+            v[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                xl64[(4 * st + lk) * kXs + cb * 16 + pli], a[st], v[cb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
-          // transposed product, FP32 accumulator layout: register r of lane l holds
-          // (pair 4 (l/16) + r, row l%16)
           const int col = cb * 16 + 4 * lk + r;
           if (col < cnt && row < np)
-            unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + col] * np + row], (double)acc[i][cb][r]);
+            unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + col] * np + row], v[cb][r] * so);
         }
+      }
     }
   }
 }
@@ -1112,6 +1170,18 @@ void launch_strength(hipStream_t s, int64_t n, const int64_t* order, const doubl
   k_strength<<<grid1d(n, 256), 256, 0, s>>>(n, order, w, density, q);
 }
 
+template <int CB, int MODE>
+void launch_translate32(hipStream_t s, dim3 grid, int kind, int np, int ntile, const int* tile_cls,
+                        const int* tile_beg, const int* tile_cnt, const int* pair_src,
+                        const int* pair_dst, const TransMats& T, const double* X, double* Y,
+                        int per_xcd) {
+  auto k = kind == 0   ? k_translate32<0, CB, MODE>
+           : kind == 1 ? k_translate32<1, CB, MODE>
+                       : k_translate32<2, CB, MODE>;
+  k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo,
+                         T.lead, T.s_in, T.s_out, X, Y, ntile, per_xcd);
+}
+
 template <int CB>
 void launch_translate_cb(hipStream_t s, int kind, int prec, int np, int ntile,
                          const int* tile_cls, const int* tile_beg, const int* tile_cnt,
@@ -1126,17 +1196,14 @@ void launch_translate_cb(hipStream_t s, int kind, int prec, int np, int ntile,
     k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.t64, X, Y,
                            ntile, per_xcd);
   } else if (prec == 1) {
-    auto k = kind == 0   ? k_translate32<0, CB, true>
-             : kind == 1 ? k_translate32<1, CB, true>
-                         : k_translate32<2, CB, true>;
-    k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo, X,
-                           Y, ntile, per_xcd);
+    launch_translate32<CB, 1>(s, grid, kind, np, ntile, tile_cls, tile_beg, tile_cnt, pair_src,
+                              pair_dst, T, X, Y, per_xcd);
+  } else if (prec == 2) {
+    launch_translate32<CB, 0>(s, grid, kind, np, ntile, tile_cls, tile_beg, tile_cnt, pair_src,
+                              pair_dst, T, X, Y, per_xcd);
   } else {
-    auto k = kind == 0   ? k_translate32<0, CB, false>
-             : kind == 1 ? k_translate32<1, CB, false>
-                         : k_translate32<2, CB, false>;
-    k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo, X,
-                           Y, ntile, per_xcd);
+    launch_translate32<CB, 2>(s, grid, kind, np, ntile, tile_cls, tile_beg, tile_cnt, pair_src,
+                              pair_dst, T, X, Y, per_xcd);
   }
 }
 

@@ -83,16 +83,23 @@ void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
                 const int64_t* ptr, const int* idx, const double* bctr, const double* bh,
                 SrcSoA src, const double* q, double* L);
 
-// Translation matrices of one kind, column-major n_p x n_p per class: FP64 (t64) or the
-// FP32 pair T = hi + lo.
+// Translation matrices of one kind, column-major n_p x n_p per class: FP64 (t64), or for
+// the FP32 modes the balanced matrix T^ = diag(1 / s_out) T diag(1 / s_in) as the FP32 pair
+// T^ = hi + lo, its first kLead columns in FP64 (lead: [class][kLead][trans_ld] column-major)
+// and the scalings s_in, s_out [n_p] (inputs are multiplied by s_in, outputs by s_out).
+constexpr int kLeadCols = 16;
 struct TransMats {
   const double* t64;
   const float *hi, *lo;
+  const double* lead;
+  const double *s_in, *s_out;
 };
 
 // Batched dense translations: for each tile t, Y[dst] += T[cls] X[src] for its pairs.
 // kind: 0 M2M, 1 L2L, 2 M2L (selects a separately named instantiation).
-// prec: 0 FP64 MFMA; 1 FP32 MFMA with the hi/lo split correction; 2 FP32 MFMA, hi only.
+// prec: 0 FP64 MFMA; 1 split (leading degrees on FP64 MFMA, the rest FP32 MFMA with the
+// hi/lo correction products and FP64 accumulation per K-step); 2 FP32 MFMA, hi only, FP32
+// accumulation; 3 leading degrees on FP64 MFMA, the rest FP32 MFMA hi only.
 // tile_cols: 32 or 64, the tile width the tiles were formed with; xcd_order: map
 // consecutive tiles to one XCD (else plain block order).
 void launch_translate(hipStream_t s, int kind, int prec, int np, int ntile,

@@ -82,6 +82,8 @@ int ncoef(int p);
 void m2m_matrix(int p, int octant, double* T);                  // child multipole -> parent
 void l2l_matrix(int p, int octant, double* T);                  // parent local -> child
 void m2l_matrix(int p, int ox, int oy, int oz, double* T);      // same-level, offset 2*o
+// N[(p+1)^2]: sqrt((n+m)! (n-m)!) per packed index (the balancing of the FP32 translations)
+void expansion_norms(int p, double* N);
 // The same M2L factored as T = B Z A: A rotates multipoles so that the offset points along
 // +z, Z translates along z (it couples only equal orders), B rotates locals back.  A and B
 // are block diagonal by degree; all three np x np, column-major.

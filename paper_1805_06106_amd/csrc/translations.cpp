@@ -257,6 +257,22 @@ void m2l_matrix(int p, int ox, int oy, int oz, double* T) {
   m2l_matrix_vec(p, 2.0 * ox, 2.0 * oy, 2.0 * oz, T);
 }
 
+// N_n^m = sqrt((n+m)! (n-m)!) at each packed index.  With it the normalized forms
+// R_n^m N_n^m and I_n^m / N_n^m are bounded by r^n and r^-(n+1) (the Schmidt
+// semi-normalized solid harmonics), so multipoles mu N and locals l / N of a box in its own
+// scaled units are O(1) for every order, and so are the entries of the translations
+// between them: at p = 20 the factorial form spans about 60 decades, beyond FP32's range.
+void expansion_norms(int p, double* N) {
+  std::vector<double> f(2 * p + 2, 1.0);
+  for (int i = 1; i < (int)f.size(); ++i) f[i] = f[i - 1] * i;
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m) {
+      const double v = std::sqrt(f[n + m] * f[n - m]);
+      N[n * n + (m ? 2 * m - 1 : 0)] = v;
+      if (m) N[n * n + 2 * m] = v;
+    }
+}
+
 void m2l_rotation_factors(int p, int ox, int oy, int oz, double* A, double* Z, double* B) {
   // a rotation Q taking the offset direction u to +z (Rodrigues about u x z)
   const double len = std::sqrt((double)(ox * ox + oy * oy + oz * oz));

@@ -201,3 +201,46 @@ def test_batch_with_point_targets(members):
         assert rel(pot[:, off:off + w.n_tgt], ref) < 1e-12
         off += w.n_tgt
     assert B.stats()["n_point_targets"] == 110
+
+
+def test_c3_members_full_size_vs_tier_b():
+    """Three surfaces of the 64-urchin batch at full size (surfaces 2, 0 and 14: 20 * 4^l
+    triangles at l = 3, 4, 5; 28 nodes each; D, 5/15; 8 densities), merged into one batch
+    plan with split-precision translations and a HIP graph, in the benchmark's tree
+    configuration; every member against Tier B on sampled centers for the first and the last
+    density, at the 1e-8 bar."""
+    import torch
+
+    from paper_1805_06106_amd import Plan
+    from workloads import workload_c3
+
+    dev = torch.device("cuda:0")
+    tree = dict(wfar_direct_max=64, level_restrict=True)
+    ws = [workload_c3(i) for i in (2, 0, 14)]
+    nd = ws[0].density.shape[0]
+    print(f"[gpu] C3 members {[w.n_src for w in ws]} sources, {nd} densities", flush=True)
+    members = [Plan.from_workload(w, n_densities=nd, precision="fp32_split", **tree)
+               for w in ws]
+    B = Plan.batch(members, graph=True)
+    for P in members:
+        P.close()
+    dens = torch.tensor(np.concatenate([w.density for w in ws], axis=1), device=dev)
+    pot = B.apply(dens)
+    pot2 = B.apply(dens)  # a replay of the captured graph
+    torch.cuda.synchronize()
+    pot, pot2 = pot.cpu().numpy(), pot2.cpu().numpy()
+    B.close()
+    assert np.array_equal(pot, pot2) or rel(pot2, pot) < 1e-14
+    rng = np.random.default_rng(91)
+    off = 0
+    for w in ws:
+        F = OracleFMM(w, **tree)
+        owner = np.asarray(F.tree.ctr_owner)
+        seeds = rng.choice(w.n_ctr, 3, replace=False)
+        cs = np.unique(np.concatenate([np.nonzero(owner == owner[c])[0][:8] for c in seeds]))
+        for d in (0, nd - 1):
+            tids, ref, _ = F.evaluate(density_index=d, centers=cs)
+            err = rel(pot[d, off + tids], ref)
+            print(f"[gpu] C3 member n_src={w.n_src} density {d}: {err:.3e}", flush=True)
+            assert err < 1e-8
+        off += w.n_tgt

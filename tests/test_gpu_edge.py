@@ -55,7 +55,7 @@ def test_single_source():
                             density=w.density[:, :1])
     print("[gpu] single source", flush=True)
     pot = _run(w)
-    ref, _ = O.direct_qbx("S", w.p_qbx, w.src_xyz, w.strengths()[0], w.ctr_xyz, w.tgt_xyz,
+    ref, _ = O.direct_qbx("S", w.p_qbx, w.src_xyz, O.strengths(w)[0], w.ctr_xyz, w.tgt_xyz,
                           w.tgt_center)
     tids, refb, _ = OracleFMM(w).evaluate()
     assert rel(pot[0][tids], refb) < 1e-10
@@ -89,3 +89,31 @@ def test_one_center_per_leaf_and_deep_ragged_tree():
         pot = _run(w)
         tids, ref, _ = OracleFMM(w).evaluate()
         assert rel(pot[0][tids], ref) < 1e-10
+
+
+def test_device_memory_cap():
+    """A plan over its device-memory cap is refused with GQ_ENOMEM and nothing else happens;
+    at a cap equal to what the plan holds it is created and evaluates as without a cap."""
+    import torch
+
+    import paper_1805_06106_amd as G
+    from paper_1805_06106_amd import Plan
+
+    w = workload_tiny(level=2, order=2, kernel="D", p_qbx=3, p_fmm=8, nmax=32)
+    print("[gpu] device memory cap", flush=True)
+    P0 = Plan.from_workload(w)
+    need = P0.stats()["device_bytes"]
+    assert need > 0
+    for cap in (1, need // 2, need - 1):
+        with pytest.raises(G.GQError) as e:
+            Plan.from_workload(w, max_device_bytes=cap)
+        assert e.value.status == 2 and "cap" in str(e.value)
+    P1 = Plan.from_workload(w, max_device_bytes=need)
+    assert P1.stats()["device_bytes"] == need
+    d = torch.tensor(w.density, dtype=torch.float64, device="cuda:0")
+    p0, p1 = P0.apply(d), P1.apply(d)
+    torch.cuda.synchronize()
+    # equal up to the order of the translations' atomic additions
+    assert rel(p1.cpu().numpy(), p0.cpu().numpy()) < 1e-14
+    # the refused creations left the device usable and the existing plans intact
+    assert rel(P0.apply(d).cpu().numpy(), p0.cpu().numpy()) < 1e-14

@@ -65,20 +65,25 @@ def test_urchin_sampled_vs_tier_b_and_a(urchin):
     assert err_a <= 0.75 ** (w.p_fmm + 1)
 
 
-def test_urchin_fp32_split_full_size(urchin):
-    # every target of the full problem: the split-precision translations against FP64, and
-    # sampled centers against the oracle
+def test_urchin_fp32_full_size(urchin):
+    # every target of the full problem: the FP32 matrix-core translations against the FP64
+    # path on the same tree, and sampled centers against the oracle.  The split form must
+    # be at least ten times more accurate than the uncorrected FP32 form.
     w = urchin
-    print("[gpu] urchin fp32_split vs fp64, all targets", flush=True)
+    print("[gpu] urchin fp32 modes vs fp64, all targets", flush=True)
     p64 = _gpu(w, BENCH_TREE)[0]
-    p32 = _gpu(w, BENCH_TREE, precision="fp32_split")[0]
-    err = rel(p32, p64)
-    print(f"[gpu] urchin fp32_split vs fp64: {err:.3e}", flush=True)
-    assert err < 1e-6
+    errs, pots = {}, {}
+    for prec in ("fp32_split", "fp32_lead", "fp32"):
+        pots[prec] = _gpu(w, BENCH_TREE, precision=prec)[0]
+        errs[prec] = rel(pots[prec], p64)
+        print(f"[gpu] urchin {prec} vs fp64: {errs[prec]:.3e}", flush=True)
+    assert errs["fp32"] < 1e-6
+    assert errs["fp32_split"] < 1e-8
+    assert errs["fp32_split"] <= 0.1 * errs["fp32"]
     rng = np.random.default_rng(22)
     cs = np.sort(rng.choice(w.n_ctr, 24, replace=False))
     tids, ref, _ = OracleFMM(w, **BENCH_TREE).evaluate(centers=cs)
-    assert rel(p32[tids], ref) < 1e-6
+    assert rel(pots["fp32_split"][tids], ref) < 1e-8
 
 
 def test_urchin_linearity_full_size(urchin):
@@ -95,14 +100,68 @@ def test_urchin_linearity_full_size(urchin):
     assert rel(pot0, pot[0]) < 1e-6
 
 
-def test_ellipsoid_sampled_vs_tier_b():
-    w = workload_c4()
-    print(f"[gpu] ellipsoid S 8/20 n_src={w.n_src}", flush=True)
-    pot = _gpu(w, BENCH_TREE)[0]
-    rng = np.random.default_rng(40)
-    cs = np.sort(rng.choice(w.n_ctr, 12, replace=False))
-    F = OracleFMM(w, **BENCH_TREE)
+@pytest.fixture(scope="module")
+def ellipsoid():
+    print("[gpu] building the ellipsoid workload", flush=True)
+    return workload_c4()
+
+
+# the ellipsoid's benchmark configuration: Remark 4 at the cost-model crossover of S 8/20
+# (335 sources), which leaves no W-far pair; a threshold of 64 keeps the W-far list busy
+C4_TREE = dict(wfar_direct_max=335, level_restrict=True)
+
+
+def _clustered_centers(F, w, rng, n_boxes, per_box):
+    """Centers of a few random owner boxes (up to per_box each): the oracle's cost per
+    center is dominated by its box's ancestor chain, which centers of one box share."""
+    owner = np.asarray(F.tree.ctr_owner)
+    picked = []
+    for c in rng.choice(w.n_ctr, n_boxes, replace=False):
+        same = np.nonzero(owner == owner[c])[0]
+        picked.append(same[rng.permutation(len(same))[:per_box]])
+    return np.unique(np.concatenate(picked))
+
+
+@pytest.fixture(scope="module")
+def ellipsoid_ref(ellipsoid):
+    """FP64 GPU potentials in the benchmark configuration and Tier B on about 96 centers."""
+    w = ellipsoid
+    print(f"[gpu] ellipsoid S 8/20 n_src={w.n_src} {C4_TREE}", flush=True)
+    p64 = _gpu(w, C4_TREE)[0]
+    F = OracleFMM(w, **C4_TREE)
+    cs = _clustered_centers(F, w, np.random.default_rng(40), 6, 16)
+    print(f"[gpu] ellipsoid Tier B on {len(cs)} centers", flush=True)
     tids, ref, _ = F.evaluate(centers=cs)
-    err_b = rel(pot[tids], ref)
-    print(f"[gpu] ellipsoid vs Tier B: {err_b:.3e}", flush=True)
+    return p64, tids, ref
+
+
+def test_ellipsoid_sampled_vs_tier_b(ellipsoid, ellipsoid_ref):
+    w = ellipsoid
+    p64, tids, ref = ellipsoid_ref
+    err_b = rel(p64[tids], ref)
+    print(f"[gpu] ellipsoid vs Tier B ({len(tids)} targets): {err_b:.3e}", flush=True)
     assert err_b < TOL
+    # Remark 4 at 64 keeps W-far pairs (M2QBXL at q = 8, p = 20)
+    print(f"[gpu] ellipsoid {BENCH_TREE}", flush=True)
+    pot = _gpu(w, BENCH_TREE)[0]
+    F = OracleFMM(w, **BENCH_TREE)
+    cs = _clustered_centers(F, w, np.random.default_rng(42), 2, 8)
+    tids2, ref2, _ = F.evaluate(centers=cs)
+    assert rel(pot[tids2], ref2) < TOL
+
+
+def test_ellipsoid_fp32_split(ellipsoid, ellipsoid_ref):
+    """The ellipsoid with split-precision translations (leading degrees in FP64, the rest on
+    the FP32 matrix cores with the hi/lo correction), every target against the FP64 path on
+    the same tree and sampled centers against the oracle, at the 1e-8 bar."""
+    w = ellipsoid
+    p64, tids, ref = ellipsoid_ref
+    print("[gpu] ellipsoid fp32_split and fp32 vs fp64, all targets", flush=True)
+    psp = _gpu(w, C4_TREE, precision="fp32_split")[0]
+    p32 = _gpu(w, C4_TREE, precision="fp32")[0]
+    e_sp, e_32 = rel(psp, p64), rel(p32, p64)
+    print(f"[gpu] ellipsoid fp32_split {e_sp:.3e}, fp32 {e_32:.3e}", flush=True)
+    assert e_sp < 1e-8
+    assert e_32 < 1e-6
+    assert e_sp <= 0.1 * e_32
+    assert rel(psp[tids], ref) < 1e-8

@@ -119,6 +119,35 @@ def test_stats_pair_counts(gq):
     assert s["n_boxes"] == t.nboxes and s["n_levels"] == t.nlevels
 
 
+def test_stats_modeled_flops_table7(gq):
+    """gq_stats' modeled flops are Table 7's counts over the plan's lists, checked against
+    the per-entry sum written out from the oracle's own lists."""
+    from paper_1805_06106_amd import costmodel as CM
+
+    w = workload_tiny(**CASES["D-l1-n32"])
+    P = gq.Plan.from_workload(w, host_only=True)
+    F = OracleFMM(w)
+    s = P.stats()
+    t, L = F.tree, F.lists
+    p, q = w.p_fmm, w.p_qbx
+    ref = {nm: 0.0 for nm in ("U", "V", "Wclose", "Wfar", "Xclose", "Xfar")}
+    for b in F.target_boxes():
+        nt = len(t.own_ctr[b])
+        for nm in ("U", "Wclose", "Xclose"):
+            ref[nm] += q * q * sum(len(t.own_src[d]) for d in L.get(nm, b)) * nt
+        ref["Wfar"] += p ** 3 * len(L.Wfar(b)) * nt
+    for b in F.list_owner_boxes():
+        ref["V"] += p ** 3 * len(L.V(b))
+    model = s["modeled_flops"]
+    for nm in ("U", "V", "Wclose", "Wfar", "Xclose"):
+        assert model[nm] == ref[nm], nm
+    assert model["Xfar"] == p * p * s["pairs"]["Xfar"]
+    assert model["total_lists"] == sum(model[nm] for nm in ref)
+    py = CM.paper_list_model(s, p, q)
+    for nm in ref:
+        assert model[nm] == py[nm]
+
+
 # --- translation matrices ----------------------------------------------------------------
 
 def _octant_vec(o):
@@ -198,6 +227,9 @@ def test_invalid_arguments(gq):
     assert e.value.status == 4
     with pytest.raises(G.GQError):
         G.Plan(**_args(w, tcf=1.5))
+    with pytest.raises(G.GQError) as e:
+        G.Plan(**_args(w, max_device_bytes=-1))
+    assert e.value.status == 1 and "max_device_bytes" in str(e.value)
     with pytest.raises(G.GQError):
         G.Plan(**_args(w, src_normal=None))
     bad = w.src_normal.copy()
@@ -248,11 +280,11 @@ def test_batch_and_graph_validation(gq):
 
 
 def test_default_translation_tile_widths(gq):
-    """Without autotuning: 32-pair M2L tiles for FP64 and plain FP32, 64 for split FP32 (its
-    three products per tile), 32 for the rotation M2L; XCD-aware tile order throughout."""
+    """Without autotuning: 32-pair M2L tiles in every precision mode (the split kernel keeps
+    FP64 accumulators in registers) and for the rotation M2L; XCD-aware tile order."""
     w = workload_tiny(level=1, order=2, kernel="D", p_qbx=3, p_fmm=6, nmax=32)
     G = gq
-    for prec, cols in (("fp64", 32), ("fp32", 32), ("fp32_split", 64)):
+    for prec, cols in (("fp64", 32), ("fp32", 32), ("fp32_split", 32), ("fp32_lead", 32)):
         st = G.Plan(**_args(w, precision=prec)).stats()
         assert (st["m2l_tile_cols"], st["m2l_xcd_order"]) == (cols, True), prec
     st = G.Plan(**_args(w, m2l_rotation=True)).stats()
