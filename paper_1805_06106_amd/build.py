@@ -49,5 +49,42 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SAN_LIB = os.path.join(HERE, "libgigaqbx_san.so")
+SAN_BUILD = os.path.join(HERE, "_build_san")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """A host-sanitized copy of the library (AddressSanitizer and UndefinedBehaviorSanitizer
+    on the host code only; device code is built as usual), for CPU runs of the host-side
+    tests with host-only plans.  Load it in a process started with clang's ASan runtime
+    preloaded and GQ_LIBRARY pointing at it."""
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    san = ["-fno-omit-frame-pointer", "-g"]
+    jobs = []
+    for f in ("planner.cpp", "translations.cpp"):
+        jobs.append(["/opt/rocm/llvm/bin/clang++", "-O1", "-std=c++17", "-fPIC",
+                     "-ffp-contract=off", "-fsanitize=address,undefined", *san, "-c",
+                     os.path.join(CSRC, f), "-o", os.path.join(SAN_BUILD, f + ".o")])
+    hip_sources = ("kernels.hip", "kernels_p2x.hip", "kernels_pt.hip", "kernels_rot.hip",
+                   "oversample.hip", "associate.hip", "executor.hip")
+    for f in hip_sources:
+        jobs.append(["hipcc", *HIP_FLAGS, "-Xarch_host", "-fsanitize=address,undefined", *san,
+                     "-c", os.path.join(CSRC, f), "-o", os.path.join(SAN_BUILD, f + ".o")])
+    with ThreadPoolExecutor(max_workers=6) as ex:
+        for out in ex.map(_run, jobs):
+            if verbose and out:
+                print(out)
+    objs = [os.path.join(SAN_BUILD, f + ".o") for f in ("planner.cpp", "translations.cpp",
+                                                         *hip_sources)]
+    tmp = SAN_LIB + ".tmp%d" % os.getpid()
+    _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-shared-libsan",
+          "-Xarch_host", "-fsanitize=address,undefined", "-o", tmp, *objs])
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if len(sys.argv) > 1 and sys.argv[1] == "--sanitize":
+        print(build_sanitized(verbose=True))
+    else:
+        print(build(verbose=True))
