@@ -1,44 +1,71 @@
 """Green's formula through the library (the accuracy experiment of Section 6.1, at small
 size): for u the potential of a unit charge outside the surface, S(du/dn) - D(u) = u at the
-interior-side limit.  The residual must fall as p_fmm grows and stay under the a-priori
-acceleration factor (3/4)^(p_fmm+1) once p_fmm exceeds p_qbx; with a single box (no
-acceleration) it is the plain QBX error."""
+interior-side limit.  The surface is discretized as the paper's stage-2 pair (density on
+element nodes, an oversampled quadrature on the same elements).  The accelerated residual
+is compared with the residual of the direct (unaccelerated) QBX oracle on the same inputs:
+their difference is the acceleration error, which must stay under Theorem 1's factor
+(3/4)^(p_fmm+1) and fall as p_fmm grows."""
 
 import numpy as np
 import pytest
 
-from workloads import workload_tiny
+import oracle as O
+from workloads import oversampled_workload
+from workloads.geometry import SurfaceSpec
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+URCHIN = SurfaceSpec(curved=True, bump_k=8, bump_m=4, bump_a=0.2)
+X0 = np.array([3.0, 1.0, 2.0])
 
 
-def _residual(w, p_fmm, p_qbx, nmax):
+def _inputs(kern, p_qbx, p_fmm, nmax):
+    w = oversampled_workload("greens", level=1, spec=URCHIN, kernel=kern, p_qbx=p_qbx,
+                             p_fmm=p_fmm, node_order=4, quad_order=4, sub=4,
+                             sides="interior", nmax=nmax)
+    d = w.node_xyz - X0
+    r = np.linalg.norm(d, axis=1)
+    u = 1.0 / r
+    dudn = -np.sum(d * w.node_normal, axis=1) / r ** 3
+    w.density = (dudn if kern == "S" else u)[None, :]
+    return w, u
+
+
+def _residual_gpu(p_fmm, p_qbx, nmax):
     import torch
 
     import paper_1805_06106_amd  # noqa: F401
     from paper_1805_06106_amd import Plan
 
-    x0 = np.array([3.0, 1.0, 2.0])
-    d = w.src_xyz - x0
-    r = np.linalg.norm(d, axis=1)
-    u = 1.0 / r
-    dudn = -np.sum(d * w.src_normal, axis=1) / r ** 3
     pots = {}
-    for kern, dens in (("S", dudn), ("D", u)):
-        P = Plan.from_workload(w, kernel=kern, p_fmm=p_fmm, p_qbx=p_qbx, nmax=nmax)
-        pots[kern] = P.apply(torch.tensor(dens[None, :], device="cuda:0"))[0].cpu().numpy()
-    inner = np.arange(1, w.n_tgt, 2)
-    E = pots["S"][inner] - pots["D"][inner] - u[inner // 2]
-    return float(np.max(np.abs(E)) / np.max(np.abs(u)))
+    for kern in ("S", "D"):
+        w, u = _inputs(kern, p_qbx, p_fmm, nmax)
+        P = Plan.from_workload(w)
+        pots[kern] = P.apply(torch.tensor(w.density, device="cuda:0"))[0].cpu().numpy()
+        P.close()
+    return pots["S"] - pots["D"] - u, u
 
 
-def test_greens_formula_residual_pattern():
-    w = workload_tiny(level=3, order=4, kernel="S", p_qbx=3, p_fmm=10, nmax=64)
-    print(f"[gpu] greens n_src={w.n_src}", flush=True)
-    plain = _residual(w, 10, 3, nmax=10 ** 7)  # one box: unaccelerated QBX
-    errs = {p: _residual(w, p, 3, nmax=64) for p in (3, 5, 10, 15)}
-    print(f"[gpu] greens plain {plain:.3e} accelerated {errs}", flush=True)
-    for p, e in errs.items():
-        assert abs(e - plain) <= 0.75 ** (p + 1)
-    assert abs(errs[15] - plain) <= 1e-3 * plain + 1e-12
-    assert errs[3] >= errs[15]
+def _residual_direct(p_qbx):
+    pots = {}
+    for kern in ("S", "D"):
+        w, u = _inputs(kern, p_qbx, p_qbx, 512)
+        pots[kern], _ = O.direct_qbx(kern, p_qbx, w.src_xyz, O.strengths(w)[0], w.ctr_xyz,
+                                     w.tgt_xyz, w.tgt_center, nrm=w.src_normal)
+    return pots["S"] - pots["D"] - u
+
+
+@pytest.mark.parametrize("p_qbx", [3, 5])
+def test_greens_formula_vs_direct_qbx(p_qbx):
+    EA = _residual_direct(p_qbx)
+    diffs = {}
+    for p_fmm in (p_qbx, 6, 10, 15):
+        E, u = _residual_gpu(p_fmm, p_qbx, nmax=48)
+        scale = np.max(np.abs(u))
+        diffs[p_fmm] = float(np.max(np.abs(E - EA)) / scale)
+        print(f"[gpu] greens q={p_qbx} p_fmm={p_fmm}: residual {np.max(np.abs(E)) / scale:.3e}, "
+              f"direct QBX {np.max(np.abs(EA)) / scale:.3e}, acceleration {diffs[p_fmm]:.3e}",
+              flush=True)
+        assert diffs[p_fmm] <= 0.75 ** (p_fmm + 1)
+    assert diffs[15] < diffs[p_qbx]
+    assert diffs[15] <= 1e-2 * float(np.max(np.abs(EA)) / np.max(np.abs(u)))
