@@ -240,6 +240,22 @@ gq_status gq_set_target_normals(gq_plan* plan, const double* tgt_normal);
 gq_status gq_set_source_interp(gq_plan* plan, int64_t n_elem, int n_node, int n_quad,
                                const double* interp);
 
+/*
+ * gq_points_near without device allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, result and errors as gq_points_near; every device buffer of the query (cell
+ * starts, sorted points, queries, radii, flags) lives in one fixed scratch array of 32 MiB
+ * per GPU, held until the process ends.  The grid is limited to 2^20 cells (wider cells
+ * only add candidates).  A query whose buffers exceed the scratch (about
+ * 24 n_p + 33 n_q bytes plus the cell starts) returns GQ_EINVAL with outputs untouched.
+ * Calls share the scratch of their GPU: calls that overlap in time on one GPU (from several
+ * host threads) race and must be serialized by the caller; a call returns only when its
+ * result is on the host.
+ */
+gq_status gq_points_near_noalloc(int64_t n_q, const double* q_xyz, const double* radius,
+                                 int strict, int64_t n_p, const double* p_xyz, uint8_t* hit,
+                                 void* hip_stream);
+
 /* Target association results (gq_associate_targets) besides a center index. */
 #define GQ_TARGET_FAR (-1)        /* no source endangers it: a conventional target */
 #define GQ_TARGET_UNMATCHED (-2)  /* endangered, but no admissible center is close enough */

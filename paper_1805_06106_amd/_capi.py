@@ -44,7 +44,8 @@ STAGES = ("strength", "p2m", "m2m", "m2l", "p2l", "l2l", "p2qbxl", "m2qbxl", "l2
 EXPORTED = ("gq_plan_create", "gq_apply", "gq_stats", "gq_plan_destroy", "gq_last_error",
             "gq_tree_export", "gq_list_export", "gq_qbx_locals", "gq_translation_matrix",
             "gq_batch_create", "gq_set_target_normals", "gq_set_source_interp",
-            "gq_associate_targets", "gq_points_near", "gq_set_overlap")
+            "gq_associate_targets", "gq_points_near", "gq_set_overlap",
+            "gq_points_near_noalloc")
 GQ_TARGET_FAR = -1
 GQ_TARGET_UNMATCHED = -2
 
@@ -118,6 +119,8 @@ def lib():
         L.gq_set_source_interp.restype = i32
         L.gq_points_near.restype = i32
         L.gq_points_near.argtypes = [ctypes.c_int64, P, P, i32, ctypes.c_int64, P, P, P]
+        L.gq_points_near_noalloc.restype = i32
+        L.gq_points_near_noalloc.argtypes = [ctypes.c_int64, P, P, i32, ctypes.c_int64, P, P, P]
         L.gq_associate_targets.restype = i32
         L.gq_associate_targets.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, P, P,
                                            ctypes.c_int64, P, P, ctypes.c_double, P, P]
@@ -213,15 +216,18 @@ def gq_set_source_interp(plan, n_elem, interp):
                                       int(n_quad), _ptr(interp)))
 
 
-def gq_points_near(q_xyz, radius, p_xyz, strict=False, stream=None):
-    """Host bool array: is some point of p_xyz within radius[i] of q_xyz[i] (< if strict)?"""
+def gq_points_near(q_xyz, radius, p_xyz, strict=False, stream=None, noalloc=False):
+    """Host bool array: is some point of p_xyz within radius[i] of q_xyz[i] (< if strict)?
+    noalloc=True calls gq_points_near_noalloc (device buffers in the library's fixed
+    scratch, no device allocation)."""
     q_xyz = np.ascontiguousarray(np.asarray(q_xyz, dtype=np.float64).reshape(-1, 3))
     p_xyz = np.ascontiguousarray(np.asarray(p_xyz, dtype=np.float64).reshape(-1, 3))
     radius = np.ascontiguousarray(np.broadcast_to(np.asarray(radius, dtype=np.float64),
                                                   (q_xyz.shape[0],)))
     hit = np.empty(q_xyz.shape[0], dtype=np.uint8)
-    _check(lib().gq_points_near(q_xyz.shape[0], _ptr(q_xyz), _ptr(radius), int(bool(strict)),
-                                p_xyz.shape[0], _ptr(p_xyz), _ptr(hit), _stream(stream)))
+    fn = lib().gq_points_near_noalloc if noalloc else lib().gq_points_near
+    _check(fn(q_xyz.shape[0], _ptr(q_xyz), _ptr(radius), int(bool(strict)),
+              p_xyz.shape[0], _ptr(p_xyz), _ptr(hit), _stream(stream)))
     return hit.astype(bool)
 
 

@@ -34,7 +34,7 @@ def build(verbose: bool = False) -> str:
         jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, f),
                      "-o", os.path.join(BUILD, f + ".o")])
     hip_sources = ("kernels.hip", "kernels_p2x.hip", "kernels_pt.hip", "kernels_rot.hip",
-                   "oversample.hip", "associate.hip", "executor.hip")
+                   "oversample.hip", "associate.hip", "executor.hip", "noalloc.hip")
     for f in hip_sources:
         jobs.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, f),
                      "-o", os.path.join(BUILD, f + ".o")])
@@ -66,7 +66,7 @@ def build_sanitized(verbose: bool = False) -> str:
                      "-ffp-contract=off", "-fsanitize=address,undefined", *san, "-c",
                      os.path.join(CSRC, f), "-o", os.path.join(SAN_BUILD, f + ".o")])
     hip_sources = ("kernels.hip", "kernels_p2x.hip", "kernels_pt.hip", "kernels_rot.hip",
-                   "oversample.hip", "associate.hip", "executor.hip")
+                   "oversample.hip", "associate.hip", "executor.hip", "noalloc.hip")
     for f in hip_sources:
         jobs.append(["hipcc", *HIP_FLAGS, "-Xarch_host", "-fsanitize=address,undefined", *san,
                      "-c", os.path.join(CSRC, f), "-o", os.path.join(SAN_BUILD, f + ".o")])
