@@ -33,7 +33,7 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
     "kernels_sha256": "842cae395184d928ff85af239e7e1c5547c5b6fc763143ced1e0487ca1526e35",
-    "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True,
+    "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True, "nmax": 512,
     "precision": "fp64",
     "bytes_per_launch": {"p2qbxl": 8.09767e+09, "m2l": 1.40425e+10, "m2qbxl": 9.26699e+07,
                          "l2qbxl": 9.46716e+08},
@@ -49,7 +49,7 @@ def tree_opts(args):
     return opts
 
 
-def counter_traffic(kernel, workload, wfar_direct_max, level_restrict):
+def counter_traffic(kernel, workload, wfar_direct_max, level_restrict, nmax):
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_1805_06106_amd", "csrc")
@@ -62,7 +62,7 @@ def counter_traffic(kernel, workload, wfar_direct_max, level_restrict):
     c = COUNTER_TRAFFIC
     if (h != c["kernels_sha256"] or workload != c["workload"]
             or wfar_direct_max != c["wfar_direct_max"]
-            or level_restrict != c.get("level_restrict", False)):
+            or level_restrict != c.get("level_restrict", False) or nmax != c.get("nmax")):
         return None
     return c["bytes_per_launch"].get(kernel)
 
@@ -101,7 +101,12 @@ def main():
     ap.add_argument("--surfaces", type=int, default=8,
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
     ap.add_argument("--nmax", type=int, default=None,
-                    help="override the workload's nmax (512, the paper's choice, by default)")
+                    help="most particles (sources + centers + targets) of a box before it is "
+                         "split; default 192 for the urchin workloads (c2, c3, c5; measured "
+                         "optimum), the workload's own (512, the paper's choice) otherwise")
+    ap.add_argument("--c3-modes", default="fp64,fp32_split,fp32_lead",
+                    help="c3 only: precision modes of the batch plan, comma-separated (fp64 "
+                         "first: its member plans are the plain FP64 ones)")
     ap.add_argument("--c3-direct", type=int, default=0,
                     help="c3 only: random centers per surface checked against the direct QBX "
                          "oracle, every density (0: none)")
@@ -164,6 +169,12 @@ def main():
             args.wfar_direct_max = round(CM.m2qbxl_pair(p, q) / CM.p2qbxl_pair(q, k))
         else:
             args.wfar_direct_max = 64
+    if args.nmax is None and args.workload in ("c2", "c3", "c5") and args.study is None:
+        # the urchin workloads (D, 5/15): nmax 192, the measured optimum on one MI355X
+        # (32.3-32.5 ms per apply against 43.3 ms at the paper's 512; 33.5 at 128, 36.6 at
+        # 256, 39.1 at 384): smaller leaves move work from the near field to M2L, which the
+        # matrix cores run at a higher fraction of their peak
+        args.nmax = 192
 
     if args.study == "scaling":
         return study_scaling(args)
@@ -252,11 +263,12 @@ def main():
     dominant = max(kern_stage, key=lambda s: stage_ms[kern_stage[s]])
     dom_ms = stage_ms[kern_stage[dominant]]
     achieved = flops[dominant] / (dom_ms * 1e-3) / 1e12
-    roofline = {"kernel": dominant, "bound": "alu", "achieved": round(achieved, 3),
+    roofline = {"kernel": dominant, "bound": "mfma" if dominant == "m2l" else "alu",
+                "achieved": round(achieved, 3),
                 "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
                 "traffic": counter_traffic(dominant, w.name, args.wfar_direct_max,
-                                           bool(args.level_restrict)),
+                                           bool(args.level_restrict), args.nmax or w.nmax),
                 "flops_per_launch": flops[dominant], "ms_per_launch": round(dom_ms, 4)}
     if alone:
         # the same kernel with the far field not running beside it
@@ -330,8 +342,10 @@ def main():
         dt = time.perf_counter() - t0
         got = pot[0].cpu().numpy()[tids]
         err_direct = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                      if ln.startswith("model name")), "unknown")
         cpu = {"value": round(len(tids) / dt, 3), "unit": "target evals/s", "cores": int(used),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": model,
                "sample": f"direct (unaccelerated) FP64 QBX on {len(cids)} random centers of "
                          f"{w.n_ctr}, each from all {w.n_src} sources; {dt:.1f}s"}
         log(f"cpu baseline {cpu['value']} evals/s on {used} threads; rel err vs direct {err_direct:.3e}")
@@ -383,7 +397,7 @@ def study_greens(args, dev):
     vanishes up to the discretization, truncation and acceleration errors.  The surface is
     discretized as the paper's stage-2 pair: u and du/dn live on 45 nodes per element
     (degree 8) and the layer potentials use an oversampled quadrature on the same elements
-    (the degree-8 collapsed rule on each of 64 sub-triangles).  Reported: max |E| / max |u|
+    (the degree-8 collapsed rule on each of 16 sub-triangles).  Reported: max |E| / max |u|
     for each p_fmm x p_qbx (p_qbx <= p_fmm), beside the a-priori factor (3/4)^(p_fmm + 1)
     of the acceleration error."""
     import numpy as np
@@ -398,7 +412,7 @@ def study_greens(args, dev):
     t0 = time.time()
     w = oversampled_workload(f"urchin8-{20 * 4 ** args.level}-stage2", level=args.level,
                              spec=spec, kernel="S", p_qbx=3, p_fmm=3, node_order=8,
-                             quad_order=8, sub=8, sides="interior")
+                             quad_order=8, sub=4, sides="interior")
     d = w.node_xyz - x0
     r = np.linalg.norm(d, axis=1)
     u = 1.0 / r
@@ -716,9 +730,26 @@ def bench_batch(args, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3 / k
 
+    from concurrent.futures import ThreadPoolExecutor
+
+    def make_plans(prec):
+        # host planning runs in the library without the GIL: 8 plans at a time
+        out = [None] * len(ws)
+
+        def one(k):
+            out[k] = Plan.from_workload(ws[k], n_densities=nd, precision=prec,
+                                        **tree_opts(args))
+            return k
+
+        with ThreadPoolExecutor(max_workers=8) as ex:
+            for i, _ in enumerate(ex.map(one, range(len(ws)))):
+                if i % 8 == 7:
+                    log(f"[{prec}] {i + 1} of {len(ws)} plans")
+        return out
+
     # plain FP64: one plan per surface, applied one after another
     t0 = time.time()
-    plans = [Plan.from_workload(w, n_densities=nd, **tree_opts(args)) for w in ws]
+    plans = make_plans("fp64")
     plan64_s = time.time() - t0
     ref = torch.empty((nd, n_tgt), dtype=torch.float64, device=dev)
     dsl = [dall[:, offs_s[k]:offs_s[k + 1]].contiguous() for k in range(len(ws))]
@@ -735,11 +766,10 @@ def bench_batch(args, dev):
     log(f"plain fp64: {ms_plain:.2f} ms per batch apply ({plan64_s:.1f}s of plans)")
     res = {}
     pots = {}
-    for prec in ("fp64", "fp32_split", "fp32_lead"):
+    for prec in args.c3_modes.split(","):
         t0 = time.time()
-        members = plans if prec == "fp64" else [
-            Plan.from_workload(w, n_densities=nd, **tree_opts(args), precision=prec)
-            for w in ws]
+        members = plans if prec == "fp64" else make_plans(prec)
+        log(f"[{prec}] merging {len(members)} plans into one batch plan")
         B = Plan.batch(members, graph=True, autotune=True)
         for P in members:
             P.close()
@@ -758,6 +788,8 @@ def bench_batch(args, dev):
         pots[prec] = out.cpu().numpy() if args.c3_direct > 0 else None
         B.close()
         del out
+    for P in plans:  # the plain plans, if no FP64 batch took them over
+        P.close()
     direct = None
     if args.c3_direct > 0:
         import oracle as O
@@ -803,8 +835,7 @@ def bench_batch(args, dev):
         "plain_fp64": {"value": round(nd * n_tgt / (ms_plain * 1e-3), 1),
                        "ms_per_apply": round(ms_plain, 3), "plan_seconds": round(plan64_s, 2)},
         "batched_fp64_graph": res["fp64"],
-        "batched_fp32_split_graph": res["fp32_split"],
-        "batched_fp32_lead_graph": res["fp32_lead"],
+        **{f"batched_{p}_graph": r for p, r in res.items()},
         "vs_direct_qbx": direct,
     }
     print(json.dumps(out), flush=True)

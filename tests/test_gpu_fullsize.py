@@ -1,7 +1,7 @@
 """GPU parity at full size, in the benchmark's launch configuration.
 
 The urchin (573,440 sources, 1,146,880 centers, double layer, p_qbx = 5, p_fmm = 15,
-level-restricted tree, Remark 4 threshold 64) and the ellipsoid (2,293,760 sources, single layer, 8/20) are
+nmax 192, level-restricted tree, Remark 4 threshold 64) and the ellipsoid (2,293,760 sources, single layer, 8/20) are
 evaluated whole on the GPU.  The oracle checks sampled centers: Tier B evaluates the same
 GIGAQBX algorithm one center at a time (its own tree and lists), Tier A the direct QBX sum.
 Bars: 1e-8 relative to the sampled oracle values' l-inf norm against Tier B (asserted at
@@ -17,7 +17,7 @@ from workloads import workload_c2, workload_c4
 
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
 TOL = 1e-10
-BENCH_TREE = dict(wfar_direct_max=64, level_restrict=True)  # bench.py's defaults
+BENCH_TREE = dict(wfar_direct_max=64, level_restrict=True, nmax=192)  # bench.py's urchin defaults
 
 
 def rel(a, b):
