@@ -32,11 +32,11 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "842cae395184d928ff85af239e7e1c5547c5b6fc763143ced1e0487ca1526e35",
-    "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True, "nmax": 512,
+    "kernels_sha256": "a93abe8cbbb4883466479c58467ae818abb2944f57a3786bd3979d17b56be937",
+    "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True, "nmax": 192,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 8.09767e+09, "m2l": 1.40425e+10, "m2qbxl": 9.26699e+07,
-                         "l2qbxl": 9.46716e+08},
+    "bytes_per_launch": {"p2qbxl": 6.60338e+09, "m2l": 2.292756e+10, "m2qbxl": 1.651e+07,
+                         "l2qbxl": 9.9188e+08},
 }
 
 
@@ -397,7 +397,7 @@ def study_greens(args, dev):
     vanishes up to the discretization, truncation and acceleration errors.  The surface is
     discretized as the paper's stage-2 pair: u and du/dn live on 45 nodes per element
     (degree 8) and the layer potentials use an oversampled quadrature on the same elements
-    (the degree-8 collapsed rule on each of 16 sub-triangles).  Reported: max |E| / max |u|
+    (the degree-8 collapsed rule on each of 64 sub-triangles).  Reported: max |E| / max |u|
     for each p_fmm x p_qbx (p_qbx <= p_fmm), beside the a-priori factor (3/4)^(p_fmm + 1)
     of the acceleration error."""
     import numpy as np
@@ -412,7 +412,7 @@ def study_greens(args, dev):
     t0 = time.time()
     w = oversampled_workload(f"urchin8-{20 * 4 ** args.level}-stage2", level=args.level,
                              spec=spec, kernel="S", p_qbx=3, p_fmm=3, node_order=8,
-                             quad_order=8, sub=4, sides="interior")
+                             quad_order=8, sub=8, sides="interior")
     d = w.node_xyz - x0
     r = np.linalg.norm(d, axis=1)
     u = 1.0 / r

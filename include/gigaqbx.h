@@ -232,7 +232,7 @@ gq_status gq_set_target_normals(gq_plan* plan, const double* tgt_normal);
  *   q_{e*n_quad + j} = w_{e*n_quad + j} * sum_k interp[j*n_node + k] * density[e*n_node + k]
  * The plan's sources must be the quadrature nodes in element-major order, so
  * n_src = n_elem * n_quad.  interp: host, [n_quad][n_node] row-major (copied);
- * 1 <= n_node <= 64, 1 <= n_quad, n_quad * n_node <= 65536.  May be called again to change
+ * 1 <= n_node <= 64, 1 <= n_quad, n_quad * n_node <= 2^20.  May be called again to change
  * the matrix; a captured graph of the plan is recaptured at the next apply.
  * Errors: GQ_EINVAL for a host-only plan, sizes that do not match the plan's sources or
  * exceed the limits, or non-finite entries; GQ_EUNSUPPORTED for a batch plan.

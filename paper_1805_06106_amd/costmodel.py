@@ -86,10 +86,11 @@ def qbxl2p_target(q: int) -> int:
 # FP64 flops per unit that the kernels execute, counted on the GPU with rocprofv3
 # (64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_MUL_F64 + SQ_INSTS_VALU_ADD_F64) over
 # one launch, divided by the launch's units) on the urchin (double layer, p_qbx = 5,
-# p_fmm = 15).  Where a configuration has no count, the written models above are used.
-COUNTED_P2QBXL_PAIR = {(5, "D"): 526.4}      # near field, per (source, center) pair
-COUNTED_P2M_SOURCE = {(15, "D"): 8706.0}     # P2M, per source
-COUNTED_P2L_FLOPS_URCHIN = 5.658e10          # P2L, the whole launch on the urchin
+# p_fmm = 15, nmax 192, level-restricted tree, Remark 4 at 64; the near field counted 526.4
+# per pair at nmax 512, where its items are larger).  Where a configuration has no count,
+# the written models above are used.
+COUNTED_P2QBXL_PAIR = {(5, "D"): 532.9}      # near field, per (source, center) pair
+COUNTED_P2M_SOURCE = {(15, "D"): 9327.0}     # P2M, per source
 
 
 def p2qbxl_pair_counted(q: int, kernel: str) -> float:

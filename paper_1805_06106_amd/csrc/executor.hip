@@ -308,8 +308,6 @@ void near_center_items(const gq::Tree& T, int b, std::vector<int>& box, std::vec
   }
 }
 
-// Near-field items, most expensive first (passes over the near sources times slice length),
-// so that the longest workgroups start early.
 // Stage 8 items of at most 32 centers go two to a wave, one per half-wave: the arrays hold
 // the single items first, then the pairs as consecutive entries.  Rebuilds the order from
 // any input order (a batch re-pairs its members' items).
@@ -341,6 +339,8 @@ void pair_center_items(gq_plan* P) {
   P->k8_nc.swap(nc);
 }
 
+// Near-field items, most expensive first (passes over the near sources times slice length),
+// so that the longest workgroups start early.
 void sort_near_items(gq_plan* P) {
   const size_t n = P->k3_box.size();
   std::vector<size_t> ord(n);
@@ -1797,9 +1797,9 @@ gq_status gq_set_source_interp(gq_plan* P, int64_t n_elem, int n_node, int n_qua
   g_err.clear();
   if (!P || !interp) return fail(GQ_EINVAL, "NULL argument");
   if (P->is_batch) return fail(GQ_EUNSUPPORTED, "a batch plan cannot take a source interpolation");
-  if (n_node < 1 || n_node > 64 || n_quad < 1 || (int64_t)n_quad * n_node > 65536)
+  if (n_node < 1 || n_node > 64 || n_quad < 1 || (int64_t)n_quad * n_node > (1 << 20))
     return fail(GQ_EINVAL, "interpolation size out of range (1 <= n_node <= 64, "
-                           "n_quad * n_node <= 65536)");
+                           "n_quad * n_node <= 2^20)");
   if (n_elem < 1 || n_elem * n_quad != P->n_src)
     return fail(GQ_EINVAL, "n_elem * n_quad must equal the plan's source count");
   const int64_t nm = (int64_t)n_quad * n_node;

@@ -4,7 +4,7 @@
 // quadrature node's value is the element's interpolant at that node, times its weight:
 //   q_i = w_i * sum_k A[f][k] * mu[e * n_node + k],   (e, f) = divmod(input index of i, n_quad)
 // One thread per source in tree order.  Neighbouring threads mostly share an element, so the
-// node values and the matrix rows (at most 64K entries) are served from L1/L2; the kernel is
+// node values and the matrix rows (at most 2^20 entries) are served from L1/L2; the kernel is
 // bound by the strength write and the index reads (24 B per source plus the node values).
 #include <hip/hip_runtime.h>
 
