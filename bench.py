@@ -102,8 +102,9 @@ def main():
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
     ap.add_argument("--nmax", type=int, default=None,
                     help="most particles (sources + centers + targets) of a box before it is "
-                         "split; default 192 for the urchin workloads (c2, c3, c5; measured "
-                         "optimum), the workload's own (512, the paper's choice) otherwise")
+                         "split; default: the measured optimum, 192 for the urchin workloads "
+                         "(c2, c3, c5) and 256 for the ellipsoid (c4); the workload's own "
+                         "(512, the paper's choice) for c1")
     ap.add_argument("--c3-modes", default="fp64,fp32_split,fp32_lead",
                     help="c3 only: precision modes of the batch plan, comma-separated (fp64 "
                          "first: its member plans are the plain FP64 ones)")
@@ -169,12 +170,13 @@ def main():
             args.wfar_direct_max = round(CM.m2qbxl_pair(p, q) / CM.p2qbxl_pair(q, k))
         else:
             args.wfar_direct_max = 64
-    if args.nmax is None and args.workload in ("c2", "c3", "c5") and args.study is None:
-        # the urchin workloads (D, 5/15): nmax 192, the measured optimum on one MI355X
-        # (32.3-32.5 ms per apply against 43.3 ms at the paper's 512; 33.5 at 128, 36.6 at
-        # 256, 39.1 at 384): smaller leaves move work from the near field to M2L, which the
-        # matrix cores run at a higher fraction of their peak
-        args.nmax = 192
+    if args.nmax is None and args.study is None:
+        # nmax measured on one MI355X (smaller leaves move work from the near field to M2L,
+        # which the matrix cores run at a higher fraction of their peak): the urchin
+        # workloads (D, 5/15) 192 (32.3-32.5 ms per apply against 43.3 ms at the paper's
+        # 512; 33.5 at 128, 36.6 at 256, 39.1 at 384); the ellipsoid (S, 8/20) 256 (242.8 ms
+        # against 262.7 at 512 and 244.0 at 384)
+        args.nmax = {"c2": 192, "c3": 192, "c5": 192, "c4": 256}.get(args.workload)
 
     if args.study == "scaling":
         return study_scaling(args)

@@ -106,9 +106,10 @@ def ellipsoid():
     return workload_c4()
 
 
-# the ellipsoid's benchmark configuration: Remark 4 at the cost-model crossover of S 8/20
-# (335 sources), which leaves no W-far pair; a threshold of 64 keeps the W-far list busy
-C4_TREE = dict(wfar_direct_max=335, level_restrict=True)
+# the ellipsoid's benchmark configuration: nmax 256 and Remark 4 at the cost-model crossover
+# of S 8/20 (335 sources), which leaves no W-far pair; a threshold of 64 keeps the W-far
+# list busy
+C4_TREE = dict(wfar_direct_max=335, level_restrict=True, nmax=256)
 
 
 def _clustered_centers(F, w, rng, n_boxes, per_box):
