@@ -3,7 +3,7 @@
 
 Workload (default): the 'urchin' surface rho = 1 + 0.2 Re Y_8^4 on 20,480 curved triangles,
 28 nodes per triangle (573,440 sources), two QBX centers per node (1,146,880 centers, one
-target each), double-layer potential, p_qbx = 5, p_fmm = 15, nmax = 512, t_f = 0.9, FP64;
+target each), double-layer potential, p_qbx = 5, p_fmm = 15, nmax = 192, t_f = 0.9, FP64;
 level-restricted tree, Remark 4 at 64 sources (both paper options, measured fastest here).
 One step = one full evaluation (Algorithm 5 Stages 2-9) of one density with the plan cached
 and all inputs resident in HBM.
@@ -114,6 +114,15 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=768,
                     help="centers evaluated by the CPU oracle (direct QBX) for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-c1", type=int, choices=[0, 1], default=1,
+                    help="1 (default): also time the CPU oracles on the small sphere (4,800 "
+                         "sources, S 3/10) in full: direct QBX on one core and on all cores, "
+                         "and the step-by-step GIGAQBX oracle, beside this GPU on the same "
+                         "workload (about 40 s of CPU)")
+    ap.add_argument("--cpu-tier-b", type=int, default=0,
+                    help="centers of the main workload evaluated by the step-by-step GIGAQBX "
+                         "oracle (the algorithmic CPU baseline; 0: none; 64 take about 40 s "
+                         "on 8 cores, tree and lists included)")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the split-precision (FP32 matrix-core) translation runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -351,6 +360,10 @@ def main():
                "sample": f"direct (unaccelerated) FP64 QBX on {len(cids)} random centers of "
                          f"{w.n_ctr}, each from all {w.n_src} sources; {dt:.1f}s"}
         log(f"cpu baseline {cpu['value']} evals/s on {used} threads; rel err vs direct {err_direct:.3e}")
+        if args.cpu_tier_b > 0:
+            cpu["tier_b"] = cpu_tier_b_sample(args, w, pot[0].cpu().numpy(), int(used))
+        if args.cpu_c1:
+            cpu["c1"] = cpu_c1(args, dev)
 
     out = {
         "metric": "QBX-FMM target evals/sec at stated rel. error; M2L MFMA util (FP32 vs FP64)",
@@ -389,6 +402,94 @@ def main():
         "tree": {"boxes": st["n_boxes"], "levels": st["n_levels"], "pairs": st["pairs"]},
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_tier_b_sample(args, w, got, cores):
+    """The step-by-step GIGAQBX oracle on a random sample of centers of the main workload,
+    with the plan's tree options, on all host cores: the algorithmic CPU baseline."""
+    import numpy as np
+
+    from oracle.gigaqbx import OracleFMM
+
+    rng = np.random.default_rng(54321)
+    cids = np.sort(rng.choice(w.n_ctr, args.cpu_tier_b, replace=False))
+    log(f"cpu tier b: step-by-step oracle on {len(cids)} centers")
+    t0 = time.perf_counter()
+    F = OracleFMM(w, nmax=args.nmax or w.nmax, wfar_direct_max=args.wfar_direct_max,
+                  level_restrict=bool(args.level_restrict))
+    t1 = time.perf_counter()
+    tids, ref, _ = F.evaluate(0, centers=cids)
+    dt = time.perf_counter() - t0
+    err = float(np.max(np.abs(got[tids] - ref)) / np.max(np.abs(ref)))
+    out = {"value": round(len(tids) / dt, 4), "unit": "target evals/s",
+           "cores": cores, "kind": "oracle (step-by-step GIGAQBX)",
+           "sample": f"{len(cids)} random centers of {w.n_ctr}; tree and lists "
+                     f"{t1 - t0:.1f}s, evaluation {dt - (t1 - t0):.1f}s",
+           "gpu_rel_err_vs_it": err}
+    log(f"cpu tier b {out['value']} evals/s ({dt:.1f}s); GPU vs it {err:.3e}")
+    return out
+
+
+def cpu_c1(args, dev):
+    """The small sphere (4,800 sources, 9,600 targets, single layer, 3/10) in full: direct
+    QBX on one core and on all cores, the step-by-step GIGAQBX oracle on one thread, and the
+    GPU apply on the same inputs."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from oracle.gigaqbx import OracleFMM
+    from paper_1805_06106_amd import Plan
+
+    w = make_workload("c1")
+    cids = np.arange(w.n_ctr)
+    # all cores first: a one-thread request stays in force for the process's later calls
+    t0 = time.perf_counter()
+    tids, ref, used_n = O.direct_qbx_sampled(
+        w, cids, density_index=0,
+        nthreads=int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count())
+    dn = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, ref_1, used1 = O.direct_qbx_sampled(w, cids, density_index=0, nthreads=1)
+    d1 = time.perf_counter() - t0
+    assert np.array_equal(tids, np.arange(w.n_tgt))
+    scale = np.max(np.abs(ref))
+    res = {"workload": w.name, "n_sources": w.n_src, "n_targets": w.n_tgt,
+           "direct_1core_vs_all_cores": float(np.max(np.abs(ref_1 - ref)) / scale)}
+    t0 = time.perf_counter()
+    F = OracleFMM(w, nthreads=1)
+    tb_ids, tb, _ = F.evaluate(0)
+    db = time.perf_counter() - t0
+    tb_full = np.empty(w.n_tgt)
+    tb_full[tb_ids] = tb
+    plan = Plan.from_workload(w, timing=False)
+    dens = torch.tensor(w.density[:1], dtype=torch.float64, device=dev)
+    pot = torch.empty((1, w.n_tgt), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        plan.apply(dens, pot)
+    torch.cuda.synchronize()
+    n = 50
+    t0 = time.perf_counter()
+    for _ in range(n):
+        plan.apply(dens, pot)
+    torch.cuda.synchronize()
+    dg = (time.perf_counter() - t0) / n
+    got = pot[0].cpu().numpy()
+    plan.close()
+    res.update({
+        "direct_1core": {"value": round(w.n_tgt / d1, 1), "cores": int(used1), "seconds": round(d1, 2)},
+        "direct_all_cores": {"value": round(w.n_tgt / dn, 1), "cores": int(used_n),
+                             "seconds": round(dn, 2)},
+        "tier_b_1thread": {"value": round(w.n_tgt / db, 1), "cores": 1, "seconds": round(db, 2),
+                           "rel_err_vs_direct": float(np.max(np.abs(tb_full - ref)) / scale)},
+        "gpu": {"value": round(w.n_tgt / dg, 1), "ms_per_apply": round(dg * 1e3, 4),
+                "rel_err_vs_direct": float(np.max(np.abs(got - ref)) / scale)},
+        "unit": "target evals/s",
+    })
+    log(f"c1 in full: direct {res['direct_1core']['value']} evals/s on 1 core, "
+        f"{res['direct_all_cores']['value']} on {used_n}; tier b {res['tier_b_1thread']['value']} "
+        f"on 1 thread; GPU {res['gpu']['value']} ({dg * 1e3:.3f} ms)")
+    return res
 
 
 def study_greens(args, dev):

@@ -17,6 +17,8 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall"]
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
+# roctx stage ranges (rocprofiler-sdk's marker library, part of ROCm)
+LINK_FLAGS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def _run(cmd):
@@ -44,7 +46,7 @@ def build(verbose: bool = False) -> str:
                 print(out)
     objs = [os.path.join(BUILD, f + ".o") for f in ("planner.cpp", "translations.cpp", *hip_sources)]
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs])
+    _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, *LINK_FLAGS])
     os.replace(tmp, LIB)
     return LIB
 
@@ -78,7 +80,7 @@ def build_sanitized(verbose: bool = False) -> str:
                                                          *hip_sources)]
     tmp = SAN_LIB + ".tmp%d" % os.getpid()
     _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-shared-libsan",
-          "-Xarch_host", "-fsanitize=address,undefined", "-o", tmp, *objs])
+          "-Xarch_host", "-fsanitize=address,undefined", "-o", tmp, *objs, *LINK_FLAGS])
     os.replace(tmp, SAN_LIB)
     return SAN_LIB
 

@@ -91,6 +91,7 @@ def qbxl2p_target(q: int) -> int:
 # the written models above are used.
 COUNTED_P2QBXL_PAIR = {(5, "D"): 532.9}      # near field, per (source, center) pair
 COUNTED_P2M_SOURCE = {(15, "D"): 9327.0}     # P2M, per source
+COUNTED_P2L_PAIR = {(15, "D"): 9565.0}       # P2L, per (source, List 4 far box) pair
 
 
 def p2qbxl_pair_counted(q: int, kernel: str) -> float:
@@ -101,7 +102,8 @@ def apply_flops(stats: dict, p: int, q: int, kernel: str) -> dict:
     """Work of one apply, per stage, from the plan's interaction counts: the near field by
     its counted flops per pair where counted; the M2QBXL, L2QBXL and QBXL2P models; the
     dense translations at 2 (p+1)^4 per product (M2M and L2L: one product per box below
-    the root); P2M by its counted flops per source where counted (else omitted)."""
+    the root); P2M per source and P2L per (source, box) pair by their counted flops where
+    counted (else omitted)."""
     pr = stats["pairs"]
     near = pr["U"] + pr["Wclose"] + pr["Xclose"]
     out = {
@@ -115,6 +117,8 @@ def apply_flops(stats: dict, p: int, q: int, kernel: str) -> dict:
     }
     if (p, kernel) in COUNTED_P2M_SOURCE:
         out["p2m"] = stats["n_sources"] * COUNTED_P2M_SOURCE[(p, kernel)]
+    if (p, kernel) in COUNTED_P2L_PAIR:
+        out["p2l"] = pr["Xfar"] * COUNTED_P2L_PAIR[(p, kernel)]
     return out
 
 

@@ -1,5 +1,6 @@
 // Plan construction and the Algorithm 5 evaluation pipeline behind the C ABI.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <array>
@@ -1347,6 +1348,24 @@ namespace {
 
 // Enqueues every density pass of one apply on stream s (eager launches, or the launches
 // being captured into a graph).
+// One roctx range per stage of an apply, shown by rocprofv3 --marker-trace.  The ranges are
+// host-side: they bracket the enqueue of each stage's launches, and the kernel records of the
+// same trace give the device times.  Outside a profiler the calls return at once.
+class StageRanges {
+ public:
+  void next(const char* name) {
+    if (open_) roctxRangePop();
+    roctxRangePushA(name);
+    open_ = true;
+  }
+  ~StageRanges() {
+    if (open_) roctxRangePop();
+  }
+
+ private:
+  bool open_ = false;
+};
+
 gq_status apply_passes(gq_plan* P, const double* density, double* potential, hipStream_t s,
                        bool timing) {
   const gq::Tree& T = P->tree;
@@ -1370,6 +1389,8 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
       }
       ev = P->ev_sets[P->ev_used++].data();
     }
+    StageRanges rng;
+    rng.next("gq: strengths");
     GQ_TRY(mark(0, s));
     if (P->interp)
       gq::launch_strength_interp(s, P->n_src, P->src_order, P->sw, P->n_node, P->n_quad,
@@ -1378,6 +1399,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
       gq::launch_strength(s, P->n_src, P->src_order, P->sw, density + (int64_t)d * P->n_src,
                           P->q);
     GQ_TRY(mark(1, s));
+    rng.next("gq: clear expansions");
     gq::launch_fill(s, P->M, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->L, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->Lq, (int64_t)P->n_ctr * P->nq, 0.0);
@@ -1390,9 +1412,11 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
       GQ_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
       f = P->side;
     }
+    rng.next("gq: stage 2a P2M");
     gq::launch_p2m(f, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_ptr,
                    P->d_p2m_idx, P->bctr, P->bh, src, P->q, P->M);
     GQ_TRY(mark(3, f));
+    rng.next("gq: stage 2b M2M");
     for (int l = T.nlevels - 1; l >= 1; --l) {
       const auto& t = P->m2m_levels[l];
       const auto& dd = P->d_m2m[l];
@@ -1400,6 +1424,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
                            P->M, P->M, P->lvl_cols);
     }
     GQ_TRY(mark(4, f));
+    rng.next("gq: stage 4 M2L");
     if (P->prm.m2l_rotation)
       gq::launch_m2l_rot(f, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
                          P->d_m2l[3], P->d_m2l[4], P->rot, P->M, P->L, P->m2l_xcd);
@@ -1408,9 +1433,11 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
                            P->d_m2l[2], P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L,
                            P->m2l_cols, P->m2l_xcd);
     GQ_TRY(mark(5, f));
+    rng.next("gq: stage 6b P2L");
     gq::launch_p2l(f, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_ptr,
                    P->d_p2l_idx, P->bctr, P->bh, src, P->q, P->L);
     GQ_TRY(mark(6, f));
+    rng.next("gq: stage 7 L2L");
     for (int l = 1; l < T.nlevels; ++l) {
       const auto& t = P->l2l_levels[l];
       const auto& dd = P->d_l2l[l];
@@ -1419,6 +1446,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     }
     GQ_TRY(mark(7, f));
     // near field: writes only Lq and the point-target potentials
+    rng.next("gq: stages 3, 5a, 6a P2QBXL");
     GQ_TRY(mark(12, s));
     gq::launch_p2qbxl(s, kern, qo, (int)P->k3_box.size(), P->d_k3_box, P->d_k3_c0, P->d_k3_nc,
                       P->d_near_ptr, P->d_near_idx, src, P->q, P->cx, P->cy,
@@ -1431,18 +1459,21 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
       GQ_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
     }
     GQ_TRY(mark(13, s));
+    rng.next("gq: stage 5b M2QBXL");
     gq::launch_m2qbxl(s, p, qo, (int)P->k5_c0.size(), P->d_k5_c0, P->d_k5_nc, P->d_k5_w0,
                       P->d_k5_w1, P->d_wf_box, P->bctr, P->bh, P->M, P->cx, P->cy, P->cz,
                       P->Lq, P->n_ctr);
     gq::launch_m2p(s, p, (int)P->pm_t0.size(), P->d_pm_t0, P->d_pm_nt, P->d_pm_w0, P->d_pm_w1,
                    P->d_wf_box, P->bctr, P->bh, P->M, P->px, P->py, P->pz, P->phi);
     GQ_TRY(mark(9, s));
+    rng.next("gq: stage 8 L2QBXL");
     gq::launch_l2qbxl(s, p, qo, P->k8_nsingle, P->d_k8_box, P->d_k8_c0, P->d_k8_nc, P->bctr,
                       P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
     gq::launch_l2qbxl_pairs(s, p, qo, P->k8_npair, P->d_k8_box + P->k8_nsingle,
                             P->d_k8_c0 + P->k8_nsingle, P->d_k8_nc + P->k8_nsingle, P->bctr,
                             P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
     GQ_TRY(mark(10, s));
+    rng.next("gq: stage 9 QBXL2P");
     if (sprime)
       gq::launch_qbxl2p_grad(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->tnx, P->tny,
                              P->tnz, P->cx, P->cy, P->cz, P->Lq, P->n_ctr, P->tgt_out,
