@@ -125,6 +125,9 @@ def main():
                          "on 8 cores, tree and lists included)")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the split-precision (FP32 matrix-core) translation runs")
+    ap.add_argument("--no-det", action="store_true",
+                    help="skip the run of the deterministic plan (GQ_FLAG_DETERMINISTIC: "
+                         "bitwise-reproducible applies)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain elementwise copy (y = -x) over 1 GiB, so that a "
                          "hardware-counter pass can scale its byte counters by a kernel of "
@@ -217,12 +220,12 @@ def main():
     dens = torch.tensor(w.density[:1], dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def run(precision):
+    def run(precision, deterministic=False):
         t0 = time.time()
         plan = Plan.from_workload(w, timing=True, precision=precision,
                                   m2l_rotation=bool(args.m2l_rotation) and precision == "fp64",
                                   overlap=bool(args.overlap), autotune=bool(args.autotune),
-                                  **tree_opts(args))
+                                  deterministic=deterministic, **tree_opts(args))
         plan_wall = time.time() - t0
         st = plan.stats()
         log(f"[{precision}] plan: {st['n_boxes']} boxes, {st['n_levels']} levels, pairs "
@@ -243,6 +246,12 @@ def main():
         st = plan.stats()
         k = max(st["timed_applies"], 1)
         stage_ms = {s: v / k for s, v in st["stage_ms"].items()}
+        if deterministic:
+            # outside the timed region: one more apply must reproduce the last bit for bit
+            last = pot.clone()
+            plan.apply(dens, pot, stream=stream)
+            torch.cuda.synchronize()
+            st["repeat_bitwise_equal"] = bool(torch.equal(last, pot))
         log(f"[{precision}] {ms_per_step:.2f} ms/step, {w.n_tgt / (ms_per_step * 1e-3):.4g} "
             f"target evals/s; stage ms {stage_ms}")
         alone = None
@@ -339,6 +348,19 @@ def main():
             }
             log(f"[{prec}] rel err vs fp64 path {err:.3e}")
 
+    # reproducible applies (GQ_FLAG_DETERMINISTIC): per-pair slots and ordered sums
+    det = None
+    if not args.no_det:
+        ms_d, sm_d, st_d, _, pot_d, _ = run("fp64", deterministic=True)
+        det = {"value": round(w.n_tgt / (ms_d * 1e-3), 1), "ms_per_step": round(ms_d, 4),
+               "repeat_bitwise_equal": st_d["repeat_bitwise_equal"],
+               "rel_diff_vs_atomic_path": float((pot_d[0] - pot[0]).abs().max()
+                                                / pot[0].abs().max()),
+               "device_bytes": st_d.get("device_bytes"),
+               "stage_ms": {s: round(v, 4) for s, v in sm_d.items()}}
+        log(f"[deterministic] {ms_d:.2f} ms/step; repeat bitwise equal "
+            f"{det['repeat_bitwise_equal']}; vs atomic {det['rel_diff_vs_atomic_path']:.2e}")
+
     cpu = None
     err_direct = None
     if not args.no_cpu_baseline:
@@ -393,6 +415,7 @@ def main():
         "cpu_baseline": cpu,
         "m2l": m2l,
         "split_precision": split,
+        "deterministic": det,
         "stages": per_stage,
         "stage_ms": {s: round(v, 4) for s, v in stage_ms.items()},
         "one_stream": ({"ms_per_step": round(alone["ms_per_step"], 4), "steps": alone["steps"],

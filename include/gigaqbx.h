@@ -80,6 +80,17 @@ typedef enum { GQ_FP64 = 0, GQ_FP32_SPLIT = 1, GQ_FP32 = 2, GQ_FP32_LEAD = 3 } g
    XCD-aware or plain tile order on the plan's own tiles, and keep the fastest (reported in
    gq_stats_t).  Without it: XCD-aware order, width 32 (also for the rotation M2L). */
 #define GQ_FLAG_AUTOTUNE (1u << 3)
+/* Reproducible applies: every gq_apply of the plan returns the same bits for the same
+   density, and so does any plan built from the same inputs and parameters (the M2L tile
+   shape the autotuner picks does not matter).  The translations (M2M, M2L, L2L) store each
+   pair's result to a slot of its own and sum the slots of a destination in a fixed order
+   instead of adding atomically; P2M and P2L combine their partial sums in a fixed order;
+   List 3 far boxes are not split over several M2QBXL items.
+   Costs one slot of (p_fmm+1)^2 doubles per M2L pair of device memory (11 GB for 5.5M
+   pairs at p_fmm = 15) and the extra pass over it.  Without the flag, results of two
+   applies agree to rounding (about 1e-15 relative) but not bit for bit.  Batch members
+   must all have it or all lack it; the batch plan inherits it. */
+#define GQ_FLAG_DETERMINISTIC (1u << 4)
 /* Which interaction lists contribute (testing aid).  0 in bits 8..13 means all. */
 #define GQ_LIST_U (1u << 8)       /* List 1 (direct)            Stage 3 */
 #define GQ_LIST_V (1u << 9)       /* List 2 (M2L, then L2L)     Stages 4, 7, 8 */

@@ -29,6 +29,7 @@ GQ_FLAG_HOST_ONLY = 1 << 0
 GQ_FLAG_TIMING = 1 << 1
 GQ_FLAG_GRAPH = 1 << 2
 GQ_FLAG_AUTOTUNE = 1 << 3
+GQ_FLAG_DETERMINISTIC = 1 << 4
 GQ_LIST_U = 1 << 8
 GQ_LIST_V = 1 << 9
 GQ_LIST_WCLOSE = 1 << 10

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <numeric>
 #include <string>
 #include <thread>
 #include <vector>
@@ -168,6 +169,19 @@ struct gq_plan {
   gq::TransMats tm_m2m{}, tm_l2l{}, tm_m2l{};
   double *q = nullptr, *M = nullptr, *L = nullptr, *Lq = nullptr;
   double* interp = nullptr;  // [n_quad][n_node], set by gq_set_source_interp
+  // GQ_FLAG_DETERMINISTIC: every translation stores its result to a slot of its own (one
+  // per pair, np doubles each, shared by all tile sets) and an ordered sum per destination
+  // adds them in pair order
+  struct SlotSum {
+    int ndst = 0;
+    int* dst = nullptr;
+    int64_t* ptr = nullptr;
+    int* pair = nullptr;
+  };
+  bool det = false;
+  double* slots = nullptr;
+  SlotSum ss_m2l;
+  std::vector<SlotSum> ss_m2m, ss_l2l;  // index: child level
   // GQ_FLAG_GRAPH: the passes of one apply captured once per (density, potential) pair
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -489,8 +503,10 @@ gq_status build_work(gq_plan* P) {
         const int w0 = (int)P->wf_box.size();
         for (int64_t k = W.ptr[b]; k < W.ptr[b + 1]; ++k) P->wf_box.push_back(W.items[k]);
         const int w1 = (int)P->wf_box.size();
-        // (center chunk of <= 64) x (W-far chunk of <= kWfarChunk boxes) items
-        const int kWfarChunk = 4;
+        // (center chunk of <= 64) x (W-far chunk of <= kWfarChunk boxes) items; a
+        // deterministic plan keeps a center's whole list in one item, so that its single
+        // atomic add lands on a value fixed by the stages before it
+        const int kWfarChunk = (P->prm.flags & GQ_FLAG_DETERMINISTIC) ? (1 << 30) : 4;
         for (int64_t o = 0; o < T.ctr_count[b]; o += 64)
           for (int ws = w0; ws < w1; ws += kWfarChunk) {
             P->k5_c0.push_back((int)(T.ctr_start[b] + o));
@@ -747,6 +763,55 @@ gq_status upload_work(gq_plan* P) {
   return GQ_OK;
 }
 
+
+// GQ_FLAG_DETERMINISTIC: for every tile set, its destinations and the positions of their
+// pairs in ascending order, and one slot buffer for the largest tile set.  Pair positions
+// follow the class order of make_tiles (a stable sort), whatever the tile width, so the
+// sums are the same for every tile shape the autotuner may pick.  Called once the M2L
+// tiles are final.
+gq_status upload_slot_sums(gq_plan* P) {
+  if (!(P->prm.flags & GQ_FLAG_DETERMINISTIC) || (P->prm.flags & GQ_FLAG_HOST_ONLY))
+    return GQ_OK;
+  hipStream_t s = P->last_stream;
+  int64_t most = 0;
+  std::vector<std::vector<int>> keep_i;  // host copies alive until the uploads complete
+  std::vector<std::vector<int64_t>> keep_p;
+  auto one = [&](const TileSet& t, gq_plan::SlotSum& out) -> gq_status {
+    const int n = (int)t.dst.size();
+    most = std::max<int64_t>(most, n);
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return t.dst[a] < t.dst[b]; });
+    std::vector<int> dst;
+    std::vector<int64_t> ptr;
+    for (int i = 0; i < n; ++i)
+      if (i == 0 || t.dst[ord[i]] != t.dst[ord[i - 1]]) {
+        dst.push_back(t.dst[ord[i]]);
+        ptr.push_back(i);
+      }
+    ptr.push_back(n);
+    out.ndst = (int)dst.size();
+    GQ_TRY(upload(P, dst, &out.dst, s));
+    GQ_TRY(upload(P, ptr, &out.ptr, s));
+    GQ_TRY(upload(P, ord, &out.pair, s));
+    keep_i.push_back(std::move(dst));
+    keep_i.push_back(std::move(ord));
+    keep_p.push_back(std::move(ptr));
+    return GQ_OK;
+  };
+  const int nl = P->tree.nlevels;
+  P->ss_m2m.assign(nl, {});
+  P->ss_l2l.assign(nl, {});
+  for (int l = 0; l < nl; ++l) {
+    GQ_TRY(one(P->m2m_levels[l], P->ss_m2m[l]));
+    GQ_TRY(one(P->l2l_levels[l], P->ss_l2l[l]));
+  }
+  GQ_TRY(one(P->m2l, P->ss_m2l));
+  GQ_TRY(alloc(P, (size_t)most * P->np, &P->slots));
+  GQ_HIP(hipStreamSynchronize(s));
+  P->det = true;
+  return GQ_OK;
+}
 
 // ------------------------------------------------------------------------------------
 // Batches: several plans merged into one plan whose stages each run as one launch over
@@ -1331,6 +1396,7 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     };
     st = go();
     if (st == GQ_OK && (prm->flags & GQ_FLAG_AUTOTUNE)) st = autotune_m2l(P, s);
+    if (st == GQ_OK) st = upload_slot_sums(P);
     if (st != GQ_OK) {
       delete P;
       return st;
@@ -1380,6 +1446,20 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     if (timing) GQ_HIP(hipEventRecord(ev[i], st));
     return GQ_OK;
   };
+  // one batch of dense translations, Y[dst] += T X[src]: added atomically, or (deterministic
+  // plans) stored to the pair slots and summed per destination in pair order
+  auto translate = [&](hipStream_t st, int kind, const TileSet& t, const std::array<int*, 5>& dd,
+                       const gq::TransMats& tm, const double* X, double* Y, int cols, bool xcd,
+                       const gq_plan::SlotSum* ss) {
+    if (P->det) {
+      gq::launch_translate(st, kind, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], tm,
+                           X, P->slots, cols, xcd, true);
+      gq::launch_slot_sum(st, np, ss->ndst, ss->dst, ss->ptr, ss->pair, P->slots, Y);
+    } else {
+      gq::launch_translate(st, kind, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], tm,
+                           X, Y, cols, xcd);
+    }
+  };
   for (int d = 0; d < P->prm.n_densities; ++d) {
     if (timing) {
       if (P->ev_used == P->ev_sets.size()) {
@@ -1414,36 +1494,34 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     }
     rng.next("gq: stage 2a P2M");
     gq::launch_p2m(f, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_ptr,
-                   P->d_p2m_idx, P->bctr, P->bh, src, P->q, P->M);
+                   P->d_p2m_idx, P->bctr, P->bh, src, P->q, P->M, P->det);
     GQ_TRY(mark(3, f));
     rng.next("gq: stage 2b M2M");
-    for (int l = T.nlevels - 1; l >= 1; --l) {
-      const auto& t = P->m2m_levels[l];
-      const auto& dd = P->d_m2m[l];
-      gq::launch_translate(f, 0, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_m2m,
-                           P->M, P->M, P->lvl_cols);
-    }
+    for (int l = T.nlevels - 1; l >= 1; --l)
+      translate(f, 0, P->m2m_levels[l], P->d_m2m[l], P->tm_m2m, P->M, P->M, P->lvl_cols, true,
+                P->det ? &P->ss_m2m[l] : nullptr);
     GQ_TRY(mark(4, f));
     rng.next("gq: stage 4 M2L");
-    if (P->prm.m2l_rotation)
+    if (P->prm.m2l_rotation) {
       gq::launch_m2l_rot(f, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1], P->d_m2l[2],
-                         P->d_m2l[3], P->d_m2l[4], P->rot, P->M, P->L, P->m2l_xcd);
-    else
-      gq::launch_translate(f, 2, prec, np, P->m2l.ntile(), P->d_m2l[0], P->d_m2l[1],
-                           P->d_m2l[2], P->d_m2l[3], P->d_m2l[4], P->tm_m2l, P->M, P->L,
-                           P->m2l_cols, P->m2l_xcd);
+                         P->d_m2l[3], P->d_m2l[4], P->rot, P->M, P->det ? P->slots : P->L,
+                         P->m2l_xcd, P->det);
+      if (P->det)
+        gq::launch_slot_sum(f, np, P->ss_m2l.ndst, P->ss_m2l.dst, P->ss_m2l.ptr,
+                            P->ss_m2l.pair, P->slots, P->L);
+    } else {
+      translate(f, 2, P->m2l, P->d_m2l, P->tm_m2l, P->M, P->L, P->m2l_cols, P->m2l_xcd,
+                &P->ss_m2l);
+    }
     GQ_TRY(mark(5, f));
     rng.next("gq: stage 6b P2L");
     gq::launch_p2l(f, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_ptr,
-                   P->d_p2l_idx, P->bctr, P->bh, src, P->q, P->L);
+                   P->d_p2l_idx, P->bctr, P->bh, src, P->q, P->L, P->det);
     GQ_TRY(mark(6, f));
     rng.next("gq: stage 7 L2L");
-    for (int l = 1; l < T.nlevels; ++l) {
-      const auto& t = P->l2l_levels[l];
-      const auto& dd = P->d_l2l[l];
-      gq::launch_translate(f, 1, prec, np, t.ntile(), dd[0], dd[1], dd[2], dd[3], dd[4], P->tm_l2l,
-                           P->L, P->L, P->lvl_cols);
-    }
+    for (int l = 1; l < T.nlevels; ++l)
+      translate(f, 1, P->l2l_levels[l], P->d_l2l[l], P->tm_l2l, P->L, P->L, P->lvl_cols, true,
+                P->det ? &P->ss_l2l[l] : nullptr);
     GQ_TRY(mark(7, f));
     // near field: writes only Lq and the point-target potentials
     rng.next("gq: stages 3, 5a, 6a P2QBXL");
@@ -1873,9 +1951,10 @@ gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, vo
     if (P->prm.p_qbx != P0->prm.p_qbx || P->prm.p_fmm != P0->prm.p_fmm ||
         P->prm.kernel != P0->prm.kernel || P->prm.precision != P0->prm.precision ||
         P->prm.m2l_rotation != P0->prm.m2l_rotation ||
-        P->prm.n_densities != P0->prm.n_densities)
-      return fail(GQ_EINVAL, "batch members must share p_qbx, p_fmm, kernel, precision and "
-                             "n_densities");
+        P->prm.n_densities != P0->prm.n_densities ||
+        (P->prm.flags & GQ_FLAG_DETERMINISTIC) != (P0->prm.flags & GQ_FLAG_DETERMINISTIC))
+      return fail(GQ_EINVAL, "batch members must share p_qbx, p_fmm, kernel, precision, "
+                             "n_densities and GQ_FLAG_DETERMINISTIC");
     for (int j = 0; j < k; ++j)
       if (plans[j] == P) return fail(GQ_EINVAL, "plan listed twice in batch");
   }
@@ -1900,6 +1979,7 @@ gq_status gq_batch_create(int n_plans, gq_plan* const* plans, unsigned flags, vo
   if (st == GQ_OK) st = merge_geometry(B, plans, n_plans, B->last_stream);
   if (st == GQ_OK) st = upload_work(B);
   if (st == GQ_OK && (flags & GQ_FLAG_AUTOTUNE)) st = autotune_m2l(B, B->last_stream);
+  if (st == GQ_OK) st = upload_slot_sums(B);
   if (st != GQ_OK) {
     delete B;
     return st;

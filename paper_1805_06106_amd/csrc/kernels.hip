@@ -72,7 +72,7 @@ __device__ __forceinline__ void fill_invtab(double* tab) {
 // matrix rows in rounds of 16 row-blocks; wave w owns row-blocks w, w+4, w+8, w+12 of the
 // round and all column blocks of the tile, so each matrix element is read once per tile.
 // The input expansions are staged in LDS in chunks of kKc coefficients; outputs are added
-// atomically (several classes can target one box).
+// atomically (several classes can target one box), or stored to per-pair slots (KIND 3).
 // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, each with its
 // own L2, and tiles are sorted by class; block i therefore takes tile
 // (i % 8) * per_xcd + i / 8, so each XCD walks one contiguous range of classes and reads
@@ -86,7 +86,9 @@ constexpr int kPf64 = 2;            // K-steps of matrix prefetch, FP64 kernel
 constexpr int kPf32 = 4;            // K-steps of matrix prefetch, FP32 kernel
 
 // KIND (0 M2M, 1 L2L, 2 M2L) only names the instantiation, so that profiles tell the
-// three uses apart; the code is the same.
+// three uses apart; the code is the same.  KIND 3 is any of them with each pair's result
+// stored to its own slot Y[pair position] instead of added into Y[dst] (deterministic
+// plans, summed afterwards by k_slot_sum).
 template <int KIND, int CB>
 __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict__ tile_cls,
                                                    const int* __restrict__ tile_beg,
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
                                                    const double* __restrict__ X,
                                                    double* __restrict__ Y, int ntile,
                                                    int per_xcd) {
+  constexpr bool to_slots = KIND == 3;
   constexpr int kXs = 16 * CB + 1;  // padded LDS row
   __shared__ double xs[2][kKc * kXs];  // double-buffered [k][col]
   const int t = per_xcd ? (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds)
@@ -203,8 +206,12 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
           // transposed product: register r of lane l holds (pair l/16 + 4r, row l%16), so
           // 16 lanes add 16 consecutive coefficients of one destination
           const int col = cb * 16 + lk + 4 * r;
-          if (col < cnt && row < np)
-            unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + col] * np + row], acc[i][cb][r]);
+          if (col < cnt && row < np) {
+            if constexpr (to_slots)
+              Y[(int64_t)(beg + col) * np + row] = acc[i][cb][r];
+            else
+              unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + col] * np + row], acc[i][cb][r]);
+          }
         }
     }
   }
@@ -241,6 +248,7 @@ __global__ __launch_bounds__(256, MODE == 2 && CB == 2 ? 4 : 1) void k_translate
                                                      const double* __restrict__ X,
                                                      double* __restrict__ Y, int ntile,
                                                      int per_xcd) {
+  constexpr bool to_slots = KIND == 3;
   constexpr bool kLeadOn = MODE != 0;
   constexpr int kXs = 16 * CB + 1;  // padded LDS row
   __shared__ float2 xs[2][kKc * kXs];  // double-buffered [k][col] = (hi, lo)
@@ -399,8 +407,12 @@ __global__ __launch_bounds__(256, MODE == 2 && CB == 2 ? 4 : 1) void k_translate
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int col = cb * 16 + 4 * lk + r;
-          if (col < cnt && row < np)
-            unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + col] * np + row], v[cb][r] * so);
+          if (col < cnt && row < np) {
+            if constexpr (to_slots)
+              Y[(int64_t)(beg + col) * np + row] = v[cb][r] * so;
+            else
+              unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + col] * np + row], v[cb][r] * so);
+          }
         }
       }
     }
@@ -1177,7 +1189,8 @@ void launch_translate32(hipStream_t s, dim3 grid, int kind, int np, int ntile, c
                         int per_xcd) {
   auto k = kind == 0   ? k_translate32<0, CB, MODE>
            : kind == 1 ? k_translate32<1, CB, MODE>
-                       : k_translate32<2, CB, MODE>;
+           : kind == 2 ? k_translate32<2, CB, MODE>
+                       : k_translate32<3, CB, MODE>;
   k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo,
                          T.lead, T.s_in, T.s_out, X, Y, ntile, per_xcd);
 }
@@ -1192,7 +1205,10 @@ void launch_translate_cb(hipStream_t s, int kind, int prec, int np, int ntile,
   const int per_xcd = xcd_order ? (ntile + kXcds - 1) / kXcds : 0;
   const dim3 grid(xcd_order ? per_xcd * kXcds : ntile);
   if (prec == 0) {
-    auto k = kind == 0 ? k_translate<0, CB> : kind == 1 ? k_translate<1, CB> : k_translate<2, CB>;
+    auto k = kind == 0   ? k_translate<0, CB>
+             : kind == 1 ? k_translate<1, CB>
+             : kind == 2 ? k_translate<2, CB>
+                         : k_translate<3, CB>;
     k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.t64, X, Y,
                            ntile, per_xcd);
   } else if (prec == 1) {
@@ -1207,17 +1223,43 @@ void launch_translate_cb(hipStream_t s, int kind, int prec, int np, int ntile,
   }
 }
 
+// Ordered sum of slot results: block i adds the slots of destination dst[i], the pair
+// positions pair[ptr[i] .. ptr[i+1]) in that order, into Y[dst[i]].  Each destination
+// appears once, so no two blocks write the same output.
+__global__ __launch_bounds__(256) void k_slot_sum(int np, const int* __restrict__ dst,
+                                                  const int64_t* __restrict__ ptr,
+                                                  const int* __restrict__ pair,
+                                                  const double* __restrict__ S,
+                                                  double* __restrict__ Y) {
+  const int i = blockIdx.x;
+  const int64_t b = ptr[i], e = ptr[i + 1];
+  double* y = Y + (int64_t)dst[i] * np;
+  for (int row = threadIdx.x; row < np; row += blockDim.x) {
+    double sum = 0.0;
+    for (int64_t k = b; k < e; ++k) sum += S[(int64_t)pair[k] * np + row];
+    y[row] += sum;
+  }
+}
+
 void launch_translate(hipStream_t s, int kind, int prec, int np, int ntile,
                       const int* tile_cls, const int* tile_beg, const int* tile_cnt,
                       const int* pair_src, const int* pair_dst, const TransMats& T,
-                      const double* X, double* Y, int tile_cols, bool xcd_order) {
+                      const double* X, double* Y, int tile_cols, bool xcd_order,
+                      bool to_slots) {
   if (ntile <= 0) return;
+  if (to_slots) kind = 3;
   if (tile_cols == 32)
     launch_translate_cb<2>(s, kind, prec, np, ntile, tile_cls, tile_beg, tile_cnt, pair_src,
                            pair_dst, T, X, Y, xcd_order);
   else
     launch_translate_cb<4>(s, kind, prec, np, ntile, tile_cls, tile_beg, tile_cnt, pair_src,
                            pair_dst, T, X, Y, xcd_order);
+}
+
+void launch_slot_sum(hipStream_t s, int np, int ndst, const int* dst, const int64_t* ptr,
+                     const int* pair, const double* slots, double* Y) {
+  if (ndst <= 0) return;
+  k_slot_sum<<<ndst, 256, 0, s>>>(np, dst, ptr, pair, slots, Y);
 }
 
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,

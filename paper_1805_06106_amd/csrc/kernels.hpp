@@ -46,7 +46,8 @@ struct RotMats {
 };
 void launch_m2l_rot(hipStream_t s, int np, int ntile, const int* tile_cls, const int* tile_beg,
                     const int* tile_cnt, const int* pair_src, const int* pair_dst,
-                    const RotMats& R, const double* X, double* Y, bool xcd_order);
+                    const RotMats& R, const double* X, double* Y, bool xcd_order,
+                    bool to_slots = false);
 
 // Target association (associate.hip).  A uniform grid of n[0] x n[1] x n[2] cells of width
 // h from lo; cell (i, j, k) has linear index (k * n[1] + j) * n[0] + i.
@@ -73,15 +74,17 @@ void launch_points_near(hipStream_t s, int64_t nq, const double* qx, const doubl
 
 // Stage 2a: multipoles (scaled) of leaf boxes from their own sources.  Item i: box
 // boxes[i], sources idx[ptr[i] .. ptr[i+1]) (tree positions).  Overwrites.  (kernels_p2x.hip)
+// ordered: the block's partial sums are combined in a fixed order (reproducible results)
+// instead of with LDS atomics; the same for P2L.
 void launch_p2m(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
                 const int64_t* ptr, const int* idx, const double* bctr, const double* bh,
-                SrcSoA src, const double* q, double* M);
+                SrcSoA src, const double* q, double* M, bool ordered = false);
 
 // Stage 6b: box locals (scaled) of target boxes from the sources of their X-far boxes.
 // Item i: box boxes[i], sources idx[ptr[i] .. ptr[i+1]).  Accumulates into L.
 void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
                 const int64_t* ptr, const int* idx, const double* bctr, const double* bh,
-                SrcSoA src, const double* q, double* L);
+                SrcSoA src, const double* q, double* L, bool ordered = false);
 
 // Translation matrices of one kind, column-major n_p x n_p per class: FP64 (t64), or for
 // the FP32 modes the balanced matrix T^ = diag(1 / s_out) T diag(1 / s_in) as the FP32 pair
@@ -101,12 +104,18 @@ struct TransMats {
 // hi/lo correction products and FP64 accumulation per K-step); 2 FP32 MFMA, hi only, FP32
 // accumulation; 3 leading degrees on FP64 MFMA, the rest FP32 MFMA hi only.
 // tile_cols: 32 or 64, the tile width the tiles were formed with; xcd_order: map
-// consecutive tiles to one XCD (else plain block order).
+// consecutive tiles to one XCD (else plain block order).  to_slots: instead of adding into
+// Y[dst], store each pair's result to Y[(pair position) * np ..] (Y then holds one slot per
+// pair of the tile set), for launch_slot_sum.
 void launch_translate(hipStream_t s, int kind, int prec, int np, int ntile,
                       const int* tile_cls, const int* tile_beg, const int* tile_cnt,
                       const int* pair_src, const int* pair_dst, const TransMats& T,
                       const double* X, double* Y, int tile_cols = kTileCols,
-                      bool xcd_order = true);
+                      bool xcd_order = true, bool to_slots = false);
+// Reproducible accumulation of slot results: Y[dst[i]] += sum over k in [ptr[i], ptr[i+1])
+// of slots[pair[k]], summed in that order; the dst[i] are distinct.
+void launch_slot_sum(hipStream_t s, int np, int ndst, const int* dst, const int64_t* ptr,
+                     const int* pair, const double* slots, double* Y);
 
 // Stages 3, 5a, 6a: QBX locals from the near sources (U, W-close, X-close).
 // Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]) (at most 64); the

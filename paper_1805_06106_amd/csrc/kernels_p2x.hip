@@ -19,8 +19,9 @@
 // columns together have NT + 2 entries, so all threads carry the same load) for a slice of
 // the staged sources: it runs the upward degree recurrence of its two columns from the
 // staged diagonal and accumulates in registers.  No cross-lane reduction happens per
-// source; at the end each thread adds its column entries into an LDS moment table with
-// LDS atomics, and the block combines the moments into the output.
+// source; at the end each thread adds its column entries into an LDS moment table, with LDS
+// atomics or (ordered, for reproducible results) one slice at a time in slice order, and the
+// block combines the moments into the output.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256, EMAX <= 18 ? 4 : 1) void k_p2x(int P, const in
                                              const double* __restrict__ bctr,
                                              const double* __restrict__ bh, SrcSoA src,
                                              const double* __restrict__ q,
-                                             double* __restrict__ out) {
+                                             double* __restrict__ out, int ordered) {
   constexpr int NMOM = KERN ? 3 : 1;
   constexpr int DMAX = EMAX - 1;
   __shared__ double sdiag[kChunk][DMAX][2];  // H_m^m of each staged source
@@ -186,18 +187,38 @@ __global__ __launch_bounds__(256, EMAX <= 18 ? 4 : 1) void k_p2x(int P, const in
     }
   }
   // moments of all slices into the LDS table
-  if (active) {
+  __syncthreads();  // the table's clearing is complete even when the item has no sources
+  if (ordered) {
+    // one slice after the other in slice order: within a slice every table entry belongs
+    // to one thread, so the sums are plain adds in a fixed order, the same on every run
+    for (int r = 0; r < S; ++r) {
+      if (active && sl == r) {
 #pragma unroll
-    for (int i = 0; i < EMAX; ++i) {
-      if (i < ntot) {
-        const int m = i < LA ? mA : mB;
-        const int N = i < LA ? mA + i : mB + (i - LA);
-        atomicAdd(&res[t][tri(N, m)][0], acc[i][0]);
-        atomicAdd(&res[t][tri(N, m)][1], acc[i][1]);
+        for (int i = 0; i < EMAX; ++i) {
+          if (i < ntot) {
+            const int m = i < LA ? mA : mB;
+            const int N = i < LA ? mA + i : mB + (i - LA);
+            res[t][tri(N, m)][0] += acc[i][0];
+            res[t][tri(N, m)][1] += acc[i][1];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < EMAX; ++i) {
+        if (i < ntot) {
+          const int m = i < LA ? mA : mB;
+          const int N = i < LA ? mA + i : mB + (i - LA);
+          atomicAdd(&res[t][tri(N, m)][0], acc[i][0]);
+          atomicAdd(&res[t][tri(N, m)][1], acc[i][1]);
+        }
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
   auto mom = [&](int tt, int N, int m, int c) -> double { return res[tt][tri(N, m)][c]; };
   const int np = (P + 1) * (P + 1);
   double* o = out + (int64_t)b * np;
@@ -235,43 +256,43 @@ __global__ __launch_bounds__(256, EMAX <= 18 ? 4 : 1) void k_p2x(int P, const in
 template <int KERN, bool IRR>
 void launch_p2x_k(hipStream_t s, int p, int nitem, const int* boxes, const int64_t* ptr,
                   const int* idx, const double* bctr, const double* bh, SrcSoA src,
-                  const double* q, double* out) {
+                  const double* q, double* out, int ordered) {
   const int NT = IRR ? p + KERN : p - KERN;
   const int e = NT + 2;
   if (e <= 8)
-    k_p2x<KERN, IRR, 8><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
+    k_p2x<KERN, IRR, 8><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out, ordered);
   else if (e <= 12)
-    k_p2x<KERN, IRR, 12><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
+    k_p2x<KERN, IRR, 12><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out, ordered);
   else if (e <= 16)
-    k_p2x<KERN, IRR, 16><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
+    k_p2x<KERN, IRR, 16><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out, ordered);
   else if (e <= 18)
-    k_p2x<KERN, IRR, 18><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
+    k_p2x<KERN, IRR, 18><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out, ordered);
   else if (e <= 20)
-    k_p2x<KERN, IRR, 20><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
+    k_p2x<KERN, IRR, 20><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out, ordered);
   else
-    k_p2x<KERN, IRR, 24><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out);
+    k_p2x<KERN, IRR, 24><<<nitem, 256, 0, s>>>(p, boxes, ptr, idx, bctr, bh, src, q, out, ordered);
 }
 
 }  // namespace
 
 void launch_p2m(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
                 const int64_t* ptr, const int* idx, const double* bctr, const double* bh,
-                SrcSoA src, const double* q, double* M) {
+                SrcSoA src, const double* q, double* M, bool ordered) {
   if (nitem <= 0) return;
   if (kernel)
-    launch_p2x_k<1, false>(s, p, nitem, boxes, ptr, idx, bctr, bh, src, q, M);
+    launch_p2x_k<1, false>(s, p, nitem, boxes, ptr, idx, bctr, bh, src, q, M, ordered);
   else
-    launch_p2x_k<0, false>(s, p, nitem, boxes, ptr, idx, bctr, bh, src, q, M);
+    launch_p2x_k<0, false>(s, p, nitem, boxes, ptr, idx, bctr, bh, src, q, M, ordered);
 }
 
 void launch_p2l(hipStream_t s, int kernel, int p, int nitem, const int* boxes,
                 const int64_t* ptr, const int* idx, const double* bctr, const double* bh,
-                SrcSoA src, const double* q, double* L) {
+                SrcSoA src, const double* q, double* L, bool ordered) {
   if (nitem <= 0) return;
   if (kernel)
-    launch_p2x_k<1, true>(s, p, nitem, boxes, ptr, idx, bctr, bh, src, q, L);
+    launch_p2x_k<1, true>(s, p, nitem, boxes, ptr, idx, bctr, bh, src, q, L, ordered);
   else
-    launch_p2x_k<0, true>(s, p, nitem, boxes, ptr, idx, bctr, bh, src, q, L);
+    launch_p2x_k<0, true>(s, p, nitem, boxes, ptr, idx, bctr, bh, src, q, L, ordered);
 }
 
 }  // namespace gq

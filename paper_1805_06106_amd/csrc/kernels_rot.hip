@@ -14,7 +14,8 @@
 //   stage 1  Y = A Y        all products read before any row is written back
 //   stage 2  Y = Z Y        in place, one order block at a time (row gather/scatter)
 //   stage 3  L += B Y       computed transposed (L^T = Y^T B^T) so that the atomic adds of
-//                           16 lanes go to 16 consecutive coefficients of one pair
+//                           16 lanes go to 16 consecutive coefficients of one pair (or, with
+//                           to_slots, the stores to the pair's own slot)
 // MFMA layout of v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register r of lane l holds D[l / 16 + 4 r][l % 16].
 #include <hip/hip_runtime.h>
@@ -44,6 +45,9 @@ __device__ __forceinline__ int wsw(int row, int col) { return row * kRC + (col ^
 // accumulation chains are in flight.
 constexpr int kSlots = 4;
 
+// TO_SLOTS: each pair's result is stored to its own slot Y[pair position] instead of added
+// into Y[dst] (deterministic plans).
+template <bool TO_SLOTS>
 __global__ __launch_bounds__(256) void k_m2l_rot(int np, const int* __restrict__ tile_cls,
                                                  const int* __restrict__ tile_beg,
                                                  const int* __restrict__ tile_cnt,
@@ -168,7 +172,11 @@ __global__ __launch_bounds__(256) void k_m2l_rot(int np, const int* __restrict__
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int pair = 16 * h + lk + 4 * i;
-        if (pair < cnt) unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + pair] * np + row], acc[j][h][i]);
+        if (pair >= cnt) continue;
+        if constexpr (TO_SLOTS)
+          Y[(int64_t)(beg + pair) * np + row] = acc[j][h][i];
+        else
+          unsafeAtomicAdd(&Y[(int64_t)pair_dst[beg + pair] * np + row], acc[j][h][i]);
       }
   }
 }
@@ -177,12 +185,14 @@ __global__ __launch_bounds__(256) void k_m2l_rot(int np, const int* __restrict__
 
 void launch_m2l_rot(hipStream_t s, int np, int ntile, const int* tile_cls, const int* tile_beg,
                     const int* tile_cnt, const int* pair_src, const int* pair_dst,
-                    const RotMats& R, const double* X, double* Y, bool xcd_order) {
+                    const RotMats& R, const double* X, double* Y, bool xcd_order,
+                    bool to_slots) {
   if (ntile <= 0) return;
   const int per_xcd = xcd_order ? (ntile + kRotXcds - 1) / kRotXcds : 0;
   const dim3 grid(xcd_order ? per_xcd * kRotXcds : ntile);
-  k_m2l_rot<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, R, X, Y,
-                                 ntile, per_xcd);
+  auto k = to_slots ? k_m2l_rot<true> : k_m2l_rot<false>;
+  k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, R, X, Y, ntile,
+                         per_xcd);
 }
 
 }  // namespace gq
