@@ -360,7 +360,8 @@ gq_status gq_list_export(const gq_plan* plan, int list, int64_t* ptr, int32_t* i
                          int64_t* n_items);
 
 /*
- * Download the QBX local coefficients of the last gq_apply for density 0, after Stage 8:
+ * Download the QBX local coefficients of the last gq_apply for its last density
+ * (n_densities - 1; density 0 for a one-density plan), after Stage 8:
  * host_out[n_ctr * (p_qbx+1)^2], input center order, in the library's internal real-packed
  * solid-harmonic form l_n^m = sum_j q_j conj(I_n^m)(s_j - c), with
  * I_n^m(v) = (n-m)! P_n^m(cos theta) e^{i m phi} / r^(n+1) (Condon-Shortley phase in P_n^m),

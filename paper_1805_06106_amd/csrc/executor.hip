@@ -180,6 +180,8 @@ struct gq_plan {
   };
   bool det = false;
   double* slots = nullptr;
+  // densities per near-field pass (1 or 2): with 2, q and Lq hold two densities each
+  int nbuf = 1;
   SlotSum ss_m2l;
   std::vector<SlotSum> ss_m2m, ss_l2l;  // index: child level
   // GQ_FLAG_GRAPH: the passes of one apply captured once per (density, potential) pair
@@ -212,6 +214,16 @@ struct gq_plan {
 };
 
 namespace {
+
+// Densities that share one near-field pass: two for the double layer up to p_qbx =
+// kNd2Qmax when the plan has more than one density.  Measured on one MI355X: the urchin's
+// near field for two densities took 25.5 ms in one pass against 32.6 ms in two (D, q = 5);
+// the single layer lost (217 against 193 ms, S, q = 8: the pass's two sets of sums leave too
+// few registers for the harmonics), so it keeps one density per pass.
+int near_field_densities(const gq_params& prm) {
+  return prm.n_densities >= 2 && prm.kernel == GQ_KERNEL_D && prm.p_qbx <= gq::kNd2Qmax ? 2
+                                                                                        : 1;
+}
 
 // Every device allocation of a plan goes through here: the workspace cap is enforced and
 // the held bytes counted.
@@ -1009,10 +1021,11 @@ gq_status merge_geometry(gq_plan* B, gq_plan* const* plans, int n, hipStream_t s
   GQ_TRY(upload(B, B->h_tgt_out, &B->tgt_out, s));
   GQ_TRY(upload(B, T.center, &B->bctr, s));
   GQ_TRY(upload(B, T.h, &B->bh, s));
-  GQ_TRY(alloc(B, (size_t)B->n_src, &B->q));
+  B->nbuf = near_field_densities(B->prm);
+  GQ_TRY(alloc(B, (size_t)B->n_src * B->nbuf, &B->q));
   GQ_TRY(alloc(B, (size_t)T.nboxes * B->np, &B->M));
   GQ_TRY(alloc(B, (size_t)T.nboxes * B->np, &B->L));
-  GQ_TRY(alloc(B, (size_t)B->n_ctr * B->nq, &B->Lq));
+  GQ_TRY(alloc(B, (size_t)B->n_ctr * B->nq * B->nbuf, &B->Lq));
   GQ_HIP(hipStreamSynchronize(s));
   return GQ_OK;
 }
@@ -1387,10 +1400,11 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
       GQ_TRY(upload(P, T.h, &P->bh, s));
       GQ_TRY(upload(P, T.src_start, &P->src_start, s));
       GQ_TRY(upload(P, T.src_count, &P->src_count, s));
-      GQ_TRY(alloc(P, (size_t)n_src, &P->q));
+      P->nbuf = near_field_densities(P->prm);
+      GQ_TRY(alloc(P, (size_t)n_src * P->nbuf, &P->q));
       GQ_TRY(alloc(P, (size_t)T.nboxes * P->np, &P->M));
       GQ_TRY(alloc(P, (size_t)T.nboxes * P->np, &P->L));
-      GQ_TRY(alloc(P, (size_t)n_ctr * P->nq, &P->Lq));
+      GQ_TRY(alloc(P, (size_t)n_ctr * P->nq * P->nbuf, &P->Lq));
       GQ_HIP(hipStreamSynchronize(s));
       return GQ_OK;
     };
@@ -1460,7 +1474,16 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
                            X, Y, cols, xcd);
     }
   };
-  for (int d = 0; d < P->prm.n_densities; ++d) {
+  // Densities go through the near field in groups of P->nbuf (its kernel shares each
+  // pair's harmonics between them); every other stage runs once per density.  One timed pass
+  // per density: the group's strengths, fills and near field are timed in its first pass.
+  const int nden = P->prm.n_densities;
+  const int64_t nlq = P->n_ctr * P->nq;
+  for (int d = 0; d < nden; ++d) {
+    const int e = d % P->nbuf;                        // position in the near-field group
+    const int ng = std::min(P->nbuf, nden - (d - e));  // densities of the group
+    double* qd = P->q + (int64_t)e * P->n_src;        // this density's strengths
+    double* Lqd = P->Lq + (int64_t)e * nlq;           // and center locals
     if (timing) {
       if (P->ev_used == P->ev_sets.size()) {
         std::array<hipEvent_t, kEvents> set{};
@@ -1472,17 +1495,21 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     StageRanges rng;
     rng.next("gq: strengths");
     GQ_TRY(mark(0, s));
-    if (P->interp)
-      gq::launch_strength_interp(s, P->n_src, P->src_order, P->sw, P->n_node, P->n_quad,
-                                 P->interp, density + (int64_t)d * P->n_elem * P->n_node, P->q);
-    else
-      gq::launch_strength(s, P->n_src, P->src_order, P->sw, density + (int64_t)d * P->n_src,
-                          P->q);
+    for (int g = 0; e == 0 && g < ng; ++g) {
+      double* qg = P->q + (int64_t)g * P->n_src;
+      if (P->interp)
+        gq::launch_strength_interp(s, P->n_src, P->src_order, P->sw, P->n_node, P->n_quad,
+                                   P->interp, density + (int64_t)(d + g) * P->n_elem * P->n_node,
+                                   qg);
+      else
+        gq::launch_strength(s, P->n_src, P->src_order, P->sw,
+                            density + (int64_t)(d + g) * P->n_src, qg);
+    }
     GQ_TRY(mark(1, s));
     rng.next("gq: clear expansions");
     gq::launch_fill(s, P->M, (int64_t)T.nboxes * np, 0.0);
     gq::launch_fill(s, P->L, (int64_t)T.nboxes * np, 0.0);
-    gq::launch_fill(s, P->Lq, (int64_t)P->n_ctr * P->nq, 0.0);
+    if (e == 0) gq::launch_fill(s, P->Lq, nlq * ng, 0.0);
     if (P->n_pt > 0) gq::launch_fill(s, P->phi, P->n_pt, 0.0);
     GQ_TRY(mark(2, s));
     // far-field chain: writes only M and L, so it may run beside the near field
@@ -1494,7 +1521,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     }
     rng.next("gq: stage 2a P2M");
     gq::launch_p2m(f, kern, p, (int)P->p2m_boxes.size(), P->d_p2m_boxes, P->d_p2m_ptr,
-                   P->d_p2m_idx, P->bctr, P->bh, src, P->q, P->M, P->det);
+                   P->d_p2m_idx, P->bctr, P->bh, src, qd, P->M, P->det);
     GQ_TRY(mark(3, f));
     rng.next("gq: stage 2b M2M");
     for (int l = T.nlevels - 1; l >= 1; --l)
@@ -1516,7 +1543,7 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     GQ_TRY(mark(5, f));
     rng.next("gq: stage 6b P2L");
     gq::launch_p2l(f, kern, p, (int)P->p2l_box.size(), P->d_p2l_box, P->d_p2l_ptr,
-                   P->d_p2l_idx, P->bctr, P->bh, src, P->q, P->L, P->det);
+                   P->d_p2l_idx, P->bctr, P->bh, src, qd, P->L, P->det);
     GQ_TRY(mark(6, f));
     rng.next("gq: stage 7 L2L");
     for (int l = 1; l < T.nlevels; ++l)
@@ -1526,11 +1553,12 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     // near field: writes only Lq and the point-target potentials
     rng.next("gq: stages 3, 5a, 6a P2QBXL");
     GQ_TRY(mark(12, s));
-    gq::launch_p2qbxl(s, kern, qo, (int)P->k3_box.size(), P->d_k3_box, P->d_k3_c0, P->d_k3_nc,
-                      P->d_near_ptr, P->d_near_idx, src, P->q, P->cx, P->cy,
-                      P->cz, P->Lq, P->n_ctr);
+    if (e == 0)
+      gq::launch_p2qbxl(s, kern, qo, (int)P->k3_box.size(), P->d_k3_box, P->d_k3_c0,
+                        P->d_k3_nc, P->d_near_ptr, P->d_near_idx, src, P->q, P->cx, P->cy,
+                        P->cz, P->Lq, P->n_ctr, ng, P->n_src, nlq);
     gq::launch_p2p(s, kern, (int)P->pp_box.size(), P->d_pp_box, P->d_pp_t0, P->d_pp_nt,
-                   P->d_near_ptr, P->d_near_idx, src, P->q, P->px, P->py, P->pz, P->phi);
+                   P->d_near_ptr, P->d_near_idx, src, qd, P->px, P->py, P->pz, P->phi);
     GQ_TRY(mark(8, s));
     if (overlap) {
       GQ_HIP(hipEventRecord(P->ev_join, f));
@@ -1540,25 +1568,25 @@ gq_status apply_passes(gq_plan* P, const double* density, double* potential, hip
     rng.next("gq: stage 5b M2QBXL");
     gq::launch_m2qbxl(s, p, qo, (int)P->k5_c0.size(), P->d_k5_c0, P->d_k5_nc, P->d_k5_w0,
                       P->d_k5_w1, P->d_wf_box, P->bctr, P->bh, P->M, P->cx, P->cy, P->cz,
-                      P->Lq, P->n_ctr);
+                      Lqd, P->n_ctr);
     gq::launch_m2p(s, p, (int)P->pm_t0.size(), P->d_pm_t0, P->d_pm_nt, P->d_pm_w0, P->d_pm_w1,
                    P->d_wf_box, P->bctr, P->bh, P->M, P->px, P->py, P->pz, P->phi);
     GQ_TRY(mark(9, s));
     rng.next("gq: stage 8 L2QBXL");
     gq::launch_l2qbxl(s, p, qo, P->k8_nsingle, P->d_k8_box, P->d_k8_c0, P->d_k8_nc, P->bctr,
-                      P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
+                      P->bh, P->L, P->cx, P->cy, P->cz, Lqd, P->n_ctr);
     gq::launch_l2qbxl_pairs(s, p, qo, P->k8_npair, P->d_k8_box + P->k8_nsingle,
                             P->d_k8_c0 + P->k8_nsingle, P->d_k8_nc + P->k8_nsingle, P->bctr,
-                            P->bh, P->L, P->cx, P->cy, P->cz, P->Lq, P->n_ctr);
+                            P->bh, P->L, P->cx, P->cy, P->cz, Lqd, P->n_ctr);
     GQ_TRY(mark(10, s));
     rng.next("gq: stage 9 QBXL2P");
     if (sprime)
       gq::launch_qbxl2p_grad(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->tnx, P->tny,
-                             P->tnz, P->cx, P->cy, P->cz, P->Lq, P->n_ctr, P->tgt_out,
+                             P->tnz, P->cx, P->cy, P->cz, Lqd, P->n_ctr, P->tgt_out,
                              potential + (int64_t)d * P->n_tgt);
     else
       gq::launch_qbxl2p(s, qo, P->n_qt, P->tgt_ctr, P->tx, P->ty, P->tz, P->cx, P->cy, P->cz,
-                        P->Lq, P->n_ctr, P->tgt_out, potential + (int64_t)d * P->n_tgt);
+                        Lqd, P->n_ctr, P->tgt_out, potential + (int64_t)d * P->n_tgt);
     gq::launch_l2p(s, p, P->n_pt, P->d_pt_box, P->bctr, P->bh, P->L, P->px, P->py, P->pz,
                    P->phi, P->d_pt_out, potential + (int64_t)d * P->n_tgt);
     GQ_TRY(mark(11, s));
@@ -2030,7 +2058,9 @@ gq_status gq_qbx_locals(gq_plan* P, double* host_out) {
   if (P->prm.flags & GQ_FLAG_HOST_ONLY) return fail(GQ_EINVAL, "plan was created host-only");
   std::vector<double> buf((size_t)P->n_ctr * P->nq);
   GQ_HIP(hipStreamSynchronize(P->last_stream));
-  GQ_HIP(hipMemcpy(buf.data(), P->Lq, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  const int last = (P->prm.n_densities - 1) % P->nbuf;  // buffer of the last density
+  GQ_HIP(hipMemcpy(buf.data(), P->Lq + (int64_t)last * P->n_ctr * P->nq,
+                   buf.size() * sizeof(double), hipMemcpyDeviceToHost));
   for (int64_t i = 0; i < P->n_ctr; ++i) {
     int64_t j = P->tree.ctr_order[i];
     for (int k = 0; k < P->nq; ++k) host_out[j * P->nq + k] = buf[(size_t)k * P->n_ctr + i];

@@ -473,12 +473,14 @@ __device__ __forceinline__ void p2qbxl_single(double dx, double dy, double dz, d
   }
 }
 
-template <int Q>
-__device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz, double qz,
-                                              double qxh, double qyh,
-                                              double (&acc)[(Q + 1) * (Q + 1)]) {
+template <int Q, int ND>
+__device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz,
+                                              const double (&qz)[ND], const double (&qxh)[ND],
+                                              const double (&qyh)[ND],
+                                              double (&acc)[ND][(Q + 1) * (Q + 1)]) {
   // l_n^m += -qz J_{n+1}^m + qa J_{n+1}^{m+1} - conj(qa) J_{n+1}^{m-1}, qa = (qx + i qy)/2,
-  // scattered from each J_N^M (N = n+1 <= Q+1) into the outputs it feeds, as FMA chains.
+  // scattered from each J_N^M (N = n+1 <= Q+1) into the outputs it feeds, as FMA chains;
+  // the ND densities share the generated J.
   const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
   const double ir = rsqrt_nr(r2);
   const double ir2 = ir * ir;
@@ -510,19 +512,23 @@ __device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz, d
       }
       if (N >= 1) {
         const int n = N - 1;
-        if (M <= n) {  // -qz J_N^M -> l_n^M
-          acc[cpk_re(n, M)] = fma(-qz, jr, acc[cpk_re(n, M)]);
-          if (M) acc[cpk_im(n, M)] = fma(-qz, ji, acc[cpk_im(n, M)]);
-        }
-        if (M == 1) {  // qa J^1 + conj(qa J^1) -> l_n^0
-          acc[cpk_re(n, 0)] = fma(2.0 * qxh, jr, fma(-2.0 * qyh, ji, acc[cpk_re(n, 0)]));
-        } else if (M >= 2 && M - 1 <= n) {  // qa J_N^M -> l_n^{M-1}
-          acc[cpk_re(n, M - 1)] = fma(qxh, jr, fma(-qyh, ji, acc[cpk_re(n, M - 1)]));
-          acc[cpk_im(n, M - 1)] = fma(qxh, ji, fma(qyh, jr, acc[cpk_im(n, M - 1)]));
-        }
-        if (M + 1 <= n) {  // -conj(qa) J_N^M -> l_n^{M+1}
-          acc[cpk_re(n, M + 1)] = fma(-qxh, jr, fma(-qyh, ji, acc[cpk_re(n, M + 1)]));
-          acc[cpk_im(n, M + 1)] = fma(-qxh, ji, fma(qyh, jr, acc[cpk_im(n, M + 1)]));
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          double* a = acc[d];
+          if (M <= n) {  // -qz J_N^M -> l_n^M
+            a[cpk_re(n, M)] = fma(-qz[d], jr, a[cpk_re(n, M)]);
+            if (M) a[cpk_im(n, M)] = fma(-qz[d], ji, a[cpk_im(n, M)]);
+          }
+          if (M == 1) {  // qa J^1 + conj(qa J^1) -> l_n^0
+            a[cpk_re(n, 0)] = fma(2.0 * qxh[d], jr, fma(-2.0 * qyh[d], ji, a[cpk_re(n, 0)]));
+          } else if (M >= 2 && M - 1 <= n) {  // qa J_N^M -> l_n^{M-1}
+            a[cpk_re(n, M - 1)] = fma(qxh[d], jr, fma(-qyh[d], ji, a[cpk_re(n, M - 1)]));
+            a[cpk_im(n, M - 1)] = fma(qxh[d], ji, fma(qyh[d], jr, a[cpk_im(n, M - 1)]));
+          }
+          if (M + 1 <= n) {  // -conj(qa) J_N^M -> l_n^{M+1}
+            a[cpk_re(n, M + 1)] = fma(-qxh[d], jr, fma(-qyh[d], ji, a[cpk_re(n, M + 1)]));
+            a[cpk_im(n, M + 1)] = fma(-qxh[d], ji, fma(qyh[d], jr, a[cpk_im(n, M + 1)]));
+          }
         }
       }
       if (N == M) {
@@ -543,19 +549,25 @@ __device__ __forceinline__ void p2qbxl_double(double dx, double dy, double dz, d
 // at least 60 of the 64 lanes are busy for every nc.  The box's near sources (U, W-close,
 // X-close, flattened) are staged through LDS 64 at a time, the next batch being fetched
 // into registers while the current one is evaluated; slices are summed through LDS.
-template <int Q, int KERN>
+// ND densities (1 or 2; 2 for the double layer only) share each pair's solid harmonics:
+// density d reads its strengths at qs + d qstride and adds into Lq + d lqstride.
+template <int Q, int KERN, int ND>
 __global__ __launch_bounds__(64) void k_p2qbxl(const int* __restrict__ it_box,
                                                const int* __restrict__ it_c0,
                                                const int* __restrict__ it_nc,
                                                const int64_t* __restrict__ near_ptr,
                                                const int* __restrict__ near_idx,
                                                SrcSoA src, const double* __restrict__ qs,
+                                               int64_t qstride,
                                                const double* __restrict__ cx,
                                                const double* __restrict__ cy,
                                                const double* __restrict__ cz,
-                                               double* __restrict__ Lq, int64_t nctr) {
+                                               double* __restrict__ Lq, int64_t nctr,
+                                               int64_t lqstride) {
+  static_assert(ND == 1 || KERN != 0, "the single layer evaluates one density per pass");
   constexpr int NQ = (Q + 1) * (Q + 1);
-  constexpr int NF = KERN ? 6 : 4;
+  constexpr int NW = KERN ? 3 : 1;  // strength factors per source and density
+  constexpr int NF = 3 + NW * ND;
   constexpr int kRed = 8;
   __shared__ double ss[NF * 64];
   __shared__ double red[kRed * 64];
@@ -568,25 +580,30 @@ __global__ __launch_bounds__(64) void k_p2qbxl(const int* __restrict__ it_box,
   const bool active = sl < S;
   const int64_t c = (int64_t)c0 + ci;
   const double xc = cx[c], yc = cy[c], zc = cz[c];
-  double acc[NQ];
+  double acc[ND][NQ];
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) acc[d][i] = 0.0;
   const int64_t fb = near_ptr[b], fe = near_ptr[b + 1];
   double pf[NF];
   auto fetch = [&](int64_t f0) {
     const int64_t f = f0 + lane;
     if (f < fe) {
       const int64_t sidx = near_idx[f];
-      const double qq = qs[sidx];
       pf[0] = src.x[sidx];
       pf[1] = src.y[sidx];
       pf[2] = src.z[sidx];
-      if constexpr (KERN != 0) {
-        pf[3] = qq * src.nz[sidx];
-        pf[4] = 0.5 * qq * src.nx[sidx];
-        pf[5] = 0.5 * qq * src.ny[sidx];
-      } else {
-        pf[3] = qq;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const double qq = qs[d * qstride + sidx];
+        if constexpr (KERN != 0) {
+          pf[3 + 3 * d] = qq * src.nz[sidx];
+          pf[4 + 3 * d] = 0.5 * qq * src.nx[sidx];
+          pf[5 + 3 * d] = 0.5 * qq * src.ny[sidx];
+        } else {
+          pf[3 + d] = qq;
+        }
       }
     }
   };
@@ -603,35 +620,47 @@ __global__ __launch_bounds__(64) void k_p2qbxl(const int* __restrict__ it_box,
     if (active) {
       for (int j = sl; j < n; j += S) {
         const double dx = ss[j] - xc, dy = ss[64 + j] - yc, dz = ss[128 + j] - zc;
-        if (KERN)
-          p2qbxl_double<Q>(dx, dy, dz, ss[192 + j], ss[256 + j], ss[320 + j], acc);
-        else
-          p2qbxl_single<Q>(dx, dy, dz, ss[192 + j], acc);
+        if constexpr (KERN != 0) {
+          double qz[ND], qxh[ND], qyh[ND];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            qz[d] = ss[(3 + 3 * d) * 64 + j];
+            qxh[d] = ss[(4 + 3 * d) * 64 + j];
+            qyh[d] = ss[(5 + 3 * d) * 64 + j];
+          }
+          p2qbxl_double<Q, ND>(dx, dy, dz, qz, qxh, qyh, acc);
+        } else {
+          p2qbxl_single<Q>(dx, dy, dz, ss[192 + j], acc[0]);
+        }
       }
     }
   }
   if (S == 1) {
     if (active)
 #pragma unroll
-      for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) Lq[d * lqstride + (int64_t)i * nctr + c] += acc[d][i];
     return;
   }
   // sum the S slices of each center through LDS, kRed coefficients at a time
 #pragma unroll
-  for (int base = 0; base < NQ; base += kRed) {
-    __syncthreads();
+  for (int d = 0; d < ND; ++d)
 #pragma unroll
-    for (int k = 0; k < kRed; ++k)
-      if (base + k < NQ) red[k * 64 + lane] = active ? acc[base + k] : 0.0;
-    __syncthreads();
-    if (sl == 0) {
-      for (int k = 0; k < kRed && base + k < NQ; ++k) {
-        double sum = 0.0;
-        for (int t = 0; t < S; ++t) sum += red[k * 64 + t * nc + ci];
-        Lq[(int64_t)(base + k) * nctr + c] += sum;
+    for (int base = 0; base < NQ; base += kRed) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kRed; ++k)
+        if (base + k < NQ) red[k * 64 + lane] = active ? acc[d][base + k] : 0.0;
+      __syncthreads();
+      if (sl == 0) {
+        for (int k = 0; k < kRed && base + k < NQ; ++k) {
+          double sum = 0.0;
+          for (int t = 0; t < S; ++t) sum += red[k * 64 + t * nc + ci];
+          Lq[d * lqstride + (int64_t)(base + k) * nctr + c] += sum;
+        }
       }
     }
-  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -1089,16 +1118,24 @@ inline dim3 grid1d(int64_t n, int bs) { return dim3((unsigned)((n + bs - 1) / bs
 
 template <int Q>
 struct P2qbxlGo {
-  static void go(hipStream_t s, int kernel, int nitem, const int* it_box, const int* it_c0,
-                 const int* it_nc, const int64_t* np_, const int* ni, SrcSoA src,
-                 const double* qs, const double* cx, const double* cy, const double* cz,
-                 double* Lq, int64_t nctr) {
+  static void go(hipStream_t s, int kernel, int nd, int nitem, const int* it_box,
+                 const int* it_c0, const int* it_nc, const int64_t* np_, const int* ni,
+                 SrcSoA src, const double* qs, int64_t qstride, const double* cx,
+                 const double* cy, const double* cz, double* Lq, int64_t nctr,
+                 int64_t lqstride) {
+    if constexpr (Q <= kNd2Qmax) {
+      if (nd == 2 && kernel) {
+        k_p2qbxl<Q, 1, 2><<<nitem, 64, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, qstride,
+                                               cx, cy, cz, Lq, nctr, lqstride);
+        return;
+      }
+    }
     if (kernel)
-      k_p2qbxl<Q, 1><<<nitem, 64, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, cx, cy, cz,
-                                          Lq, nctr);
+      k_p2qbxl<Q, 1, 1><<<nitem, 64, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, qstride, cx,
+                                             cy, cz, Lq, nctr, lqstride);
     else
-      k_p2qbxl<Q, 0><<<nitem, 64, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, cx, cy, cz,
-                                          Lq, nctr);
+      k_p2qbxl<Q, 0, 1><<<nitem, 64, 0, s>>>(it_box, it_c0, it_nc, np_, ni, src, qs, qstride, cx,
+                                             cy, cz, Lq, nctr, lqstride);
   }
 };
 
@@ -1265,10 +1302,11 @@ void launch_slot_sum(hipStream_t s, int np, int ndst, const int* dst, const int6
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
                    const int* it_c0, const int* it_nc, const int64_t* near_ptr,
                    const int* near_idx, SrcSoA src, const double* qs, const double* cx,
-                   const double* cy, const double* cz, double* Lq, int64_t nctr) {
+                   const double* cy, const double* cz, double* Lq, int64_t nctr, int nd,
+                   int64_t qstride, int64_t lqstride) {
   if (nitem <= 0) return;
-  QDispatch<P2qbxlGo>::run(q, s, kernel, nitem, it_box, it_c0, it_nc, near_ptr, near_idx, src,
-                           qs, cx, cy, cz, Lq, nctr);
+  QDispatch<P2qbxlGo>::run(q, s, kernel, nd == 2 ? 2 : 1, nitem, it_box, it_c0, it_nc, near_ptr,
+                           near_idx, src, qs, qstride, cx, cy, cz, Lq, nctr, lqstride);
 }
 
 void launch_m2qbxl(hipStream_t s, int p, int q, int nitem, const int* it_c0,

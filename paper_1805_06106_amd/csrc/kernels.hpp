@@ -9,6 +9,7 @@ namespace gq {
 
 constexpr int kPmax = 20;  // highest FMM order supported by the device kernels
 constexpr int kQmax = 10;  // highest QBX order supported by the device kernels
+constexpr int kNd2Qmax = 5;  // highest QBX order of the two-density near-field kernel
 constexpr int kTileCols = 64;  // expansions per translation tile (default; 32 also built)
 constexpr int kTransKc = 64;   // K-chunk of the translation kernels
 
@@ -120,11 +121,15 @@ void launch_slot_sum(hipStream_t s, int np, int ndst, const int* dst, const int6
 // Stages 3, 5a, 6a: QBX locals from the near sources (U, W-close, X-close).
 // Item i: target box it_box[i], centers [it_c0[i], it_c0[i]+it_nc[i]) (at most 64); the
 // box's near sources are near_idx[near_ptr[b] .. near_ptr[b+1]) (tree positions).
+// nd (1 or 2) densities in one pass, sharing each pair's solid harmonics: density d has
+// its strengths at qs + d qstride and its locals at Lq + d lqstride.  nd = 2 is built for
+// the double layer with q <= kNd2Qmax only (other calls run one density).
 void launch_p2qbxl(hipStream_t s, int kernel, int q, int nitem, const int* it_box,
                    const int* it_c0, const int* it_nc, const int64_t* near_ptr,
                    const int* near_idx, SrcSoA src,
                    const double* qs, const double* cx, const double* cy, const double* cz,
-                   double* Lq, int64_t nctr);
+                   double* Lq, int64_t nctr, int nd = 1, int64_t qstride = 0,
+                   int64_t lqstride = 0);
 
 // Stage 5b: QBX locals from W-far multipoles.  Item i: centers [it_c0, it_c0 + it_nc) and
 // W-far boxes wf_box[it_w0 .. it_w1); accumulated atomically into Lq.
