@@ -69,8 +69,10 @@ __device__ __forceinline__ void fill_invtab(double* tab) {
 // The product is formed transposed, Y^T = X^T T^T (inputs as the A operand, matrix as the
 // B operand), so that the 16 lanes sharing a register hold 16 consecutive output
 // coefficients of one destination and its atomic adds coalesce.  A block (4 waves) walks the
-// matrix rows in rounds of 16 row-blocks; wave w owns row-blocks w, w+4, w+8, w+12 of the
-// round and all column blocks of the tile, so each matrix element is read once per tile.
+// matrix rows in rounds of 4 RB row-blocks; wave w owns row-blocks w, w+4, ... of the round
+// and all column blocks of the tile, so each matrix element is read once per tile.  RB = 4
+// (16 row blocks, p <= 15: one round); for p = 16..20 (19 to 28 row blocks) RB = 7 makes it
+// one round too, instead of a second, partly idle round that stages the inputs again.
 // The input expansions are staged in LDS in chunks of kKc coefficients; outputs are added
 // atomically (several classes can target one box), or stored to per-pair slots (KIND 3).
 // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, each with its
@@ -89,7 +91,7 @@ constexpr int kPf32 = 4;            // K-steps of matrix prefetch, FP32 kernel
 // three uses apart; the code is the same.  KIND 3 is any of them with each pair's result
 // stored to its own slot Y[pair position] instead of added into Y[dst] (deterministic
 // plans, summed afterwards by k_slot_sum).
-template <int KIND, int CB>
+template <int KIND, int CB, int RB = 4>
 __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict__ tile_cls,
                                                    const int* __restrict__ tile_beg,
                                                    const int* __restrict__ tile_cnt,
@@ -138,15 +140,15 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
   };
   // matrices are zero-padded to ld rows and kd columns; row blocks past the end and
   // prefetches past the last column are clamped to valid addresses (and never used)
-  auto load_a = [&](int r0, int k, double (&a)[4]) {
+  auto load_a = [&](int r0, int k, double (&a)[RB]) {
     const double* col = Tc + (int64_t)min(k, kd - 1) * ld + li;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = col[min(r0 + wave_u + 4 * i, nrb - 1) * 16];
+    for (int i = 0; i < RB; ++i) a[i] = col[min(r0 + wave_u + 4 * i, nrb - 1) * 16];
   };
-  for (int r0 = 0; r0 < nrb; r0 += 16) {
-    d4_t acc[4][CB];
+  for (int r0 = 0; r0 < nrb; r0 += 4 * RB) {
+    d4_t acc[RB][CB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[i][cb] = (d4_t){0.0, 0.0, 0.0, 0.0};
     double xr[kHalf];
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
     load_half(0, 1, xr);
     store_half(xs[0], 1, xr);
     // matrix fragments of the next kPf64 K-steps are in flight while a step's MFMAs run
-    double a[kPf64][4];
+    double a[kPf64][RB];
 #pragma unroll
     for (int d = 0; d < kPf64; ++d) load_a(r0, 4 * d + lk, a[d]);
     __syncthreads();
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) b[cb] = xb[(4 * st + lk) * kXs + cb * 16 + li];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < RB; ++i)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb)
               acc[i][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[cb], a[d][i], acc[i][cb], 0, 0, 0);
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
       __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < RB; ++i) {
       const int rb = r0 + wave + 4 * i;
       if (rb >= nrb) continue;
       const int row = rb * 16 + li;
@@ -1242,10 +1244,19 @@ void launch_translate_cb(hipStream_t s, int kind, int prec, int np, int ntile,
   const int per_xcd = xcd_order ? (ntile + kXcds - 1) / kXcds : 0;
   const dim3 grid(xcd_order ? per_xcd * kXcds : ntile);
   if (prec == 0) {
+    // one row round of 28 row blocks for p = 16..20 (32-pair tiles; 64-pair tiles would need
+    // twice the accumulators)
+    const int nrb = trans_ld(np) / 16;
+    constexpr bool kWide = CB == 2;
     auto k = kind == 0   ? k_translate<0, CB>
              : kind == 1 ? k_translate<1, CB>
              : kind == 2 ? k_translate<2, CB>
                          : k_translate<3, CB>;
+    if (kWide && nrb > 16 && nrb <= 28)
+      k = kind == 0   ? k_translate<0, CB, kWide ? 7 : 4>
+          : kind == 1 ? k_translate<1, CB, kWide ? 7 : 4>
+          : kind == 2 ? k_translate<2, CB, kWide ? 7 : 4>
+                      : k_translate<3, CB, kWide ? 7 : 4>;
     k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.t64, X, Y,
                            ntile, per_xcd);
   } else if (prec == 1) {
