@@ -16,6 +16,8 @@
 //     and n.grad = n_z d_z + (n_x - i n_y)/2 (d_x + i d_y) + (n_x + i n_y)/2 (d_x - i d_y).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace gq {
@@ -861,9 +863,52 @@ __global__ __launch_bounds__(64 * NW, Q <= 5 ? 3 : 1) void k_m2qbxl(int P, const
     for (int i = 0; i < NQ; ++i) unsafeAtomicAdd(&Lq[(int64_t)i * nctr + c], acc[i]);
 }
 
+// f(integral_constant<int, I>) for I = B .. E-1, each with I a constant expression
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Stage 8 output rows per wave.  The NW waves of an item split the output degrees j
+// (each wave keeps the sums of its own rows only), balanced by longest-processing-time on
+// the row's work (2j + 1)(P - j + 1)^2, at P = 15 for q <= 5 and P = 20 above.
+template <int Q, int NW>
+struct L2qRows {
+  static constexpr int owner(int j) {
+    const int P = Q <= 5 ? 15 : 20;
+    long load[NW > 0 ? NW : 1] = {};
+    int own[Q + 1] = {};
+    bool done[Q + 1] = {};
+    for (int step = 0; step <= Q; ++step) {
+      int best = -1;
+      long bw = -1;
+      for (int jj = 0; jj <= Q; ++jj) {
+        const long w = (long)(2 * jj + 1) * (P - jj + 1) * (P - jj + 1);
+        if (!done[jj] && w > bw) {
+          bw = w;
+          best = jj;
+        }
+      }
+      int g = 0;
+      for (int h = 1; h < NW; ++h)
+        if (load[h] < load[g]) g = h;
+      own[best] = g;
+      load[g] += bw;
+      done[best] = true;
+    }
+    return own[j];
+  }
+};
+
 // PAIR: the item is two consecutive entries of at most 32 centers each (of two boxes); the
 // lower half of every wave serves the first, the upper half the second, each with its own
 // table, so the order loop stays uniform over the wave.
+// The waves split the output rows (L2qRows): every wave generates all harmonics of the
+// center offset and adds them into its own rows' sums only, so a wave holds a quarter of
+// the sums and no sums are combined across waves.
 template <int Q, int NW = qbxl_waves(Q), bool PAIR = false>
 __global__ __launch_bounds__(64 * NW, Q <= 5 ? (PAIR ? 3 : 4) : 1) void k_l2qbxl(int P, const int* __restrict__ it_box,
                                                            const int* __restrict__ it_c0,
@@ -905,57 +950,78 @@ __global__ __launch_bounds__(64 * NW, Q <= 5 ? (PAIR ? 3 : 4) : 1) void k_l2qbxl
   const double2* tb = tab + sub * TSZ;  // this lane's table
   const double vx = cx[c] - bctr[3 * b], vy = cy[c] - bctr[3 * b + 1], vz = cz[c] - bctr[3 * b + 2];
   const double r2 = vx * vx + vy * vy + vz * vz;
-  double acc[NQ];
+  auto rows = [&](auto wtag) {
+    constexpr int WV = decltype(wtag)::value;
+    double acc[NQ];
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
-  double dr = 1.0, di = 0.0;
-  for (int mu = 0; mu <= P; ++mu) {
-    if (mu > 0) {  // the diagonal R_mu^mu is carried by every wave
-      const double f = -0.5 / mu;
-      const double nr = f * (dr * vx - di * vy), ni = f * (dr * vy + di * vx);
-      dr = nr;
-      di = ni;
-    }
-    if (order_owner<NW>(mu) != wave) continue;  // uniform over the wave
-    const double sgn = (mu & 1) ? -1.0 : 1.0;
-    double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
-    for (int N = mu; N <= P; ++N) {
-      double rr, ri;
-      if (N == mu) {
-        rr = dr;
-        ri = di;
-      } else {
-        const double tt = invtab[N * kInvTab + mu];
-        const double c1 = (2.0 * N - 1.0) * vz;
-        rr = (c1 * p1r - r2 * p2r) * tt;
-        ri = (c1 * p1i - r2 * p2i) * tt;
-        p2r = p1r;
-        p2i = p1i;
+    for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
+    double dr = 1.0, di = 0.0;
+    for (int mu = 0; mu <= P; ++mu) {
+      if (mu > 0) {
+        const double f = -0.5 / mu;
+        const double nr = f * (dr * vx - di * vy), ni = f * (dr * vy + di * vx);
+        dr = nr;
+        di = ni;
       }
-      p1r = rr;
-      p1i = ri;
-      const double rnr = sgn * rr, rni = -sgn * ri;  // R^{-mu} = (-1)^mu conj(R^mu)
-      const double2* t1 = tb + (N * TB::W + mu + TB::MOFF);
-      const double2* t2 = tb + (N * TB::W - mu + TB::MOFF);
-#pragma unroll
-      for (int j = 0; j <= Q; ++j) {
-        const int n = N + j;
-        if (n > P) continue;  // uniform
-        if (mu <= n) {
-#pragma unroll
-          for (int k = 0; k <= j; ++k) cmac<Q>(acc, j, k, t1[j * TB::W + k], rr, ri);
+      const double sgn = (mu & 1) ? -1.0 : 1.0;
+      double p1r = 0, p1i = 0, p2r = 0, p2i = 0;
+      for (int N = mu; N <= P; ++N) {
+        double rr, ri;
+        if (N == mu) {
+          rr = dr;
+          ri = di;
+        } else {
+          const double tt = invtab[N * kInvTab + mu];
+          const double c1 = (2.0 * N - 1.0) * vz;
+          rr = (c1 * p1r - r2 * p2r) * tt;
+          ri = (c1 * p1i - r2 * p2i) * tt;
+          p2r = p1r;
+          p2i = p1i;
         }
-        if (mu > 0 && mu - j <= n) {
+        p1r = rr;
+        p1i = ri;
+        const double rnr = sgn * rr, rni = -sgn * ri;  // R^{-mu} = (-1)^mu conj(R^mu)
+        const double2* t1 = tb + (N * TB::W + mu + TB::MOFF);
+        const double2* t2 = tb + (N * TB::W - mu + TB::MOFF);
+        static_for<0, Q + 1>([&](auto jtag) {
+          constexpr int j = decltype(jtag)::value;
+          if constexpr (L2qRows<Q, NW>::owner(j) == WV) {
+            const int n = N + j;
+            if (n <= P) {  // uniform
+              if (mu <= n) {
 #pragma unroll
-          for (int k = 0; k <= j; ++k) cmac<Q>(acc, j, k, t2[j * TB::W + k], rnr, rni);
-        }
+                for (int k = 0; k <= j; ++k) cmac<Q>(acc, j, k, t1[j * TB::W + k], rr, ri);
+              }
+              if (mu > 0 && mu - j <= n) {
+#pragma unroll
+                for (int k = 0; k <= j; ++k) cmac<Q>(acc, j, k, t2[j * TB::W + k], rnr, rni);
+              }
+            }
+          }
+        });
       }
     }
+    if (!active) return;
+    static_for<0, Q + 1>([&](auto jtag) {
+      constexpr int j = decltype(jtag)::value;
+      if constexpr (L2qRows<Q, NW>::owner(j) == WV) {
+#pragma unroll
+        for (int i = j * j; i < (j + 1) * (j + 1); ++i) Lq[(int64_t)i * nctr + c] += acc[i];
+      }
+    });
+  };
+  static_assert(NW >= 1 && NW <= 4, "up to four waves per item");
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  if (wv == 0) rows(std::integral_constant<int, 0>{});
+  if constexpr (NW > 1) {
+    if (wv == 1) rows(std::integral_constant<int, 1>{});
   }
-  sum_waves<NQ, NW>(acc, reinterpret_cast<double*>(tab), (int)sizeof(tab));
-  if (wave != 0 || !active) return;
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) Lq[(int64_t)i * nctr + c] += acc[i];
+  if constexpr (NW > 2) {
+    if (wv == 2) rows(std::integral_constant<int, 2>{});
+  }
+  if constexpr (NW > 3) {
+    if (wv == 3) rows(std::integral_constant<int, 3>{});
+  }
 }
 
 // ------------------------------------------------------------------------------------
