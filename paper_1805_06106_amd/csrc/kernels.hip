@@ -740,6 +740,10 @@ __device__ __forceinline__ void cmac(double (&acc)[(Q + 1) * (Q + 1)], int j, in
 // kept.  Up to q = 5 the registers are capped for 3 (M2QBXL) and 4 (L2QBXL) waves per SIMD,
 // at the cost of 2 spilled VGPRs.
 constexpr int qbxl_waves(int q) { return q <= 8 ? 4 : 1; }
+// L2QBXL splits the output rows over its waves, so each keeps only its rows' sums, at every
+// q.  Eight waves would not raise the occupancy at q = 8 (85 against 97 VGPRs: 5 waves per
+// SIMD either way), since every wave also carries the harmonic recurrences.
+constexpr int l2qbxl_waves(int) { return 4; }
 
 // Wave that takes order mu: snake order over the NW waves, so that each gets the same
 // number of (order, degree) steps when the work of an order falls linearly with mu.
@@ -909,7 +913,7 @@ struct L2qRows {
 // The waves split the output rows (L2qRows): every wave generates all harmonics of the
 // center offset and adds them into its own rows' sums only, so a wave holds a quarter of
 // the sums and no sums are combined across waves.
-template <int Q, int NW = qbxl_waves(Q), bool PAIR = false>
+template <int Q, int NW = l2qbxl_waves(Q), bool PAIR = false>
 __global__ __launch_bounds__(64 * NW, Q <= 5 ? (PAIR ? 3 : 4) : 1) void k_l2qbxl(int P, const int* __restrict__ it_box,
                                                            const int* __restrict__ it_c0,
                                                            const int* __restrict__ it_nc,
@@ -1010,18 +1014,11 @@ __global__ __launch_bounds__(64 * NW, Q <= 5 ? (PAIR ? 3 : 4) : 1) void k_l2qbxl
       }
     });
   };
-  static_assert(NW >= 1 && NW <= 4, "up to four waves per item");
+  static_assert(NW >= 1 && NW <= 8, "up to eight waves per item");
   const int wv = __builtin_amdgcn_readfirstlane(wave);
-  if (wv == 0) rows(std::integral_constant<int, 0>{});
-  if constexpr (NW > 1) {
-    if (wv == 1) rows(std::integral_constant<int, 1>{});
-  }
-  if constexpr (NW > 2) {
-    if (wv == 2) rows(std::integral_constant<int, 2>{});
-  }
-  if constexpr (NW > 3) {
-    if (wv == 3) rows(std::integral_constant<int, 3>{});
-  }
+  static_for<0, NW>([&](auto wtag) {
+    if (wv == decltype(wtag)::value) rows(wtag);
+  });
 }
 
 // ------------------------------------------------------------------------------------
@@ -1235,7 +1232,7 @@ struct L2qbxlGo {
                  const int* it_nc, const double* bctr, const double* bh, const double* L,
                  const double* cx, const double* cy, const double* cz, double* Lq,
                  int64_t nctr) {
-    k_l2qbxl<Q><<<nitem, 64 * qbxl_waves(Q), 0, s>>>(p, it_box, it_c0, it_nc, bctr, bh, L, cx,
+    k_l2qbxl<Q><<<nitem, 64 * l2qbxl_waves(Q), 0, s>>>(p, it_box, it_c0, it_nc, bctr, bh, L, cx,
                                                     cy, cz, Lq, nctr);
   }
 };
@@ -1246,7 +1243,7 @@ struct L2qbxlPairGo {
                  const int* it_nc, const double* bctr, const double* bh, const double* L,
                  const double* cx, const double* cy, const double* cz, double* Lq,
                  int64_t nctr) {
-    k_l2qbxl<Q, qbxl_waves(Q), true><<<nitem, 64 * qbxl_waves(Q), 0, s>>>(
+    k_l2qbxl<Q, l2qbxl_waves(Q), true><<<nitem, 64 * l2qbxl_waves(Q), 0, s>>>(
         p, it_box, it_c0, it_nc, bctr, bh, L, cx, cy, cz, Lq, nctr);
   }
 };
