@@ -46,6 +46,8 @@ def tree_opts(args):
     opts = {"wfar_direct_max": args.wfar_direct_max, "level_restrict": bool(args.level_restrict)}
     if getattr(args, "nmax", None):
         opts["nmax"] = args.nmax
+    if getattr(args, "autotune_tree", 0):
+        opts["autotune_tree"] = True
     return opts
 
 
@@ -154,6 +156,11 @@ def main():
                          "with and without the XCD-aware order, and keep the fastest (outside "
                          "the timed region); 0 (default): the library's default tiles (width "
                          "64 for split FP32, 32 otherwise; XCD-aware order)")
+    ap.add_argument("--autotune-tree", type=int, choices=[0, 1], default=0,
+                    help="1: every plan chooses its nmax and Remark 4 threshold at creation "
+                         "by timing candidate trees around the given values "
+                         "(GQ_FLAG_AUTOTUNE_TREE; outside the timed region), and the values "
+                         "kept are reported")
     ap.add_argument("--m2l-rotation", type=int, choices=[0, 1], default=0,
                     help="1: FP64 M2L as rotate, translate along z, rotate back (three sparse "
                          "tile products) instead of one dense matrix per offset class")
@@ -408,6 +415,9 @@ def main():
                    "m2l_rotation": bool(args.m2l_rotation),
                    "m2l_autotune": bool(args.autotune),
                    "m2l_tile": [st.get("m2l_tile_cols"), st.get("m2l_xcd_order")],
+                   "tree_autotuned": ({"nmax": st.get("nmax"),
+                                       "wfar_direct_max": st.get("wfar_direct_max")}
+                                      if args.autotune_tree else None),
                    "schedule": ("near and far field on two streams" if args.overlap
                                 else "one stream")},
         "rel_err_vs_direct_qbx": err_direct,

@@ -91,6 +91,15 @@ typedef enum { GQ_FP64 = 0, GQ_FP32_SPLIT = 1, GQ_FP32 = 2, GQ_FP32_LEAD = 3 } g
    applies agree to rounding (about 1e-15 relative) but not bit for bit.  Batch members
    must all have it or all lack it; the batch plan inherits it. */
 #define GQ_FLAG_DETERMINISTIC (1u << 4)
+/* Choose the tree at plan creation: build and time complete candidate plans (one warm-up
+   and two timed applies of a unit density each, on hip_stream) with nmax at 1/2, 3/4, 1
+   and 3/2 of gq_params.nmax, then, when wfar_direct_max is nonzero, Remark 4's threshold
+   at 1/2 and 2 times its value with the best nmax, and keep the fastest.  The parameters
+   kept are in the nmax and wfar_direct_max fields of the statistics; plan_seconds includes
+   the search.  Candidates over max_device_bytes are skipped (GQ_ENOMEM if none fits); the
+   search also holds a density and a potential buffer of its own.  Not with
+   GQ_FLAG_HOST_ONLY. */
+#define GQ_FLAG_AUTOTUNE_TREE (1u << 5)
 /* Which interaction lists contribute (testing aid).  0 in bits 8..13 means all. */
 #define GQ_LIST_U (1u << 8)       /* List 1 (direct)            Stage 3 */
 #define GQ_LIST_V (1u << 9)       /* List 2 (M2L, then L2L)     Stages 4, 7, 8 */
@@ -164,6 +173,8 @@ typedef struct {
      of the source box, n_t centers of the target box), then the total of the six. */
   double modeled_flops[7];
   int64_t device_bytes;     /* device memory held by the plan (its workspace) */
+  int32_t nmax;             /* the tree's nmax and Remark 4 threshold in use (the given */
+  int32_t wfar_direct_max;  /* values, or those GQ_FLAG_AUTOTUNE_TREE kept) */
 } gq_stats_t;
 
 /*

@@ -30,6 +30,7 @@ GQ_FLAG_TIMING = 1 << 1
 GQ_FLAG_GRAPH = 1 << 2
 GQ_FLAG_AUTOTUNE = 1 << 3
 GQ_FLAG_DETERMINISTIC = 1 << 4
+GQ_FLAG_AUTOTUNE_TREE = 1 << 5
 GQ_LIST_U = 1 << 8
 GQ_LIST_V = 1 << 9
 GQ_LIST_WCLOSE = 1 << 10
@@ -70,7 +71,8 @@ class gq_stats_t(ctypes.Structure):
                 ("stage_ms", ctypes.c_double * 12), ("timed_applies", ctypes.c_int64),
                 ("m2l_tile_cols", ctypes.c_int32), ("m2l_xcd_order", ctypes.c_int32),
                 ("n_point_targets", ctypes.c_int64), ("modeled_flops", ctypes.c_double * 7),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("nmax", ctypes.c_int32),
+                ("wfar_direct_max", ctypes.c_int32)]
 
 
 class GQError(RuntimeError):
@@ -288,6 +290,7 @@ def gq_stats(plan):
         "n_point_targets": s.n_point_targets,
         "modeled_flops": dict(zip(list(LIST_INDEX) + ["total_lists"], list(s.modeled_flops))),
         "device_bytes": s.device_bytes,
+        "nmax": s.nmax, "wfar_direct_max": s.wfar_direct_max,
     }
 
 

@@ -1203,11 +1203,12 @@ extern "C" {
 
 const char* gq_last_error(void) { return g_err.c_str(); }
 
-gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_xyz,
-                         const double* src_w, const double* src_normal, int64_t n_ctr,
-                         const double* ctr_xyz, const double* ctr_radius, int64_t n_tgt,
-                         const double* tgt_xyz, const int64_t* tgt_center, void* hip_stream,
-                         gq_plan** out) {
+// One plan with the given parameters (gq_plan_create without GQ_FLAG_AUTOTUNE_TREE).
+static gq_status create_plan(const gq_params* prm, int64_t n_src, const double* src_xyz,
+                             const double* src_w, const double* src_normal, int64_t n_ctr,
+                             const double* ctr_xyz, const double* ctr_radius, int64_t n_tgt,
+                             const double* tgt_xyz, const int64_t* tgt_center,
+                             void* hip_stream, gq_plan** out) {
   g_err.clear();
   auto t0 = std::chrono::steady_clock::now();
   if (!prm || !out) return fail(GQ_EINVAL, "params and out must not be NULL");
@@ -1240,6 +1241,8 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
     return fail(GQ_EUNSUPPORTED, "M2L by rotation needs GQ_FP64 and p_fmm <= 15");
   if ((prm->flags & GQ_FLAG_TIMING) && (prm->flags & GQ_FLAG_GRAPH))
     return fail(GQ_EINVAL, "GQ_FLAG_TIMING and GQ_FLAG_GRAPH are exclusive");
+  if ((prm->flags & GQ_FLAG_AUTOTUNE_TREE) && (prm->flags & GQ_FLAG_HOST_ONLY))
+    return fail(GQ_EINVAL, "GQ_FLAG_AUTOTUNE_TREE needs a device plan, not a host-only one");
   if (prm->kernel == GQ_KERNEL_D && !src_normal) return fail(GQ_EINVAL, "double layer needs normals");
   if (!finite3(src_xyz, n_src) || !finite3(ctr_xyz, n_ctr) || !finite3(tgt_xyz, n_tgt))
     return fail(GQ_EINVAL, "non-finite coordinates");
@@ -1420,6 +1423,116 @@ gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = P;
   return GQ_OK;
+}
+
+// GQ_FLAG_AUTOTUNE_TREE: time one apply of candidate trees and keep the fastest.  nmax is
+// tried at 1/2, 3/4, 1 and 3/2 of the given value, then Remark 4's threshold (when
+// nonzero) at 1/2, 1 and 2 times the given value with the best nmax; the kept parameters
+// are reported in gq_stats_t.  Each candidate is a complete plan, built, timed (one warm-up
+// and two timed applies of a unit density on the plan's stream) and destroyed in turn.
+static gq_status create_plan_tuned(const gq_params* prm, int64_t n_src, const double* src_xyz,
+                                   const double* src_w, const double* src_normal,
+                                   int64_t n_ctr, const double* ctr_xyz,
+                                   const double* ctr_radius, int64_t n_tgt,
+                                   const double* tgt_xyz, const int64_t* tgt_center,
+                                   void* hip_stream, gq_plan** out) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)hip_stream;
+  gq_params base = *prm;
+  base.flags &= ~(GQ_FLAG_AUTOTUNE_TREE | GQ_FLAG_GRAPH | GQ_FLAG_TIMING | GQ_FLAG_AUTOTUNE);
+  double* dens = nullptr;
+  double* pot = nullptr;
+  GQ_HIP(hipMalloc(&dens, sizeof(double) * (size_t)prm->n_densities * n_src));
+  const hipError_t ep = hipMalloc(&pot, sizeof(double) * (size_t)prm->n_densities *
+                                            (n_tgt > 0 ? n_tgt : 1));
+  if (ep != hipSuccess) {
+    (void)hipFree(dens);
+    return fail(GQ_ENOMEM, std::string("autotune: ") + hipGetErrorString(ep));
+  }
+  gq::launch_fill(s, dens, (int64_t)prm->n_densities * n_src, 1.0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  gq_status st = GQ_OK;
+  double best_ms = 1e300;
+  gq_params best = base;
+  auto trial = [&](const gq_params& c) -> gq_status {
+    gq_plan* P = nullptr;
+    gq_status r = create_plan(&c, n_src, src_xyz, src_w, src_normal, n_ctr, ctr_xyz,
+                              ctr_radius, n_tgt, tgt_xyz, tgt_center, hip_stream, &P);
+    if (r == GQ_ENOMEM) return GQ_OK;  // a candidate over the workspace cap is skipped
+    if (r != GQ_OK) return r;
+    r = gq_apply(P, dens, pot, hip_stream);
+    hipError_t e = hipSuccess;
+    if (r == GQ_OK) e = hipEventRecord(e0, s);
+    for (int k = 0; k < 2 && r == GQ_OK && e == hipSuccess; ++k) r = gq_apply(P, dens, pot, hip_stream);
+    if (r == GQ_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+    if (r == GQ_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (r == GQ_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    gq_plan_destroy(P);
+    if (r != GQ_OK) return r;
+    if (e != hipSuccess)
+      return fail(GQ_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+    return GQ_OK;
+  };
+  const double fn[4] = {0.5, 0.75, 1.0, 1.5};
+  for (int i = 0; i < 4 && st == GQ_OK; ++i) {
+    gq_params c = base;
+    c.nmax = std::max(1, (int)std::lround(prm->nmax * fn[i]));
+    if (i > 0 && c.nmax == (int)std::lround(prm->nmax * fn[i - 1])) continue;
+    st = trial(c);
+  }
+  if (st == GQ_OK && prm->wfar_direct_max > 0) {
+    const int nm = best.nmax;
+    const int w[2] = {std::max(1, prm->wfar_direct_max / 2), 2 * prm->wfar_direct_max};
+    for (int i = 0; i < 2 && st == GQ_OK; ++i) {
+      gq_params c = base;
+      c.nmax = nm;
+      c.wfar_direct_max = w[i];
+      st = trial(c);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(dens);
+  (void)hipFree(pot);
+  if (st != GQ_OK) return st;
+  if (best_ms >= 1e300) return fail(GQ_ENOMEM, "no candidate tree fits the workspace cap");
+  gq_params fin = *prm;
+  fin.nmax = best.nmax;
+  fin.wfar_direct_max = best.wfar_direct_max;
+  fin.flags &= ~GQ_FLAG_AUTOTUNE_TREE;
+  st = create_plan(&fin, n_src, src_xyz, src_w, src_normal, n_ctr, ctr_xyz, ctr_radius, n_tgt,
+                   tgt_xyz, tgt_center, hip_stream, out);
+  if (st != GQ_OK) return st;
+  (*out)->prm.flags |= GQ_FLAG_AUTOTUNE_TREE;
+  (*out)->stats.plan_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return GQ_OK;
+}
+
+gq_status gq_plan_create(const gq_params* prm, int64_t n_src, const double* src_xyz,
+                         const double* src_w, const double* src_normal, int64_t n_ctr,
+                         const double* ctr_xyz, const double* ctr_radius, int64_t n_tgt,
+                         const double* tgt_xyz, const int64_t* tgt_center, void* hip_stream,
+                         gq_plan** out) {
+  if (prm && (prm->flags & GQ_FLAG_AUTOTUNE_TREE)) {
+    g_err.clear();
+    if (prm->flags & GQ_FLAG_HOST_ONLY)
+      return fail(GQ_EINVAL, "GQ_FLAG_AUTOTUNE_TREE needs a device plan, not a host-only one");
+    // the candidates' own validation reports bad inputs; only the tuner's buffer sizes are
+    // checked here
+    if (out && n_src > 0 && n_ctr > 0 && n_tgt >= 0 && prm->n_densities >= 1 && prm->nmax >= 1)
+      return create_plan_tuned(prm, n_src, src_xyz, src_w, src_normal, n_ctr, ctr_xyz,
+                               ctr_radius, n_tgt, tgt_xyz, tgt_center, hip_stream, out);
+  }
+  return create_plan(prm, n_src, src_xyz, src_w, src_normal, n_ctr, ctr_xyz, ctr_radius, n_tgt,
+                     tgt_xyz, tgt_center, hip_stream, out);
 }
 
 }  // extern "C"
@@ -1684,6 +1797,8 @@ gq_status gq_stats(gq_plan* P, gq_stats_t* out) {
   }
   P->stats.n_point_targets = P->n_pt;
   P->stats.device_bytes = P->dev_bytes;
+  P->stats.nmax = P->prm.nmax;
+  P->stats.wfar_direct_max = P->prm.wfar_direct_max;
   {
     // Table 7: q^2 per (source, center) pair of Lists 1, 3-close, 4-close; p^3 per List 2
     // pair and per List 3-far (box, center) pair; p^2 per List 4-far (source, box) pair

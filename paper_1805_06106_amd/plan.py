@@ -17,10 +17,11 @@ class Plan:
                  host_only=False, lists=None, wfar_direct_max=0, precision="fp64",
                  graph=False, autotune=False, tcr_norm="l2", level_restrict=False,
                  m2l_rotation=False, overlap=False, max_device_bytes=0, deterministic=False,
-                 stream=None):
+                 autotune_tree=False, stream=None):
         flags = ((C.GQ_FLAG_TIMING if timing else 0) | (C.GQ_FLAG_HOST_ONLY if host_only else 0)
                  | (C.GQ_FLAG_GRAPH if graph else 0) | (C.GQ_FLAG_AUTOTUNE if autotune else 0)
-                 | (C.GQ_FLAG_DETERMINISTIC if deterministic else 0))
+                 | (C.GQ_FLAG_DETERMINISTIC if deterministic else 0)
+                 | (C.GQ_FLAG_AUTOTUNE_TREE if autotune_tree else 0))
         self.params = C.make_params(p_qbx, p_fmm, nmax=nmax, tcf=tcf, kernel=kernel,
                                     n_densities=n_densities, flags=flags, lists=lists,
                                     wfar_direct_max=wfar_direct_max, precision=precision,

@@ -117,3 +117,24 @@ def test_device_memory_cap():
     assert rel(p1.cpu().numpy(), p0.cpu().numpy()) < 1e-14
     # the refused creations left the device usable and the existing plans intact
     assert rel(P0.apply(d).cpu().numpy(), p0.cpu().numpy()) < 1e-14
+
+
+def test_autotuned_tree():
+    """GQ_FLAG_AUTOTUNE_TREE builds and times candidate trees and keeps one of them; the
+    plan it returns evaluates like any plan with the kept parameters (against Tier B built
+    with them)."""
+    import torch
+
+    from paper_1805_06106_amd import Plan
+
+    w = workload_tiny(level=2, order=2, kernel="D", p_qbx=5, p_fmm=15, nmax=48)
+    print("[gpu] autotuned tree", flush=True)
+    P = Plan.from_workload(w, autotune_tree=True, wfar_direct_max=16, level_restrict=True)
+    st = P.stats()
+    assert st["nmax"] in (24, 36, 48, 72), st["nmax"]
+    assert st["wfar_direct_max"] in (8, 16, 32), st["wfar_direct_max"]
+    pot = P.apply(torch.tensor(w.density, dtype=torch.float64, device="cuda:0")).cpu().numpy()
+    F = OracleFMM(w, nmax=st["nmax"], wfar_direct_max=st["wfar_direct_max"], level_restrict=True)
+    tids, ref, _ = F.evaluate()
+    assert rel(pot[0][tids], ref) < 1e-10
+    P.close()

@@ -230,6 +230,10 @@ def test_invalid_arguments(gq):
     with pytest.raises(G.GQError) as e:
         G.Plan(**_args(w, max_device_bytes=-1))
     assert e.value.status == 1 and "max_device_bytes" in str(e.value)
+    # the tree search times applies, so it needs a device plan
+    with pytest.raises(G.GQError) as e:
+        G.Plan(**_args(w, autotune_tree=True))
+    assert e.value.status == 1 and "AUTOTUNE_TREE" in str(e.value)
     with pytest.raises(G.GQError):
         G.Plan(**_args(w, src_normal=None))
     bad = w.src_normal.copy()
