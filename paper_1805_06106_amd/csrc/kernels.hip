@@ -238,8 +238,8 @@ __global__ __launch_bounds__(256) void k_translate(int np, const int* __restrict
 typedef float f4_t __attribute__((ext_vector_type(4)));
 constexpr int kLead = kLeadCols;  // leading packed coefficients contracted in FP64 (MODE 1, 2)
 
-template <int KIND, int CB, int MODE>
-__global__ __launch_bounds__(256, MODE == 2 && CB == 2 ? 4 : 1) void k_translate32(int np, const int* __restrict__ tile_cls,
+template <int KIND, int CB, int MODE, int RB = 4>
+__global__ __launch_bounds__(256, MODE == 2 && CB == 2 && RB == 4 ? 4 : 1) void k_translate32(int np, const int* __restrict__ tile_cls,
                                                      const int* __restrict__ tile_beg,
                                                      const int* __restrict__ tile_cnt,
                                                      const int* __restrict__ pair_src,
@@ -301,21 +301,21 @@ __global__ __launch_bounds__(256, MODE == 2 && CB == 2 ? 4 : 1) void k_translate
       if (kLeadOn && lead && lane < kLead) xl64[lane * kXs + col] = xr[u];
     }
   };
-  auto load_a = [&](int r0, int k, float (&ah)[4], float (&al)[4]) {
+  auto load_a = [&](int r0, int k, float (&ah)[RB], float (&al)[RB]) {
     const int64_t col = moff + (int64_t)min(k, kd - 1) * ld + li;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < RB; ++i) {
       const int64_t off = col + min(r0 + wave_u + 4 * i, nrb - 1) * 16;
       ah[i] = Thi[off];
       al[i] = MODE == 1 ? Tlo[off] : 0.0f;
     }
   };
   constexpr int k0 = kLeadOn ? kLead : 0;  // first column on the FP32 matrix cores
-  for (int r0 = 0; r0 < nrb; r0 += 16) {
-    f4_t acc[4][CB];      // FP32 accumulation (MODE 0, 2)
-    double acc64[4][CB][MODE == 1 ? 4 : 1];  // FP64 accumulation of the steps (MODE 1)
+  for (int r0 = 0; r0 < nrb; r0 += 4 * RB) {
+    f4_t acc[RB][CB];      // FP32 accumulation (MODE 0, 2)
+    double acc64[RB][CB][MODE == 1 ? 4 : 1];  // FP64 accumulation of the steps (MODE 1)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
         acc[i][cb] = (f4_t){0.f, 0.f, 0.f, 0.f};
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256, MODE == 2 && CB == 2 ? 4 : 1) void k_translate
     store_half(xs[0], 0, xr, r0 == 0);
     load_half(0, 1, xr);
     store_half(xs[0], 1, xr, r0 == 0);
-    float ah[kPf][4], al[kPf][4];
+    float ah[kPf][RB], al[kPf][RB];
 #pragma unroll
     for (int d = 0; d < kPf; ++d) load_a(r0, k0 + 4 * d + lk, ah[d], al[d]);
     __syncthreads();
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256, MODE == 2 && CB == 2 ? 4 : 1) void k_translate
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) b[cb] = xb[(4 * st + lk) * kXs + cb * 16 + li];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < RB; ++i)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
               if (MODE == 1) {
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(256, MODE == 2 && CB == 2 ? 4 : 1) void k_translate
     // accumulator layout: (pair 4 (l/16) + r, row l%16) of the transposed product.
     const int pli = 4 * (li & 3) + (li >> 2);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < RB; ++i) {
       const int rb = r0 + wave_u + 4 * i;
       if (rb >= nrb) continue;  // wave-uniform
       const int row = rb * 16 + li;
@@ -1293,6 +1293,17 @@ void launch_translate32(hipStream_t s, dim3 grid, int kind, int np, int ntile, c
            : kind == 1 ? k_translate32<1, CB, MODE>
            : kind == 2 ? k_translate32<2, CB, MODE>
                        : k_translate32<3, CB, MODE>;
+  // one row round of 28 row blocks for p = 16..20, uncorrected mode with 32-pair tiles only:
+  // measured on the ellipsoid, M2L 82 against 93 ms; the leading-degree mode lost (104
+  // against 99 ms: 2 waves per SIMD instead of 4), and the split mode's FP64 step sums
+  // would not fit
+  constexpr bool kWide = CB == 2 && MODE == 0;
+  const int nrb = trans_ld(np) / 16;
+  if (kWide && nrb > 16 && nrb <= 28)
+    k = kind == 0   ? k_translate32<0, CB, MODE, kWide ? 7 : 4>
+        : kind == 1 ? k_translate32<1, CB, MODE, kWide ? 7 : 4>
+        : kind == 2 ? k_translate32<2, CB, MODE, kWide ? 7 : 4>
+                    : k_translate32<3, CB, MODE, kWide ? 7 : 4>;
   k<<<grid, 256, 0, s>>>(np, tile_cls, tile_beg, tile_cnt, pair_src, pair_dst, T.hi, T.lo,
                          T.lead, T.s_in, T.s_out, X, Y, ntile, per_xcd);
 }
