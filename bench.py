@@ -32,11 +32,11 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "9443eeb02fb7e08de202a4964b56abc20aea834097d29350b5e1ade9bbef4dce",
+    "kernels_sha256": "072b5aea8384a457fe89e8a5e2557e5eeca7012b6488a7d70f93d7c2b43bbe90",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True, "nmax": 192,
     "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 6.60221e+09, "m2l": 2.292889e+10, "m2qbxl": 1.651e+07,
-                         "l2qbxl": 9.7314e+08},
+    "bytes_per_launch": {"p2qbxl": 6.59911e+09, "m2l": 2.292814e+10, "m2qbxl": 1.652e+07,
+                         "l2qbxl": 9.7312e+08},
 }
 
 
