@@ -79,6 +79,23 @@ def translate(p: int) -> int:
     return 2 * n * n
 
 
+def rotation_m2l_pair(p: int) -> float:
+    """Executed flops per pair of the rotation-factored M2L (T = B Z A): per 16 pairs, the
+    nonzero 16 x 16 tiles of A and B (block diagonal by degree), 4 matrix-core k-steps
+    each, and the order blocks of Z (p + 1 - m rows each, k-steps of 4 past its padding),
+    every k-step 16 x 16 x 4 multiply-adds."""
+    npc = (p + 1) ** 2
+    ntr = (npc + 15) // 16
+
+    def touches(r, n):
+        return n * n <= 16 * r + 15 and (n + 1) ** 2 - 1 >= 16 * r
+
+    ntile = sum(1 for r in range(ntr) for c in range(ntr)
+                if any(touches(r, n) and touches(c, n) for n in range(p + 1)))
+    zsteps = sum(-(-(p + 1 - (b + 1) // 2) // 4) for b in range(2 * p + 1))
+    return (2 * 4 * ntile + zsteps) * 2 * 16 * 16 * 4 / 16
+
+
 def qbxl2p_target(q: int) -> int:
     return 8 + 10 * q + 9 * (q * (q + 1) // 2) + 4 * (q + 1) ** 2 + 1
 

@@ -156,10 +156,8 @@ struct gq_plan {
   int *d_pp_box = nullptr, *d_pp_t0 = nullptr, *d_pp_nt = nullptr;
   int *d_pm_t0 = nullptr, *d_pm_nt = nullptr, *d_pm_w0 = nullptr, *d_pm_w1 = nullptr;
   double *T_m2m = nullptr, *T_l2l = nullptr, *T_m2l = nullptr;
-  // M2L by rotation: per-class tiles of A, B and order blocks of Z, and their shared index
+  // M2L by rotation: per-class tiles of A, B and order blocks of Z
   double *R_A = nullptr, *R_Z = nullptr, *R_B = nullptr;
-  int *d_rot_row_beg = nullptr, *d_rot_tile_c = nullptr, *d_rot_rowmap = nullptr,
-      *d_rot_row_order = nullptr;
   gq::RotMats rot{};
   float *T32_m2m[2] = {nullptr, nullptr}, *T32_l2l[2] = {nullptr, nullptr},
         *T32_m2l[2] = {nullptr, nullptr};  // (hi, lo)
@@ -569,7 +567,8 @@ gq_status build_work(gq_plan* P) {
 
 // M2L by rotation: the factors A, Z, B of every class (host threads over classes), cut
 // into the device tiles: the nonzero 16 x 16 tiles of the block-diagonal A and B (the same
-// positions for every class) and the order blocks of Z.
+// positions for every class, which the kernel knows at compile time) and the order blocks
+// of Z.
 gq_status upload_rotation(gq_plan* P, hipStream_t s) {
   const int p = P->prm.p_fmm, np = P->np;
   const int ntr = (np + 15) / 16;
@@ -588,22 +587,15 @@ gq_status upload_rotation(gq_plan* P, hipStream_t s) {
   }
   row_beg[ntr] = (int)tile_c.size();
   const int ntile = (int)tile_c.size();
+  const int kt = gq::m2l_rot_tiles(p);
+  if (kt >= 0 && kt != ntile)
+    return fail(GQ_EUNSUPPORTED, "rotation tile shape differs from the kernel's");
   // order blocks: m = 0 (real parts), then (m, real), (m, imaginary) for m = 1..p
   const int nblk = 2 * p + 1;
   std::vector<int> rowmap((size_t)nblk * 16, -1);
   for (int b = 0; b < nblk; ++b) {
     const int m = (b + 1) / 2, im = b > 0 && (b % 2 == 0);
     for (int n = m; n <= p; ++n) rowmap[b * 16 + n - m] = n * n + (m ? 2 * m - 1 + im : 0);
-  }
-  // wave assignment of the row tiles: heaviest first, dealt to the waves in snake order
-  std::vector<int> byc(ntr), row_order(16, -1);  // 4 waves x 4 slots; ntr <= 16
-  for (int r = 0; r < ntr; ++r) byc[r] = r;
-  std::stable_sort(byc.begin(), byc.end(), [&](int a, int b) {
-    return row_beg[a + 1] - row_beg[a] > row_beg[b + 1] - row_beg[b];
-  });
-  for (int i = 0; i < ntr; ++i) {
-    const int round = i / 4, pos = i % 4, wave = round % 2 ? 3 - pos : pos;
-    row_order[wave + 4 * round] = byc[i];
   }
   const size_t ncls = P->cls_keys.size();
   std::vector<double> hA(ncls * ntile * 256, 0.0), hB(ncls * ntile * 256, 0.0),
@@ -620,7 +612,8 @@ gq_status upload_rotation(gq_plan* P, hipStream_t s) {
             for (int i = 0; i < 16; ++i) {
               const int row = 16 * r + i, col = 16 * tile_c[t] + k;
               if (row >= np || col >= np) continue;
-              const size_t at = (c * ntile + t) * 256 + k * 16 + i;
+              // lane-major: lane 16 (k % 4) + i, k-step k / 4
+              const size_t at = (c * ntile + t) * 256 + (16 * (k % 4) + i) * 4 + k / 4;
               hA[at] = A[(size_t)col * np + row];
               hB[at] = B[(size_t)col * np + row];
             }
@@ -628,7 +621,8 @@ gq_status upload_rotation(gq_plan* P, hipStream_t s) {
         for (int k = 0; k < 16; ++k)
           for (int i = 0; i < 16; ++i) {
             const int row = rowmap[b * 16 + i], col = rowmap[b * 16 + k];
-            if (row >= 0 && col >= 0) hZ[(c * nblk + b) * 256 + k * 16 + i] = Z[(size_t)col * np + row];
+            if (row >= 0 && col >= 0)
+              hZ[(c * nblk + b) * 256 + (16 * (k % 4) + i) * 4 + k / 4] = Z[(size_t)col * np + row];
           }
     }
   };
@@ -640,13 +634,8 @@ gq_status upload_rotation(gq_plan* P, hipStream_t s) {
   GQ_TRY(upload(P, hA, &P->R_A, s));
   GQ_TRY(upload(P, hZ, &P->R_Z, s));
   GQ_TRY(upload(P, hB, &P->R_B, s));
-  GQ_TRY(upload(P, row_beg, &P->d_rot_row_beg, s));
-  GQ_TRY(upload(P, tile_c, &P->d_rot_tile_c, s));
-  GQ_TRY(upload(P, rowmap, &P->d_rot_rowmap, s));
-  GQ_TRY(upload(P, row_order, &P->d_rot_row_order, s));
   GQ_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
-  P->rot = gq::RotMats{P->R_A, P->R_Z, P->R_B, P->d_rot_row_beg, P->d_rot_tile_c,
-                       P->d_rot_rowmap, P->d_rot_row_order, ntile, nblk, ntr};
+  P->rot = gq::RotMats{P->R_A, P->R_Z, P->R_B};
   return GQ_OK;
 }
 

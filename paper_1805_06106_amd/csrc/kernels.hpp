@@ -33,18 +33,16 @@ void launch_strength_interp(hipStream_t s, int64_t n, const int64_t* order, cons
 void launch_fill(hipStream_t s, double* p, int64_t n, double v);
 
 // M2L by rotation (kernels_rot.hip), FP64, p_fmm <= 15: per class, the ntile nonzero 16 x 16
-// tiles of A and B (tile t: row tile r with row_beg[r] <= t < row_beg[r + 1], column tile
-// tile_c[t]; element (row i, column k) at [k * 16 + i]), and nblk order blocks of Z (block b
-// maps the packed rows rowmap[16 b + i], -1 = padding; element at [k * 16 + i]).
-constexpr int kRotCols = 32;   // pairs per tile
-constexpr int kRotRows = 256;  // rows of the LDS working matrix ((p+1)^2 <= 256)
-// row_order[16]: the row tiles in the order the 4 waves take them (wave w: entries w, w+4,
-// w+8, w+12; -1 = none), balancing their nonzero tile counts; at most 16 row tiles.
+// tiles of A and B in row-tile order (row tile r, then column tile ascending), and the 2p+1
+// order blocks of Z (block b holds the rows n^2 + b for n >= (b + 1) / 2 in increasing n,
+// padded to 16).  Within a tile, element (row i, column k) is at [(16 (k % 4) + i) 4 + k / 4]:
+// the matrix-core operand of lane 16 (k % 4) + i in k-step k / 4.
+constexpr int kRotCols = 64;  // pairs per tile, 16 per wave
 struct RotMats {
   const double *A, *Z, *B;
-  const int *row_beg, *tile_c, *rowmap, *row_order;
-  int ntile, nblk, ntr;
 };
+// The nonzero tiles of A per class that the kernel for order p assumes (-1: p > 15).
+int m2l_rot_tiles(int p);
 void launch_m2l_rot(hipStream_t s, int np, int ntile, const int* tile_cls, const int* tile_beg,
                     const int* tile_cnt, const int* pair_src, const int* pair_dst,
                     const RotMats& R, const double* X, double* Y, bool xcd_order,

@@ -216,10 +216,12 @@ def test_gpu_level_restricted_vs_tier_b(dev, case):
 
 
 @pytest.mark.parametrize("case", ["S-l1-n32", "D-l2-flat"])
-@pytest.mark.parametrize("p_fmm", [5, 15])
+@pytest.mark.parametrize("p_fmm", [3, 5, 10, 15])
 def test_gpu_m2l_rotation_vs_tier_b(dev, case, p_fmm):
     """M2L by rotation (T = B Z A on the matrix cores) against the oracle, whose M2L is the
-    plain translation formula, and against the dense-matrix M2L of the library."""
+    plain translation formula, and against the dense-matrix M2L of the library.  The kernel
+    is compiled per order: p_fmm 3 fits one row tile, 5 and 10 end in a ragged one, 15
+    fills 16."""
     kw = dict(CASES[case])
     kw["p_fmm"] = p_fmm
     w = workload_tiny(**kw)
