@@ -161,9 +161,10 @@ def main():
                          "by timing candidate trees around the given values "
                          "(GQ_FLAG_AUTOTUNE_TREE; outside the timed region), and the values "
                          "kept are reported")
-    ap.add_argument("--m2l-rotation", type=int, choices=[0, 1], default=0,
+    ap.add_argument("--m2l-rotation", type=int, choices=[-1, 0, 1], default=-1,
                     help="1: FP64 M2L as rotate, translate along z, rotate back (three sparse "
-                         "tile products) instead of one dense matrix per offset class")
+                         "tile products) instead of one dense matrix per offset class; 0: "
+                         "dense; -1 (default): rotation where it is built (FP64, p_fmm <= 15)")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 200 if args.workload == "c5" else 10
@@ -226,11 +227,13 @@ def main():
         f"kernel {w.kernel}, p_qbx={w.p_qbx}, p_fmm={w.p_fmm} ({time.time() - t0:.1f}s)")
     dens = torch.tensor(w.density[:1], dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
+    # the FP64 M2L form: the rotation-factored kernel covers p_fmm <= 15
+    rotation = args.m2l_rotation == 1 or (args.m2l_rotation == -1 and w.p_fmm <= 15)
 
     def run(precision, deterministic=False):
         t0 = time.time()
         plan = Plan.from_workload(w, timing=True, precision=precision,
-                                  m2l_rotation=bool(args.m2l_rotation) and precision == "fp64",
+                                  m2l_rotation=rotation and precision == "fp64",
                                   overlap=bool(args.overlap), autotune=bool(args.autotune),
                                   deterministic=deterministic, **tree_opts(args))
         plan_wall = time.time() - t0
@@ -309,10 +312,10 @@ def main():
         per_stage[s] = {"ms": round(ms, 4), "tflops": round(f / (ms * 1e-3) / 1e12, 3) if ms > 0 else None}
     # matrix-core use: the executed flops (the dense product's, or the rotation's three
     # sparse products) over the time and the FP64 MFMA peak
-    m2l_exec = (st["pairs"]["V"] * CM.rotation_m2l_pair(w.p_fmm) if args.m2l_rotation
+    m2l_exec = (st["pairs"]["V"] * CM.rotation_m2l_pair(w.p_fmm) if rotation
                 else flops["m2l"])
     m2l = {"engine": "fp64 mfma (v_mfma_f64_16x16x4f64)"
-                     + (", rotation-factored" if args.m2l_rotation else ", dense"),
+                     + (", rotation-factored" if rotation else ", dense"),
            "ms": round(stage_ms["m2l"], 4),
            "dense_equivalent_tflops": per_stage["m2l"]["tflops"],
            "executed_flops": m2l_exec,
@@ -418,7 +421,7 @@ def main():
                    "nmax": args.nmax or w.nmax, "tcf": w.tcf, "n_densities": 1, "precision": "fp64",
                    "wfar_direct_max": args.wfar_direct_max,
                    "level_restrict": bool(args.level_restrict),
-                   "m2l_rotation": bool(args.m2l_rotation),
+                   "m2l_rotation": rotation,
                    "m2l_autotune": bool(args.autotune),
                    "m2l_tile": [st.get("m2l_tile_cols"), st.get("m2l_xcd_order")],
                    "tree_autotuned": ({"nmax": st.get("nmax"),

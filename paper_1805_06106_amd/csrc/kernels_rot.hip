@@ -190,7 +190,8 @@ __global__ __launch_bounds__(64 * kRotwWaves, kRotwOcc) void k_m2l_rotw(
   });
   // stage 1: y = A x over the nonzero tiles of A in row-tile order.  The operands of tile
   // j + D are loaded while tile j is multiplied (a ring of D tiles), and scheduling barriers
-  // keep the compiler from moving the loads next to their use.
+  // keep the compiler from moving the loads next to their use (stage 2 has none: there the
+  // compiler overlaps one order block's LDS reads with the previous block's products).
   constexpr int NT = S.ntile, D = kRotwD;
   d2 ra[D][2];
   static_for<0, (D < NT ? D : NT)>([&](auto jj) {
@@ -264,7 +265,6 @@ __global__ __launch_bounds__(64 * kRotwWaves, kRotwOcc) void k_m2l_rotw(
         const int i = lk + 4 * r;
         if (4 * r < len) W[(i < len ? base + i : TR) * 16 + li] = acc[r];
       }
-      __builtin_amdgcn_sched_barrier(0);
     });
     static_for<0, NTR>([&](auto tt) {
       constexpr int t = decltype(tt)::value;

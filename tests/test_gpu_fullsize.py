@@ -1,8 +1,8 @@
 """GPU parity at full size, in the benchmark's launch configuration.
 
 The urchin (573,440 sources, 1,146,880 centers, double layer, p_qbx = 5, p_fmm = 15,
-nmax 192, level-restricted tree, Remark 4 threshold 64) and the ellipsoid (2,293,760 sources, single layer, 8/20) are
-evaluated whole on the GPU.  The oracle checks sampled centers: Tier B evaluates the same
+nmax 192, level-restricted tree, Remark 4 threshold 64, rotation-factored M2L) and the
+ellipsoid (2,293,760 sources, single layer, 8/20, dense M2L) are evaluated whole on the GPU.  The oracle checks sampled centers: Tier B evaluates the same
 GIGAQBX algorithm one center at a time (its own tree and lists), Tier A the direct QBX sum.
 Bars: 1e-8 relative to the sampled oracle values' l-inf norm against Tier B (asserted at
 1e-10); against Tier A the acceleration error must stay under Theorem 1's (3/4)^(p+1).
@@ -18,20 +18,21 @@ from workloads import workload_c2, workload_c4
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
 TOL = 1e-10
 BENCH_TREE = dict(wfar_direct_max=64, level_restrict=True, nmax=192)  # bench.py's urchin defaults
+BENCH_M2L = dict(m2l_rotation=True)  # bench.py's FP64 M2L at p_fmm <= 15
 
 
 def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-def _gpu(w, tree, densities=None, precision="fp64"):
+def _gpu(w, tree, densities=None, precision="fp64", **opts):
     import torch
 
     import paper_1805_06106_amd  # noqa: F401  (fails loudly without the library)
     from paper_1805_06106_amd import Plan
 
     dens = w.density if densities is None else densities
-    P = Plan.from_workload(w, n_densities=dens.shape[0], precision=precision, **tree)
+    P = Plan.from_workload(w, n_densities=dens.shape[0], precision=precision, **tree, **opts)
     d = torch.tensor(dens, dtype=torch.float64, device="cuda:0")
     pot = P.apply(d)
     torch.cuda.synchronize()
@@ -48,8 +49,14 @@ def urchin():
 
 def test_urchin_sampled_vs_tier_b_and_a(urchin):
     w = urchin
-    print(f"[gpu] urchin D 5/15 n_src={w.n_src} {BENCH_TREE}", flush=True)
-    pot = _gpu(w, BENCH_TREE)[0]
+    print(f"[gpu] urchin D 5/15 n_src={w.n_src} {BENCH_TREE} {BENCH_M2L}", flush=True)
+    pot = _gpu(w, BENCH_TREE, **BENCH_M2L)[0]
+    # every target: the rotation-factored M2L against the dense one (factors fitted to
+    # about 1e-12 of the dense matrix, row-relative)
+    dense = _gpu(w, BENCH_TREE)[0]
+    err_d = rel(pot, dense)
+    print(f"[gpu] urchin rotation vs dense M2L, all targets: {err_d:.3e}", flush=True)
+    assert err_d < 1e-11
     rng = np.random.default_rng(20)
     cs = np.sort(rng.choice(w.n_ctr, 48, replace=False))
     # plus the first and the last center of the input order
