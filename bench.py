@@ -32,10 +32,10 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "072b5aea8384a457fe89e8a5e2557e5eeca7012b6488a7d70f93d7c2b43bbe90",
+    "kernels_sha256": "e71a27355d69a235305bdbdd7879f0e8a15c273adcd86a9d356a9260cb4f5bf6",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True, "nmax": 192,
-    "precision": "fp64",
-    "bytes_per_launch": {"p2qbxl": 6.59911e+09, "m2l": 2.292814e+10, "m2qbxl": 1.652e+07,
+    "precision": "fp64", "m2l_rotation": True,
+    "bytes_per_launch": {"p2qbxl": 6.59750e+09, "m2l": 2.246058e+10, "m2qbxl": 1.653e+07,
                          "l2qbxl": 9.7312e+08},
 }
 
@@ -51,7 +51,7 @@ def tree_opts(args):
     return opts
 
 
-def counter_traffic(kernel, workload, wfar_direct_max, level_restrict, nmax):
+def counter_traffic(kernel, workload, wfar_direct_max, level_restrict, nmax, m2l_rotation):
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_1805_06106_amd", "csrc")
@@ -64,7 +64,8 @@ def counter_traffic(kernel, workload, wfar_direct_max, level_restrict, nmax):
     c = COUNTER_TRAFFIC
     if (h != c["kernels_sha256"] or workload != c["workload"]
             or wfar_direct_max != c["wfar_direct_max"]
-            or level_restrict != c.get("level_restrict", False) or nmax != c.get("nmax")):
+            or level_restrict != c.get("level_restrict", False) or nmax != c.get("nmax")
+            or m2l_rotation != c.get("m2l_rotation", False)):
         return None
     return c["bytes_per_launch"].get(kernel)
 
@@ -298,7 +299,8 @@ def main():
                 "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
                 "traffic": counter_traffic(dominant, w.name, args.wfar_direct_max,
-                                           bool(args.level_restrict), args.nmax or w.nmax),
+                                           bool(args.level_restrict), args.nmax or w.nmax,
+                                           rotation),
                 "flops_per_launch": flops[dominant], "ms_per_launch": round(dom_ms, 4)}
     if alone:
         # the same kernel with the far field not running beside it

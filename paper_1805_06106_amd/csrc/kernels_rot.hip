@@ -217,17 +217,12 @@ __global__ __launch_bounds__(64 * kRotwWaves, kRotwOcc) void k_m2l_rotw(
     if constexpr (j + 1 == S.row_beg[t + 1]) y[t] = acc;
     __builtin_amdgcn_sched_barrier(0);
   });
-  // the first operands of stages 2 and 3, in flight while the next ones start
-  d2 rz[D][2], rb[D][2];
+  // the first operands of stage 2, in flight while the LDS is written
+  d2 rz[D][2];
   static_for<0, (D < NBLK ? D : NBLK)>([&](auto bb) {
     constexpr int b = decltype(bb)::value;
     rz[b][0] = Z[b * 128];
     rz[b][1] = Z[b * 128 + 1];
-  });
-  static_for<0, (D < NT ? D : NT)>([&](auto jj) {
-    constexpr int j = decltype(jj)::value;
-    rb[j][0] = B[j * 128];
-    rb[j][1] = B[j * 128 + 1];
   });
   __builtin_amdgcn_sched_barrier(0);
   // stage 2: y = Z y, one LDS group of order blocks at a time
@@ -279,7 +274,14 @@ __global__ __launch_bounds__(64 * kRotwWaves, kRotwOcc) void k_m2l_rotw(
       });
     });
   });
-  // stage 3: L^T += y^T B^T; register r of lane l: pair lk + 4 r, row 16 t + li
+  // stage 3: L^T += y^T B^T; register r of lane l: pair lk + 4 r, row 16 t + li.  Its
+  // first operands are loaded only now: in flight during stage 2 they cost spills.
+  d2 rb[D][2];
+  static_for<0, (D < NT ? D : NT)>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    rb[j][0] = B[j * 128];
+    rb[j][1] = B[j * 128 + 1];
+  });
   int dst[4];
   bool ok[4];
 #pragma unroll
