@@ -879,12 +879,16 @@ def bench_batch(args, dev):
 
     from concurrent.futures import ThreadPoolExecutor
 
+    # the FP64 M2L form, as for the single surface
+    rotation = args.m2l_rotation == 1 or (args.m2l_rotation == -1 and ws[0].p_fmm <= 15)
+
     def make_plans(prec):
         # host planning runs in the library without the GIL: 8 plans at a time
         out = [None] * len(ws)
 
         def one(k):
             out[k] = Plan.from_workload(ws[k], n_densities=nd, precision=prec,
+                                        m2l_rotation=rotation and prec == "fp64",
                                         **tree_opts(args))
             return k
 
@@ -980,7 +984,8 @@ def bench_batch(args, dev):
                    "n_sources": n_src, "n_targets": n_tgt,
                    "levels": [w.meta["level"] for w in ws],
                    "wfar_direct_max": args.wfar_direct_max,
-                   "level_restrict": bool(args.level_restrict)},
+                   "level_restrict": bool(args.level_restrict),
+                   "fp64_m2l_rotation": rotation},
         "plain_fp64": {"value": round(nd * n_tgt / (ms_plain * 1e-3), 1),
                        "ms_per_apply": round(ms_plain, 3), "plan_seconds": round(plan64_s, 2)},
         "batched_fp64_graph": res["fp64"],

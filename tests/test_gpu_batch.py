@@ -65,6 +65,35 @@ def test_batch_equals_members_and_oracle(members):
     assert rel(again, singles[0]) < 1e-14
 
 
+def test_batch_rotation_m2l(members):
+    """A batch of plans with the rotation-factored M2L: its factors are built for the union
+    of the members' offset classes; eager and graph applies against the members' own
+    applies, and against the dense-M2L batch to the factors' accuracy."""
+    import torch
+
+    from paper_1805_06106_amd import Plan
+
+    dev = torch.device("cuda:0")
+    print(f"[gpu] batch of {len(members)} surfaces, rotation M2L", flush=True)
+    plans = [Plan.from_workload(w, n_densities=2, m2l_rotation=True) for w in members]
+    singles = np.concatenate([p.apply(torch.tensor(w.density, device=dev)).cpu().numpy()
+                              for p, w in zip(plans, members)], axis=1)
+    dens = torch.tensor(np.concatenate([w.density for w in members], axis=1), device=dev)
+    dense = Plan.batch([Plan.from_workload(w, n_densities=2) for w in members])
+    ref = dense.apply(dens).cpu().numpy()
+    for graph in (False, True):
+        B = Plan.batch(plans, graph=graph)
+        for _ in range(2):
+            pot = B.apply(dens).cpu().numpy()
+            assert rel(pot, singles) < 1e-13, graph
+            assert rel(pot, ref) < 1e-11, graph
+            dens.mul_(1.0)  # eager work between replays
+        B.close()
+    dense.close()
+    for p in plans:
+        p.close()
+
+
 def test_graph_apply_replays_and_recaptures(members):
     import torch
 
