@@ -285,14 +285,15 @@ def test_batch_and_graph_validation(gq):
 
 def test_default_translation_tile_widths(gq):
     """Without autotuning: 32-pair M2L tiles in every precision mode (the split kernel keeps
-    FP64 accumulators in registers) and for the rotation M2L; XCD-aware tile order."""
+    FP64 accumulators in registers); 64-pair tiles for the rotation M2L (four waves of 16
+    pairs); XCD-aware tile order."""
     w = workload_tiny(level=1, order=2, kernel="D", p_qbx=3, p_fmm=6, nmax=32)
     G = gq
     for prec, cols in (("fp64", 32), ("fp32", 32), ("fp32_split", 32), ("fp32_lead", 32)):
         st = G.Plan(**_args(w, precision=prec)).stats()
         assert (st["m2l_tile_cols"], st["m2l_xcd_order"]) == (cols, True), prec
     st = G.Plan(**_args(w, m2l_rotation=True)).stats()
-    assert st["m2l_tile_cols"] == 32
+    assert st["m2l_tile_cols"] == 64
 
 
 def test_overlap_setting_validation(gq):
