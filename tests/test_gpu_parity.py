@@ -216,13 +216,15 @@ def test_gpu_level_restricted_vs_tier_b(dev, case):
 
 
 @pytest.mark.parametrize("case", ["S-l1-n32", "D-l2-flat"])
-@pytest.mark.parametrize("p_fmm", [3, 5, 10, 15])
+@pytest.mark.parametrize("p_fmm", [2, 3, 5, 10, 15])
 def test_gpu_m2l_rotation_vs_tier_b(dev, case, p_fmm):
     """M2L by rotation (T = B Z A on the matrix cores) against the oracle, whose M2L is the
     plain translation formula, and against the dense-matrix M2L of the library.  The kernel
-    is compiled per order: p_fmm 3 fits one row tile, 5 and 10 end in a ragged one, 15
-    fills 16."""
+    is compiled per order: p_fmm 2 and 3 fit one row tile (9 and 16 rows), 5 and 10 end in
+    a ragged one, 15 fills 16."""
     kw = dict(CASES[case])
+    if p_fmm < kw["p_qbx"]:
+        pytest.skip("p_fmm below the case's p_qbx")
     kw["p_fmm"] = p_fmm
     w = workload_tiny(**kw)
     print(f"[gpu] case={case} p_fmm={p_fmm} m2l rotation", flush=True)
