@@ -40,7 +40,7 @@ constexpr int kRotXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 // transposed product.  So a wave keeps its 16 pairs' (p+1)^2 x 16 working matrix in
 // registers, 4 doubles per lane per row tile, and runs the products by A and B there:
 //   stage 0  x = X          rows 16 t + l/16 + 4 r of pair l % 16, straight from HBM
-//   stage 1  y = A x        A block diagonal by degree: each row tile needs <= 3 tiles of x
+//   stage 1  y = A x        A block diagonal by degree: each row tile needs <= 5 tiles of x
 //   stage 2  y = Z y        through LDS: y is written out grouped by (order, re/im), each
 //                           order block multiplied with its rows read as operands, and read
 //                           back; in NH passes over groups of blocks to bound the LDS
@@ -55,6 +55,7 @@ constexpr int kRotXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 // odd b: (m, real), even b > 0: (m, imaginary)), b_len = P + 1 - m rows.
 template <int P, int NH>
 struct RotW {
+  static_assert(NH == 1 || NH == 2, "one or two LDS groups");
   static constexpr int NP = (P + 1) * (P + 1);
   static constexpr int NTR = (NP + 15) / 16;
   static constexpr int NBLK = 2 * P + 1;
