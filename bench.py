@@ -32,7 +32,7 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # sources (sha256 over csrc/kernels*.hip in name order) and tree options they were measured
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
-    "kernels_sha256": "ebdb065d5f194456ae70fa4215ea42cd5f9fbbfdb79105ceab7785f64271ef7f",
+    "kernels_sha256": "9dcc72e4476c9b470801527bc0ac54b7b336be3e1ac37f59c32d8a2d910fab11",
     "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True, "nmax": 192,
     "precision": "fp64", "m2l_rotation": True,
     "bytes_per_launch": {"p2qbxl": 6.59750e+09, "m2l": 2.246058e+10, "m2qbxl": 1.653e+07,

@@ -571,6 +571,7 @@ gq_status build_work(gq_plan* P) {
 // of Z.
 gq_status upload_rotation(gq_plan* P, hipStream_t s) {
   const int p = P->prm.p_fmm, np = P->np;
+  if (p > 15) return fail(GQ_EUNSUPPORTED, "M2L by rotation needs p_fmm <= 15");
   const int ntr = (np + 15) / 16;
   // tile positions of a matrix that is block diagonal by degree
   std::vector<int> row_beg(ntr + 1, 0), tile_c;

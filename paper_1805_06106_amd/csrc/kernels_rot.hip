@@ -56,6 +56,7 @@ constexpr int kRotXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 template <int P, int NH>
 struct RotW {
   static_assert(NH == 1 || NH == 2, "one or two LDS groups");
+  static_assert(P <= 15, "an order block of Z spans more than one 16-row tile beyond p = 15");
   static constexpr int NP = (P + 1) * (P + 1);
   static constexpr int NTR = (NP + 15) / 16;
   static constexpr int NBLK = 2 * P + 1;
