@@ -3,8 +3,9 @@
 
 Workload (default): the 'urchin' surface rho = 1 + 0.2 Re Y_8^4 on 20,480 curved triangles,
 28 nodes per triangle (573,440 sources), two QBX centers per node (1,146,880 centers, one
-target each), double-layer potential, p_qbx = 5, p_fmm = 15, nmax = 192, t_f = 0.9, FP64;
-level-restricted tree, Remark 4 at 64 sources (both paper options, measured fastest here).
+target each), double-layer potential, p_qbx = 5, p_fmm = 15, nmax = 160, t_f = 0.9, FP64;
+level-restricted tree, Remark 4 at 128 sources (both paper options, measured fastest here),
+rotation-form M2L.
 One step = one full evaluation (Algorithm 5 Stages 2-9) of one density with the plan cached
 and all inputs resident in HBM.
 
@@ -33,10 +34,9 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 # on: reported while they match, else null.
 COUNTER_TRAFFIC = {
     "kernels_sha256": "9dcc72e4476c9b470801527bc0ac54b7b336be3e1ac37f59c32d8a2d910fab11",
-    "workload": "urchin8-20480", "wfar_direct_max": 64, "level_restrict": True, "nmax": 192,
+    "workload": "urchin8-20480", "wfar_direct_max": 128, "level_restrict": True, "nmax": 160,
     "precision": "fp64", "m2l_rotation": True,
-    "bytes_per_launch": {"p2qbxl": 6.59750e+09, "m2l": 2.246058e+10, "m2qbxl": 1.653e+07,
-                         "l2qbxl": 9.7312e+08},
+    "bytes_per_launch": {"p2qbxl": 6.38616e+09, "m2l": 2.51890e+10, "l2qbxl": 1.003443e+09},
 }
 
 
@@ -105,9 +105,10 @@ def main():
                     help="c3 only: how many of the 64 batch surfaces to evaluate")
     ap.add_argument("--nmax", type=int, default=None,
                     help="most particles (sources + centers + targets) of a box before it is "
-                         "split; default: the measured optimum, 192 for the urchin workloads "
-                         "(c2, c3, c5) and 256 for the ellipsoid (c4); the workload's own "
-                         "(512, the paper's choice) for c1")
+                         "split; default: the measured optimum, 160 for the urchin workloads "
+                         "with the rotation-form M2L (c2, c3), 192 with the dense one (and "
+                         "c5), 256 for the ellipsoid (c4); the workload's own (512, the "
+                         "paper's choice) for c1")
     ap.add_argument("--c3-modes", default="fp64,fp32_split,fp32_lead",
                     help="c3 only: precision modes of the batch plan, comma-separated (fp64 "
                          "first: its member plans are the plain FP64 ones)")
@@ -137,9 +138,10 @@ def main():
                          "known traffic")
     ap.add_argument("--wfar-direct-max", type=int, default=None,
                     help="Remark 4: List 3 far boxes with at most this many sources are "
-                         "evaluated directly (0 disables). Default: 64 for the urchin "
-                         "workloads (the measured optimum for D 5/15 on the level-restricted "
-                         "tree; 128 without it); for c1 and c4 the cost-model crossover, the "
+                         "evaluated directly (0 disables). Default: for the urchin workloads "
+                         "128 with the rotation-form M2L (c2, c3) and 64 with the dense one "
+                         "(and c5), the measured optima for D 5/15 on the level-restricted "
+                         "tree; for c1 and c4 the cost-model crossover, the "
                          "flops of one M2QBXL pair over those of one direct pair (89 at S "
                          "3/10, 335 at S 8/20)")
     ap.add_argument("--level-restrict", type=int, choices=[0, 1], default=1,
@@ -189,15 +191,22 @@ def main():
         if args.workload in orders and args.study is None:
             p, q, k = orders[args.workload]
             args.wfar_direct_max = round(CM.m2qbxl_pair(p, q) / CM.p2qbxl_pair(q, k))
+        elif args.workload in ("c2", "c3") and args.m2l_rotation != 0 and args.study is None:
+            # with the rotation-form M2L (28.6 ms per apply at 64 and nmax 192, 27.6 at 128
+            # and nmax 160, same box)
+            args.wfar_direct_max = 128
         else:
             args.wfar_direct_max = 64
     if args.nmax is None and args.study is None:
         # nmax measured on one MI355X (smaller leaves move work from the near field to M2L,
         # which the matrix cores run at a higher fraction of their peak): the urchin
-        # workloads (D, 5/15) 192 (32.3-32.5 ms per apply against 43.3 ms at the paper's
-        # 512; 33.5 at 128, 36.6 at 256, 39.1 at 384); the ellipsoid (S, 8/20) 256 (242.8 ms
-        # against 262.7 at 512 and 244.0 at 384)
-        args.nmax = {"c2": 192, "c3": 192, "c5": 192, "c4": 256}.get(args.workload)
+        # workloads (D, 5/15) with the dense M2L 192 (32.3-32.5 ms per apply against 43.3 ms
+        # at the paper's 512; 33.5 at 128, 36.6 at 256, 39.1 at 384), with the rotation-form
+        # M2L 160 (27.8 ms against 28.6 at 192 and 27.8 at 176); the ellipsoid (S, 8/20) 256
+        # (242.8 ms against 262.7 at 512 and 244.0 at 384)
+        rot = args.m2l_rotation != 0
+        args.nmax = {"c2": 160 if rot else 192, "c3": 160 if rot else 192, "c5": 192,
+                     "c4": 256}.get(args.workload)
 
     if args.study == "scaling":
         return study_scaling(args)

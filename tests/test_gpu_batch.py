@@ -235,9 +235,9 @@ def test_batch_with_point_targets(members):
 def test_c3_members_full_size_vs_tier_b():
     """Three surfaces of the 64-urchin batch at full size (surfaces 2, 0 and 14: 20 * 4^l
     triangles at l = 3, 4, 5; 28 nodes each; D, 5/15; 8 densities), merged into one batch
-    plan with split-precision translations and a HIP graph, in the benchmark's tree
-    configuration; every member against Tier B on sampled centers for the first and the last
-    density, at the 1e-8 bar."""
+    plan with split-precision translations and a HIP graph, on a level-restricted tree with
+    Remark 4 at 64 (the workloads' own nmax, 512); every member against Tier B on sampled
+    centers for the first and the last density, at the 1e-8 bar."""
     import torch
 
     from paper_1805_06106_amd import Plan

@@ -1,7 +1,7 @@
 """GPU parity at full size, in the benchmark's launch configuration.
 
 The urchin (573,440 sources, 1,146,880 centers, double layer, p_qbx = 5, p_fmm = 15,
-nmax 192, level-restricted tree, Remark 4 threshold 64, rotation-factored M2L) and the
+nmax 160, level-restricted tree, Remark 4 threshold 128, rotation-factored M2L) and the
 ellipsoid (2,293,760 sources, single layer, 8/20, dense M2L) are evaluated whole on the GPU.  The oracle checks sampled centers: Tier B evaluates the same
 GIGAQBX algorithm one center at a time (its own tree and lists), Tier A the direct QBX sum.
 Bars: 1e-8 relative to the sampled oracle values' l-inf norm against Tier B (asserted at
@@ -17,7 +17,7 @@ from workloads import workload_c2, workload_c4
 
 pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
 TOL = 1e-10
-BENCH_TREE = dict(wfar_direct_max=64, level_restrict=True, nmax=192)  # bench.py's urchin defaults
+BENCH_TREE = dict(wfar_direct_max=128, level_restrict=True, nmax=160)  # bench.py's urchin defaults
 BENCH_M2L = dict(m2l_rotation=True)  # bench.py's FP64 M2L at p_fmm <= 15
 
 
@@ -150,9 +150,10 @@ def test_ellipsoid_sampled_vs_tier_b(ellipsoid, ellipsoid_ref):
     print(f"[gpu] ellipsoid vs Tier B ({len(tids)} targets): {err_b:.3e}", flush=True)
     assert err_b < TOL
     # Remark 4 at 64 keeps W-far pairs (M2QBXL at q = 8, p = 20)
-    print(f"[gpu] ellipsoid {BENCH_TREE}", flush=True)
-    pot = _gpu(w, BENCH_TREE)[0]
-    F = OracleFMM(w, **BENCH_TREE)
+    wfar_tree = dict(wfar_direct_max=64, level_restrict=True, nmax=192)
+    print(f"[gpu] ellipsoid {wfar_tree}", flush=True)
+    pot = _gpu(w, wfar_tree)[0]
+    F = OracleFMM(w, **wfar_tree)
     cs = _clustered_centers(F, w, np.random.default_rng(42), 2, 8)
     tids2, ref2, _ = F.evaluate(centers=cs)
     assert rel(pot[tids2], ref2) < TOL
