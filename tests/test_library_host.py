@@ -374,6 +374,30 @@ def test_associate_targets_validation(gq):
     assert got.tolist() == [G.GQ_TARGET_FAR] * 3
 
 
+@pytest.mark.parametrize("p", [2, 5, 10, 15])
+def test_rotation_m2l_work_model(gq, p):
+    """The executed work of the rotation-form M2L that the benchmark's matrix-core fraction
+    uses: the nonzero 16 x 16 tiles of the factors A and B, counted from the factors the
+    library builds, and the k-steps of Z's order blocks (p + 1 - m rows each, rounded up to
+    4), each k-step 16 x 16 x 4 multiply-adds per 16 pairs."""
+    from paper_1805_06106_amd import costmodel as CM
+
+    npc = (p + 1) ** 2
+    ntr = -(-npc // 16)
+    A = np.zeros((16 * ntr, 16 * ntr))
+    A[:npc, :npc] = gq.gq_translation_matrix(3, p, 1, 2, 3)  # a generic direction
+    B = np.zeros_like(A)
+    B[:npc, :npc] = gq.gq_translation_matrix(5, p, 1, 2, 3)
+    tiles = [int(np.count_nonzero(np.abs(M.reshape(ntr, 16, ntr, 16)).sum(axis=(1, 3))))
+             for M in (A, B)]
+    assert tiles[0] == tiles[1]
+    zsteps = sum(-(-(p + 1 - m) // 4) * (1 if m == 0 else 2) for m in range(p + 1))
+    assert CM.rotation_m2l_pair(p) == (4 * sum(tiles) + zsteps) * 2 * 16 * 16 * 4 / 16
+    if p == 15:
+        assert tiles[0] == 44 and zsteps == 76  # 428 k-steps per 16 pairs
+        assert CM.rotation_m2l_pair(p) == 54784
+
+
 @pytest.mark.parametrize("p", [4, 10, 15])
 def test_m2l_rotation_factors(gq, p):
     """The rotated form of M2L: T = B Z A to rounding, A and B block diagonal by degree
